@@ -1,0 +1,134 @@
+"""The bounds of oracle.bounds are tight: just outside each one a concrete input
+gives a wrong residue (exact integers or the bit-exact float emulation), just
+inside the worst-case input (and random ones) give the right residue."""
+import numpy as np
+import pytest
+
+from oracle import bounds, emulate
+from oracle import reference as ref
+
+
+def test_t1_eq3_lower_bound_tight():
+    # k (p-1)^2 = Q: the degree-d coefficient equals Q and its digit reads 0.
+    p, t, d = 3, 8, 5
+    k = (1 << t) // (p - 1) ** 2          # 64: eq. (3) fails by equality
+    assert not bounds.eq3_lower_ok(p, k, t)
+    A = np.full((1, k), p - 1, np.uint8)
+    B = np.full((k, 1), p - 1, np.uint8)
+    assert ref.qadic_product_mod_p(A, B, p, t, d)[0, 0] != ref.modmul(A, B, p)[0, 0]
+    # one less: eq. (3) holds, worst case and random inputs are exact
+    k -= 1
+    assert bounds.eq3_lower_ok(p, k, t)
+    A = np.full((1, k), p - 1, np.uint8)
+    B = np.full((k, 1), p - 1, np.uint8)
+    assert ref.qadic_product_mod_p(A, B, p, t, d)[0, 0] == ref.modmul(A, B, p)[0, 0]
+    rng = np.random.default_rng(1)
+    A, B = rng.integers(0, p, (8, k), np.uint8), rng.integers(0, p, (k, 8), np.uint8)
+    np.testing.assert_array_equal(ref.qadic_product_mod_p(A, B, p, t, d), ref.modmul(A, B, p))
+    # the same at the next t (what the strict reading of eq. (3) picks for k = 64)
+    A = np.full((1, 64), p - 1, np.uint8)
+    B = np.full((64, 1), p - 1, np.uint8)
+    assert ref.qadic_product_mod_p(A, B, p, 9, 4)[0, 0] == ref.modmul(A, B, p)[0, 0]
+
+
+def test_t2_high_part_bound_tight():
+    # Offset regime, 24-bit mantissa, p = 2, Q = 2^13, d = 1.  The high part may reach
+    # 2^(beta-1) once N = 1025 chunks: then the accumulator leaves [M, 2M), the float
+    # spacing doubles and a chunk with odd high part rounds up.
+    p, beta, t, d = 2, 24, 13, 1
+    assert bounds.offset_ok(p, 2046, t, d, beta) and not bounds.offset_ok(p, 2050, t, d, beta)
+    assert bounds.eq3_lower_ok(p, 2050, t) and 2 * bounds.low_max(p, t, d) < (1 << t)
+    bad_a = np.array([1] * 2048 + [0, 1], np.uint8)
+    bad_b = np.array([1] * 2048 + [1, 1], np.uint8)
+    want = int(bad_a.astype(int) @ bad_b.astype(int)) % p
+    assert emulate.qadic_entry(bad_a, bad_b, p, t, d, beta, "offset") != want
+    ok_a = np.array([1] * 2044 + [0, 1], np.uint8)
+    ok_b = np.array([1] * 2044 + [1, 1], np.uint8)
+    assert emulate.qadic_entry(ok_a, ok_b, p, t, d, beta, "offset") == int(ok_a.astype(int) @ ok_b.astype(int)) % p
+    ones = np.ones(2046, np.uint8)
+    assert emulate.qadic_entry(ones, ones, p, t, d, beta, "offset") == 2046 % p
+
+
+def test_t3_low_part_rounding_bound_tight():
+    # Offset regime, one product per rounding: a product whose low part reaches Q^d/2
+    # rounds up and adds one to the extracted digit.
+    p, beta, t = 3, 53, 5
+    d, k = 4, 5
+    assert 2 * bounds.low_max(p, t, d) >= (1 << (t * d))
+    assert not bounds.offset_ok(p, k, t, d, beta)
+    a = np.full(k, p - 1, np.uint8)
+    assert emulate.qadic_entry(a, a, p, t, d, beta, "offset") != (k * (p - 1) ** 2) % p
+    d = 3
+    for k in (4, 7):
+        assert bounds.offset_ok(p, k, t, d, beta)
+        a = np.full(k, p - 1, np.uint8)
+        assert emulate.qadic_entry(a, a, p, t, d, beta, "offset") == (k * (p - 1) ** 2) % p
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        a, b = rng.integers(0, p, 7, np.uint8), rng.integers(0, p, 7, np.uint8)
+        assert emulate.qadic_entry(a, b, p, t, 3, beta, "offset") == int(a.astype(int) @ b.astype(int)) % p
+
+
+def test_t3_grouped_summation_needs_the_g_factor():
+    # If g products were summed exactly before one rounding, g * low_max must stay
+    # below Q^d/2; p=3, t=7, d=5 is fine one product at a time but not four at a time.
+    p, beta, t, d = 3, 53, 7, 5
+    k = 24
+    assert bounds.offset_ok(p, k, t, d, beta, g=1) and not bounds.offset_ok(p, k, t, d, beta, g=4)
+    a = np.full(k, p - 1, np.uint8)
+    want = (k * (p - 1) ** 2) % p
+    assert emulate.qadic_entry(a, a, p, t, d, beta, "offset", g=1) == want
+    assert emulate.qadic_entry(a, a, p, t, d, beta, "offset", g=4) != want
+
+
+def test_t4_int32_bound_tight():
+    # Centred residues of p = 251 lie in [-125, 125]; k products of 125*125 overflow
+    # int32 exactly from k = 137439 on.
+    p = 251
+    assert bounds.int32_ok(p, 137438) and not bounds.int32_ok(p, 137439)
+    assert ref.centre(np.array([125, 126, 250, 0]), p).tolist() == [125, -125, -1, 0]
+    for k, fits in ((137438, True), (137439, False)):
+        exact = k * 125 * 125
+        got = emulate.int32_dot_wrapped(np.full(k, 125), np.full(k, 125))
+        assert (got == exact) == fits
+
+
+def test_exact_regime_is_exact_for_any_order():
+    # Inside the exact regime the emulated accumulation equals S for any grouping.
+    p, beta = 7, 53
+    k = 4096
+    t = bounds.smallest_t(p, k)
+    d = 1
+    assert (t, bounds.exact_ok(p, k, t, d, beta)) == (18, True)
+    a = np.full(k, p - 1, np.uint8)
+    for g in (1, 4, 2048):
+        assert emulate.qadic_entry(a, a, p, t, d, beta, "exact", g=g) == (k * (p - 1) ** 2) % p
+
+
+@pytest.mark.parametrize("p,k", [(3, 64), (3, 16384), (7, 4096), (101, 6688)])
+def test_offset_regime_worst_case_and_random(p, k):
+    # The regimes that the large workloads use give exact residues on the worst case.
+    beta = 53
+    t = bounds.smallest_t(p, k)
+    d = max(dd for dd in range(0, 60) if bounds.qadic_regime(p, k, t, dd, beta) and dd <= k - 1)
+    a = np.full(k, p - 1, np.uint8)
+    regime = bounds.qadic_regime(p, k, t, d, beta)
+    assert emulate.qadic_entry(a, a, p, t, d, beta, regime) == (k * (p - 1) ** 2) % p
+    rng = np.random.default_rng(k)
+    for _ in range(3):
+        x, y = rng.integers(0, p, k, np.uint8), rng.integers(0, p, k, np.uint8)
+        assert emulate.qadic_entry(x, y, p, t, d, beta, regime) == int(x.astype(int) @ y.astype(int)) % p
+
+
+def test_redq_one_division_identity():
+    # REDQ reads every digit mod p from one quotient by p: floor(floor(r/p)/Q^i)
+    # equals floor(floor(r/Q^i)/p), so floor(r/Q^i) mod p = (r >> ti) - p (s >> ti).
+    rng = np.random.default_rng(2)
+    for _ in range(2000):
+        t = int(rng.integers(1, 27))
+        d = int(rng.integers(0, 52 // t))
+        p = int(rng.integers(2, 300))
+        r = int(rng.integers(0, 1 << (t * (d + 1))))
+        s = r // p
+        for i in range(d + 1):
+            assert (r >> (t * i)) - p * (s >> (t * i)) == (r >> (t * i)) % p
