@@ -1,0 +1,202 @@
+/*
+ * qmm.h -- Q-adic compressed modular matrix multiplication on AMD MI355X (gfx950).
+ *
+ * Computes C = A x B mod p for residue matrices stored as bytes, following
+ * Dumas, Fousse and Salvy, "Compressed Modular Matrix Multiplication" (2008):
+ *   - section 2: d+1 residues packed in one floating-point word in base Q = 2^t
+ *     (rows of A reversed, columns of B forward); the product of packed matrices
+ *     holds every dot product as its degree-d coefficient (procedures (1), (2));
+ *   - section 3: a packed word times a single residue, followed by the
+ *     simultaneous reduction REDQ (procedure (5));
+ *   - sections 2.4, 2.5 and 5: the bounds tying p, k, Q, d and the mantissa.
+ * Two further forms go beyond the paper: INT8 matrix cores on centred residues
+ * with int32 accumulation, and batches of independent products in one launch.
+ *
+ * Conventions for every call below.
+ *   Matrices are row-major with an explicit leading dimension (elements, >= the
+ *   row length).  Residue matrices are uint8 in [0, p-1]; results are the
+ *   canonical residue in [0, p-1].  Packed matrices hold "words": double when
+ *   plan->beta == 53, float when plan->beta == 24.
+ *   Device pointers are HIP device addresses owned by the caller; the library
+ *   never frees them.  `stream` is a hipStream_t (NULL = the null stream); every
+ *   device call only enqueues work on it and returns.
+ *   Errors are return codes; nothing is thrown.  qmm_last_error() describes the
+ *   last failure of the calling thread.  Sizes of 0 are valid and do nothing
+ *   (a product with k == 0 writes zeros).
+ */
+#ifndef QMM_H
+#define QMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QMM_OK = 0,
+    QMM_EINVAL = 1,       /* bad argument: null pointer, negative size, short leading dimension */
+    QMM_EBOUND = 2,       /* no (Q, d, block) meets the bounds, or a given plan violates them */
+    QMM_EVALUE = 3,       /* p out of range for the path (INT8 needs p <= 256) */
+    QMM_ENOSPACE = 4,     /* workspace smaller than qmm_gemm_workspace_size() */
+    QMM_EDEVICE = 5,      /* a HIP runtime call failed (message in qmm_last_error) */
+    QMM_EUNSUPPORTED = 6  /* combination not implemented (named in qmm_last_error) */
+} qmm_status;
+
+typedef enum {
+    QMM_PATH_AUTO = 0,        /* let qmm_choose_Qd pick */
+    QMM_PATH_FP64_QADIC = 1,  /* k-compressed words, FP64 matrix cores (procedure (2)) */
+    QMM_PATH_FP64_REDQ = 2,   /* n-compressed words times residues + REDQ (procedure (5)) */
+    QMM_PATH_FP32_QADIC = 3,  /* as FP64_QADIC with a 24-bit mantissa */
+    QMM_PATH_FP32_REDQ = 4,   /* as FP64_REDQ with a 24-bit mantissa */
+    QMM_PATH_INT8 = 5         /* centred residues, int8 matrix cores, int32 accumulation */
+} qmm_path;
+
+typedef enum {
+    QMM_REGIME_EXACT = 0,   /* every partial sum is an integer below 2^beta: no rounding */
+    QMM_REGIME_OFFSET = 1,  /* accumulator starts at 2^(beta-1) Q^d; each rounding floors */
+    QMM_REGIME_PAPER = 2,   /* the paper's rule only (informational, never executed) */
+    QMM_REGIME_INT = 3      /* integer accumulation (INT8 path) */
+} qmm_regime;
+
+/* Flags for qmm_choose_Qd. */
+#define QMM_BOUND_PROVEN   0u  /* default: plans whose exactness is proven (EXACT/OFFSET) */
+#define QMM_BOUND_PAPER    1u  /* the paper's rule: smallest t with k(p-1)^2 < 2^t (eq. (3)),
+                                  d = min(floor(beta/t), k) - 1 (section 5); not executable */
+#define QMM_PLAN_UNBLOCKED 2u  /* keep k in one block (the paper's unblocked product) */
+#define QMM_BOUND_G4       4u  /* assume 4 products may be summed before one rounding */
+#define QMM_BOUND_EQ4      8u  /* also impose eq. (4) as printed, Q^(d+1) < 2^beta, instead of
+                                  only its sharper sum form (section 2.5) */
+
+/* A plan: everything the kernels need to know about the packing.  Plans are
+ * plain values; qmm_choose_Qd fills one, and the product calls re-validate any
+ * plan they are handed (a plan that violates the bounds is refused, never run). */
+typedef struct {
+    uint32_t p;        /* modulus, 2 <= p */
+    uint32_t t;        /* Q = 2^t */
+    uint32_t d;        /* polynomial degree: d+1 residues per word */
+    uint32_t beta;     /* mantissa bits: 53 (FP64), 24 (FP32); 31 for INT8 (int32) */
+    int64_t  k_block;  /* k is cut into blocks of k_block (a multiple of d+1); the
+                          residue of every block is reduced, then the blocks summed */
+    uint32_t path;     /* qmm_path; never QMM_PATH_AUTO in a returned plan */
+    uint32_t regime;   /* qmm_regime */
+    uint32_t g;        /* products per rounding assumed by the offset regime (1 or 4) */
+    uint32_t tile;     /* kernel tile variant (0 = default) */
+} qmm_plan;
+
+/* Choose (Q = 2^t, d, k_block, path) for a product of shape m x k times k x n
+ * modulo p (sections 1, 2.4, 2.5, 5: the field, the sizes and the mantissa are
+ * given, and they constrain Q and d).  beta = 0 takes the path's own mantissa.
+ * Host only, synchronous.  Returns QMM_EBOUND when no plan exists for the path. */
+qmm_status qmm_choose_Qd(uint32_t p, int64_t m, int64_t n, int64_t k, uint32_t beta,
+                         qmm_path path, uint32_t flags, qmm_plan *out);
+
+/* Checks a plan against the bounds for a product with inner dimension k.
+ * QMM_OK if it may run, QMM_EBOUND otherwise.  Host only. */
+qmm_status qmm_validate_plan(const qmm_plan *plan, int64_t m, int64_t n, int64_t k);
+
+/* CompressRows (procedure (2); section 2.1 reversed word, section 2.3 padding):
+ * CA[i][l] = sum_{s=0..d} A[i][l(d+1)+s] * Q^(d-s), residues past k read as 0.
+ * A: m x k bytes (lda >= k).  CA: m x ceil(k/(d+1)) words (ldca >= that). */
+qmm_status qmm_pack_rows_rev(const qmm_plan *plan, int64_t m, int64_t k,
+                             const uint8_t *A, int64_t lda, void *CA, int64_t ldca,
+                             void *stream);
+
+/* CompressColumns (procedure (2); section 2.1 forward word):
+ * CB[l][j] = sum_{s=0..d} B[l(d+1)+s][j] * Q^s.
+ * B: k x n bytes (ldb >= n).  CB: ceil(k/(d+1)) x n words (ldcb >= n). */
+qmm_status qmm_pack_cols_fwd(const qmm_plan *plan, int64_t k, int64_t n,
+                             const uint8_t *B, int64_t ldb, void *CB, int64_t ldcb,
+                             void *stream);
+
+/* Row compression of the right operand (section 3):
+ * CBr[i][J] = sum_{j=0..d} B[i][J(d+1)+j] * Q^j, columns past n read as 0.
+ * B: k x n bytes.  CBr: k x ceil(n/(d+1)) words (ldcbr >= that). */
+qmm_status qmm_pack_rows_fwd(const qmm_plan *plan, int64_t k, int64_t n,
+                             const uint8_t *B, int64_t ldb, void *CBr, int64_t ldcbr,
+                             void *stream);
+
+/* Uncompress (procedure (5)): the inverse of one of the three packings.
+ * which: 0 = rows reversed (out is rows x cols = m x k), 1 = columns forward
+ * (out is k x n), 2 = rows forward (out is k x n).  Each residue is digit
+ * (position) of its word, i.e. floor(w / Q^j) mod Q, stored as a byte; words must
+ * come from the matching pack call (digits below 256). */
+qmm_status qmm_unpack(const qmm_plan *plan, int which, int64_t rows, int64_t cols,
+                      const void *packed, int64_t ldp, uint8_t *out, int64_t ldo,
+                      void *stream);
+
+/* REDC of Table 2 (the per-entry extraction of section 2.5): C[i][j] = digit d of
+ * the accumulated word T[i][j], reduced mod p.  EXACT regime: T holds the exact
+ * sum S and the digit is floor(S / Q^d) mod Q.  OFFSET regime: T holds
+ * 2^(beta-1) Q^d + floor(S / Q^d) Q^d and the digit is read from the low t bits of
+ * the mantissa.  T: m x n words of one k-block.  C: m x n bytes. */
+qmm_status qmm_extract(const qmm_plan *plan, int64_t m, int64_t n, const void *T, int64_t ldt,
+                       uint8_t *C, int64_t ldc, void *stream);
+
+/* REDQ + EXTRACT (section 3, Table 2): every word r = sum_{j<=d} c_j Q^j of CC
+ * (m x ceil(n/(d+1)), EXACT regime) yields its d+1 residues c_j mod p, written to
+ * C[i][J(d+1)+j] for J(d+1)+j < n.  One division by p per word. */
+qmm_status qmm_redq(const qmm_plan *plan, int64_t m, int64_t n, const void *CC, int64_t ldcc,
+                    uint8_t *C, int64_t ldc, void *stream);
+
+/* Device workspace that qmm_gemm_mod_p needs for this plan and shape. */
+qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                                   size_t *bytes);
+
+/* C = A x B mod p from bytes to bytes (procedure (2) for the QADIC paths,
+ * procedure (5) for the REDQ paths, INT8 matrix cores for the INT8 path).
+ * plan == NULL: qmm_choose_Qd(p, m, n, k, 0, QMM_PATH_AUTO, 0) is used.
+ * A: m x k, B: k x n, C: m x n bytes (C must not overlap A or B).
+ * ws: device workspace of ws_bytes >= qmm_gemm_workspace_size (may be NULL when
+ * that size is 0); it holds the packed operands between the kernels. */
+qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, uint32_t p,
+                          const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
+                          uint8_t *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
+
+/* Procedure (1) on already compressed operands: C = digit d of CA x CB, mod p.
+ * CA: m x ceil(k/(d+1)) words from qmm_pack_rows_rev; CB: ceil(k/(d+1)) x n words
+ * from qmm_pack_cols_fwd, both with this plan.  QADIC paths only. */
+qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                           const void *CA, int64_t ldca, const void *CB, int64_t ldcb,
+                           uint8_t *C, int64_t ldc, void *stream);
+
+/* ---- batches of independent products --------------------------------------- */
+typedef struct {
+    int64_t m, n, k;
+    uint32_t p;
+    const uint8_t *A; int64_t lda;   /* device, m x k */
+    const uint8_t *B; int64_t ldb;   /* device, k x n */
+    uint8_t *C; int64_t ldc;         /* device, m x n */
+} qmm_problem;
+
+typedef struct qmm_batched qmm_batched;
+
+/* Plans every product (path and tile per product), builds the device-side
+ * descriptor table and tile list, and records one launch of the persistent kernel
+ * in a HIP graph.  probs is a host array; the device buffers it names must stay
+ * valid until qmm_batched_destroy.  The batch owns the device memory it allocates.
+ * flags: 0, or QMM_BATCH_FORCE_FP64 (every product on the FP64 Q-adic tile path). */
+#define QMM_BATCH_FORCE_FP64 1u
+qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t flags,
+                              qmm_batched **out);
+
+/* Replays the recorded launch on `stream`: every product of the batch. */
+qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream);
+
+/* Plan chosen for product i of the batch (host copy). */
+qmm_status qmm_batched_plan(const qmm_batched *batch, int64_t i, qmm_plan *out);
+
+/* Frees the batch's device memory and graph.  NULL is accepted. */
+qmm_status qmm_batched_destroy(qmm_batched *batch);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char *qmm_last_error(void);
+
+/* Library version, "major.minor.patch". */
+const char *qmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QMM_H */

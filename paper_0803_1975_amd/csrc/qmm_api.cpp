@@ -1,0 +1,190 @@
+// The C ABI: argument checking, plan selection and validation, workspace
+// layout, and the sequence of kernels for each procedure.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "qmm_internal.h"
+
+using namespace qmm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+qmm_status check_plan_for_words(const qmm_plan *pl) {
+    if (!pl) return fail(QMM_EINVAL, "plan is NULL");
+    if (pl->p < 2) return fail(QMM_EINVAL, "plan p must be >= 2");
+    if (pl->beta != 53 && pl->beta != 24) return fail(QMM_EINVAL, "packed words need beta 53 (double) or 24 (float)");
+    if (!words_exact(*pl))
+        return fail(QMM_EINVAL, "packed words (p-1)(1 + Q + ... + Q^d) must be exact floats of the plan's mantissa");
+    return QMM_OK;
+}
+
+bool bad_matrix(int64_t rows, int64_t cols, const void *ptr, int64_t ld) {
+    if (rows < 0 || cols < 0) return true;
+    if (rows == 0 || cols == 0) return false;
+    return ptr == nullptr || ld < cols;
+}
+
+struct Layout {
+    size_t bytes = 0;
+    size_t off_b = 0;  // second buffer offset
+    int64_t ld_a = 0, ld_b = 0;
+};
+
+Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
+    Layout L;
+    const int64_t kk = k < 1 ? 1 : k;
+    if (path_is_qadic(pl.path)) {
+        const int64_t nw = words_for(kk, pl.d);
+        const size_t wb = (size_t)word_bytes(pl);
+        L.ld_a = nw;
+        L.ld_b = n;
+        L.off_b = align_up((size_t)m * nw * wb);
+        L.bytes = L.off_b + align_up((size_t)nw * n * wb);
+    } else if (path_is_redq(pl.path)) {
+        const int64_t nw = words_for(n, pl.d);
+        L.ld_b = nw;
+        L.bytes = align_up((size_t)kk * nw * word_bytes(pl));
+    } else if (pl.path == QMM_PATH_INT8) {
+        L.ld_b = int8_bt_ld(kk);
+        L.bytes = align_up((size_t)n * L.ld_b);
+    }
+    return L;
+}
+
+qmm_status resolve_plan(const qmm_plan *plan, uint32_t p, int64_t m, int64_t n, int64_t k, qmm_plan *out) {
+    if (plan) {
+        if (plan->p != p) return fail(QMM_EINVAL, "plan->p differs from p");
+        const qmm_status st = qmm_validate_plan(plan, m, n, k);
+        if (st != QMM_OK) return st;
+        *out = *plan;
+        return QMM_OK;
+    }
+    return qmm_choose_Qd(p, m, n, k, 0, QMM_PATH_AUTO, 0, out);
+}
+
+}  // namespace
+
+extern "C" qmm_status qmm_pack_rows_rev(const qmm_plan *plan, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
+                                        void *CA, int64_t ldca, void *stream) {
+    qmm_status st = check_plan_for_words(plan);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(m, k, A, lda)) return fail(QMM_EINVAL, "A: bad size, pointer or lda");
+    if (bad_matrix(m, words_for(k, plan->d), CA, ldca)) return fail(QMM_EINVAL, "CA: bad pointer or ldca");
+    return launch_pack_rows_rev(*plan, m, k, A, lda, CA, ldca, stream);
+}
+
+extern "C" qmm_status qmm_pack_cols_fwd(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                        void *CB, int64_t ldcb, void *stream) {
+    qmm_status st = check_plan_for_words(plan);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad size, pointer or ldb");
+    if (bad_matrix(words_for(k, plan->d), n, CB, ldcb)) return fail(QMM_EINVAL, "CB: bad pointer or ldcb");
+    return launch_pack_cols_fwd(*plan, k, n, B, ldb, CB, ldcb, stream);
+}
+
+extern "C" qmm_status qmm_pack_rows_fwd(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                        void *CBr, int64_t ldcbr, void *stream) {
+    qmm_status st = check_plan_for_words(plan);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad size, pointer or ldb");
+    if (bad_matrix(k, words_for(n, plan->d), CBr, ldcbr)) return fail(QMM_EINVAL, "CBr: bad pointer or ldcbr");
+    return launch_pack_rows_fwd(*plan, k, n, B, ldb, CBr, ldcbr, stream);
+}
+
+extern "C" qmm_status qmm_unpack(const qmm_plan *plan, int which, int64_t rows, int64_t cols, const void *packed,
+                                 int64_t ldp, uint8_t *out, int64_t ldo, void *stream) {
+    qmm_status st = check_plan_for_words(plan);
+    if (st != QMM_OK) return st;
+    if (which < 0 || which > 2) return fail(QMM_EINVAL, "which must be 0, 1 or 2");
+    if (bad_matrix(rows, cols, out, ldo)) return fail(QMM_EINVAL, "out: bad size, pointer or ldo");
+    const int64_t prow = which == 1 ? words_for(rows, plan->d) : rows;
+    const int64_t pcol = which == 1 ? cols : words_for(cols, plan->d);
+    if (bad_matrix(prow, pcol, packed, ldp)) return fail(QMM_EINVAL, "packed: bad pointer or ldp");
+    return launch_unpack(*plan, which, rows, cols, packed, ldp, out, ldo, stream);
+}
+
+extern "C" qmm_status qmm_extract(const qmm_plan *plan, int64_t m, int64_t n, const void *T, int64_t ldt,
+                                  uint8_t *C, int64_t ldc, void *stream) {
+    qmm_status st = check_plan_for_words(plan);
+    if (st != QMM_OK) return st;
+    if (plan->regime != QMM_REGIME_EXACT && plan->regime != QMM_REGIME_OFFSET)
+        return fail(QMM_EINVAL, "extract needs an EXACT or OFFSET plan");
+    if (plan->regime == QMM_REGIME_OFFSET && plan->t > 32)
+        return fail(QMM_EINVAL, "offset extraction needs t <= 32");
+    if (bad_matrix(m, n, T, ldt) || bad_matrix(m, n, C, ldc)) return fail(QMM_EINVAL, "bad size, pointer or ld");
+    return launch_extract(*plan, m, n, T, ldt, C, ldc, stream);
+}
+
+extern "C" qmm_status qmm_redq(const qmm_plan *plan, int64_t m, int64_t n, const void *CC, int64_t ldcc, uint8_t *C,
+                               int64_t ldc, void *stream) {
+    qmm_status st = check_plan_for_words(plan);
+    if (st != QMM_OK) return st;
+    if ((uint64_t)plan->t * (plan->d + 1) > 52) return fail(QMM_EINVAL, "REDQ words need t (d+1) <= 52");
+    if (bad_matrix(m, words_for(n, plan->d), CC, ldcc) || bad_matrix(m, n, C, ldc))
+        return fail(QMM_EINVAL, "bad size, pointer or ld");
+    return launch_redq(*plan, m, n, CC, ldcc, C, ldc, stream);
+}
+
+extern "C" qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, size_t *bytes) {
+    if (!bytes) return fail(QMM_EINVAL, "bytes is NULL");
+    if (!plan) return fail(QMM_EINVAL, "plan is NULL (choose one with qmm_choose_Qd first)");
+    if (m < 0 || n < 0 || k < 0) return fail(QMM_EINVAL, "negative size");
+    *bytes = workspace_layout(*plan, m, n, k).bytes;
+    return QMM_OK;
+}
+
+extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, uint32_t p,
+                                     const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *C,
+                                     int64_t ldc, void *ws, size_t ws_bytes, void *stream) {
+    if (p < 2 || p > 256) return fail(QMM_EINVAL, "byte residues need 2 <= p <= 256");
+    if (m < 0 || n < 0 || k < 0) return fail(QMM_EINVAL, "negative size");
+    if (bad_matrix(m, k, A, lda)) return fail(QMM_EINVAL, "A: bad pointer or lda");
+    if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad pointer or ldb");
+    if (bad_matrix(m, n, C, ldc)) return fail(QMM_EINVAL, "C: bad pointer or ldc");
+    qmm_plan pl;
+    qmm_status st = resolve_plan(plan, p, m, n, k, &pl);
+    if (st != QMM_OK) return st;
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
+    const Layout L = workspace_layout(pl, m, n, k);
+    if (L.bytes > 0 && (ws == nullptr || ws_bytes < L.bytes))
+        return fail(QMM_ENOSPACE, "workspace needs " + std::to_string(L.bytes) + " bytes");
+    uint8_t *w = (uint8_t *)ws;
+    if (path_is_qadic(pl.path)) {
+        void *CA = w, *CB = w + L.off_b;
+        if ((st = launch_pack_rows_rev(pl, m, k, A, lda, CA, L.ld_a, stream)) != QMM_OK) return st;
+        if ((st = launch_pack_cols_fwd(pl, k, n, B, ldb, CB, L.ld_b, stream)) != QMM_OK) return st;
+        return launch_gemm_qadic(pl, m, n, k, CA, L.ld_a, CB, L.ld_b, C, ldc, stream);
+    }
+    if (path_is_redq(pl.path)) {
+        if ((st = launch_pack_rows_fwd(pl, k, n, B, ldb, w, L.ld_b, stream)) != QMM_OK) return st;
+        return launch_gemm_redq(pl, m, n, k, A, lda, w, L.ld_b, C, ldc, stream);
+    }
+    if (pl.path == QMM_PATH_INT8) {
+        int8_t *Bt = (int8_t *)w;
+        if ((st = launch_centre_transpose(pl, k, n, B, ldb, Bt, L.ld_b, stream)) != QMM_OK) return st;
+        return launch_gemm_int8(pl, m, n, k, A, lda, Bt, L.ld_b, C, ldc, stream);
+    }
+    return fail(QMM_EINVAL, "unknown path");
+}
+
+extern "C" qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const void *CA,
+                                      int64_t ldca, const void *CB, int64_t ldcb, uint8_t *C, int64_t ldc,
+                                      void *stream) {
+    if (!plan) return fail(QMM_EINVAL, "plan is NULL");
+    if (!path_is_qadic(plan->path)) return fail(QMM_EINVAL, "qmm_gemm_packed takes a QADIC plan");
+    qmm_status st = qmm_validate_plan(plan, m, n, k);
+    if (st != QMM_OK) return st;
+    if (m < 0 || n < 0 || k < 0) return fail(QMM_EINVAL, "negative size");
+    const int64_t nw = words_for(k < 1 ? 1 : k, plan->d);
+    if (bad_matrix(m, nw, CA, ldca) || bad_matrix(nw, n, CB, ldcb) || bad_matrix(m, n, C, ldc))
+        return fail(QMM_EINVAL, "bad pointer or leading dimension");
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
+    return launch_gemm_qadic(*plan, m, n, k, CA, ldca, CB, ldcb, C, ldc, stream);
+}

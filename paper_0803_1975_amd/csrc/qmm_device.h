@@ -1,0 +1,70 @@
+// Device-side helpers shared by the kernels: reductions mod p and word access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qmm {
+
+// x mod p for 0 <= x < 2^53, with invp = RN(1/p).  The float quotient is within
+// one of floor(x/p) (relative error of x * invp below 2^-51 and x/p < 2^52), so a
+// single correction in each direction gives the exact remainder.
+__device__ __forceinline__ uint32_t mod_u64(uint64_t x, uint32_t p, double invp) {
+    const uint64_t q = (uint64_t)((double)x * invp);
+    int64_t r = (int64_t)x - (int64_t)(q * (uint64_t)p);
+    if (r < 0) r += p;
+    if (r >= (int64_t)p) r -= p;
+    return (uint32_t)r;
+}
+
+// floor(x / p) for 0 <= x < 2^53 (same error argument as mod_u64).
+__device__ __forceinline__ uint64_t div_u64(uint64_t x, uint32_t p, double invp) {
+    uint64_t q = (uint64_t)((double)x * invp);
+    const int64_t r = (int64_t)x - (int64_t)(q * (uint64_t)p);
+    if (r < 0) q -= 1;
+    else if (r >= (int64_t)p) q += 1;
+    return q;
+}
+
+// x mod p in [0, p) for a signed 32-bit x.
+__device__ __forceinline__ uint32_t mod_i32(int32_t x, uint32_t p, double invp) {
+    const double q = floor((double)x * invp);
+    int64_t r = (int64_t)x - (int64_t)q * (int64_t)p;
+    if (r < 0) r += p;
+    if (r >= (int64_t)p) r -= p;
+    return (uint32_t)r;
+}
+
+// Word <-> integer conversions.  Packed words are non-negative integers that the
+// plan's bounds keep exactly representable.
+template <typename W> __device__ __forceinline__ W word_from_u64(uint64_t v);
+template <> __device__ __forceinline__ double word_from_u64<double>(uint64_t v) { return (double)v; }
+template <> __device__ __forceinline__ float word_from_u64<float>(uint64_t v) { return (float)v; }
+
+__device__ __forceinline__ uint64_t u64_from_word(double w) { return (uint64_t)w; }
+__device__ __forceinline__ uint64_t u64_from_word(float w) { return (uint64_t)w; }
+
+// Low 32 bits of the encoding: in the OFFSET regime they are the low bits of
+// floor(S / Q^d), i.e. digit d in the low t bits.
+__device__ __forceinline__ uint32_t low_mantissa_bits(double w) {
+    return (uint32_t)__double_as_longlong(w);
+}
+__device__ __forceinline__ uint32_t low_mantissa_bits(float w) { return __float_as_uint(w); }
+
+// Digit d of an accumulated word, for either regime.
+template <typename W>
+__device__ __forceinline__ uint32_t qadic_digit(W acc, bool offset, uint32_t td, uint64_t qmask) {
+    if (offset) return low_mantissa_bits(acc) & (uint32_t)qmask;
+    return (uint32_t)((u64_from_word(acc) >> td) & qmask);
+}
+
+// The accumulator start value of the OFFSET regime: 2^(beta-1) Q^d.
+template <typename W> struct WordTraits;
+template <> struct WordTraits<double> {
+    static constexpr int beta = 53;
+};
+template <> struct WordTraits<float> {
+    static constexpr int beta = 24;
+};
+
+}  // namespace qmm

@@ -1,0 +1,247 @@
+// INT8 path: centred residues on the int8 matrix cores with int32 accumulation.
+//
+// A residue x in [0, p-1] is replaced by x - p when x > (p-1)/2, so |x| <= p/2
+// fits a signed byte for p <= 256 and k products of two centred residues stay in
+// int32 while k (p/2)^2 < 2^31 (longer k is cut into blocks reduced mod p).
+//
+//   centre_transpose  B (k x n bytes) -> Bt (n x ldbt int8, k contiguous, zero
+//                     padded to a multiple of 64): the int8 MFMA wants both
+//                     operands contiguous along k.  HBM-bound, 64 x 64 tiles
+//                     through LDS so reads and writes are both row-contiguous.
+//   gemm_int8         C = (A_centred x Bt^T) mod p.  A is centred in registers on
+//                     its way into LDS, four residues per 32-bit word.  128 x 128
+//                     tile per 256-thread workgroup, 2 x 2 wavefronts of 64 x 64,
+//                     MFMA i32_16x16x64_i8, K stage of 64 bytes, double-buffered.
+#include <hip/hip_runtime.h>
+
+#include "qmm_device.h"
+#include "qmm_internal.h"
+
+namespace qmm {
+namespace {
+
+typedef int ix4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, KT = kInt8KT, NT = 256, PITCH = KT + 16;
+static_assert(KT == 64, "the staging map below assumes 64-byte K stages");
+
+// Centre four packed residues: x -> x - p where x > h = (p-1)/2.  With x <= p-1
+// every byte of w + (127-h) stays below 256, so its top bit is exactly [x > h];
+// adding (256-p) to the flagged bytes is x - p mod 256 (the int8 encoding) and
+// cannot carry since x + 256 - p <= 255.
+__device__ __forceinline__ uint32_t centre4(uint32_t w, uint32_t add_h, uint32_t neg_p) {
+    const uint32_t flag = ((w + add_h) >> 7) & 0x01010101u;
+    return w + flag * neg_p;
+}
+
+__global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
+                                                                int64_t ldb, int8_t *__restrict__ Bt, int64_t ldbt,
+                                                                uint32_t add_h, uint32_t neg_p) {
+    __shared__ uint8_t tile[64][65];
+    const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t kk = k0 + r, nn = n0 + tx;
+        tile[r][tx] = (kk < k && nn < n) ? B[kk * ldb + nn] : 0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t nn = n0 + r, kk = k0 + tx;
+        if (nn < n && kk < ldbt) {
+            const uint32_t c = centre4((uint32_t)tile[tx][r], add_h, neg_p) & 0xffu;
+            Bt[nn * ldbt + kk] = (int8_t)(kk < k ? c : 0);
+        }
+    }
+}
+
+__device__ __forceinline__ void tile_coords(int64_t m, int64_t n, int &tm, int &tn) {
+    const int tiles_m = (int)ceil_div(m, BM), tiles_n = (int)ceil_div(n, BN);
+    const int nb = gridDim.x;
+    int bid = blockIdx.x;
+    if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+    constexpr int GROUP = 8;
+    const int per_group = GROUP * tiles_n;
+    const int group = bid / per_group;
+    const int first_m = group * GROUP;
+    const int gsize = min(tiles_m - first_m, GROUP);
+    const int local = bid - group * per_group;
+    tm = first_m + local % gsize;
+    tn = local / gsize;
+}
+
+struct Int8Args {
+    int64_t m, n, k;
+    const uint8_t *A;
+    int64_t lda;
+    const int8_t *Bt;
+    int64_t ldbt;
+    uint8_t *C;
+    int64_t ldc;
+    int32_t kb_tiles;  // K stages per block (0 = unblocked)
+    uint32_t p, add_h, neg_p;
+    double invp;
+    bool a_vec;        // A rows 16-byte aligned: vector loads allowed
+};
+
+template <bool BLOCKED>
+__global__ __launch_bounds__(NT, 2) void gemm_int8_kernel(Int8Args g) {
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][BM * PITCH];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[2][BN * PITCH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_coords(g.m, g.n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+
+    ix4 acc[4][4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = ix4{0, 0, 0, 0};
+
+    // Staging: two 16-byte segments of A and two of Bt per thread and stage.
+    // Segment c = tid + 256 i: row c >> 2, bytes 16 (c & 3) .. +15 of the stage.
+    uint4 ra[2], rb[2];
+    auto load_stage = [&](int kt) {
+        const int64_t k0 = (int64_t)kt * KT;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int c = tid + NT * i;
+            const int r = c >> 2, seg = c & 3;
+            const int64_t kk = k0 + seg * 16;
+            const int64_t arow = row0 + r;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (arow < g.m) {
+                const uint8_t *src = g.A + arow * g.lda + kk;
+                if (g.a_vec && kk + 16 <= g.k) {
+                    v = *(const uint4 *)src;
+                } else {
+                    uint32_t w[4] = {0, 0, 0, 0};
+                    for (int b = 0; b < 16; ++b)
+                        if (kk + b < g.k) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+                    v = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+            v.x = centre4(v.x, g.add_h, g.neg_p);
+            v.y = centre4(v.y, g.add_h, g.neg_p);
+            v.z = centre4(v.z, g.add_h, g.neg_p);
+            v.w = centre4(v.w, g.add_h, g.neg_p);
+            ra[i] = v;
+            const int64_t brow = col0 + r;
+            // Bt rows are zero-padded to ldbt (a multiple of 64), so whole stages are in bounds.
+            rb[i] = (brow < g.n) ? *(const uint4 *)(g.Bt + brow * g.ldbt + kk) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int c = tid + NT * i;
+            const int r = c >> 2, seg = c & 3;
+            *(uint4 *)&sA[buf][r * PITCH + seg * 16] = ra[i];
+            *(uint4 *)&sB[buf][r * PITCH + seg * 16] = rb[i];
+        }
+    };
+
+    const int ntiles = (int)ceil_div(g.k, KT);
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+    for (int kt = 0; kt < ntiles; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < ntiles) load_stage(kt + 1);
+        ix4 af[4], bf[4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+            af[mi] = *(const ix4 *)&sA[buf][(wm * 64 + mi * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+            bf[ni] = *(const ix4 *)&sB[buf][(wn * 64 + ni * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                acc[mi][ni] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+        if constexpr (BLOCKED) {
+            if ((kt + 1) % g.kb_tiles == 0 && kt + 1 < ntiles) {
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[mi][ni][r] = (int)mod_i32(acc[mi][ni][r], g.p, g.invp);
+            }
+        }
+        if (kt + 1 < ntiles) {
+            store_stage(buf ^ 1);
+            __syncthreads();
+        }
+    }
+
+    // lane l, register r holds D[4 (l >> 4) + r][l & 15]
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + wm * 64 + mi * 16 + 4 * (lane >> 4) + r;
+                const int64_t col = col0 + wn * 64 + ni * 16 + (lane & 15);
+                if (row < g.m && col < g.n) g.C[row * g.ldc + col] = (uint8_t)mod_i32(acc[mi][ni][r], g.p, g.invp);
+            }
+}
+
+qmm_status check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(QMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return QMM_OK;
+}
+
+void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
+    const uint32_t h = (p - 1) / 2;
+    add_h = (127u - h) * 0x01010101u;
+    neg_p = (256u - p) & 0xffu;
+}
+
+}  // namespace
+
+int64_t int8_bt_ld(int64_t k) { return ceil_div(k < 1 ? 1 : k, KT) * KT; }
+
+qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                   int8_t *Bt, int64_t ldbt, void *stream) {
+    if (n == 0) return QMM_OK;
+    uint32_t add_h, neg_p;
+    centre_consts(pl.p, add_h, neg_p);
+    const dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(ldbt, 64));
+    centre_transpose_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt, ldbt, add_h, neg_p);
+    return check_launch("centre_transpose");
+}
+
+qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
+                            const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream) {
+    if (m == 0 || n == 0) return QMM_OK;
+    Int8Args g{};
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.A = A;
+    g.lda = lda;
+    g.Bt = Bt;
+    g.ldbt = ldbt;
+    g.C = C;
+    g.ldc = ldc;
+    const bool blocked = pl.k_block < k;
+    g.kb_tiles = blocked ? (int32_t)(pl.k_block / KT) : 0;
+    g.p = pl.p;
+    centre_consts(pl.p, g.add_h, g.neg_p);
+    g.invp = 1.0 / (double)pl.p;
+    g.a_vec = ((uintptr_t)A % 16 == 0) && (lda % 16 == 0);
+    const dim3 grid((unsigned)(ceil_div(m, BM) * ceil_div(n, BN)));
+    hipStream_t s = (hipStream_t)stream;
+    if (blocked)
+        gemm_int8_kernel<true><<<grid, NT, 0, s>>>(g);
+    else
+        gemm_int8_kernel<false><<<grid, NT, 0, s>>>(g);
+    return check_launch("gemm_int8");
+}
+
+}  // namespace qmm

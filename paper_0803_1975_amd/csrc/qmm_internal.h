@@ -1,0 +1,77 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "qmm.h"
+
+namespace qmm {
+
+// K-tile of the Q-adic GEMM kernels, in packed words.  A k-block always spans a
+// whole number of K-tiles of words, so block boundaries fall between tiles.
+constexpr int kQadicKT = 16;
+// K-tile of the INT8 kernel, in bytes.  Blocks of the INT8 path are multiples of it.
+constexpr int kInt8KT = 64;
+// Cost of one block boundary (extraction + reduction of every output) in units of
+// one packed word of MFMA work per output; used to rank blocked plans.
+constexpr int kBlockCostWords = 8;
+
+void set_error(const std::string &msg);
+qmm_status fail(qmm_status st, const std::string &msg);
+
+#if defined(__HIP__)
+#define QMM_HD __host__ __device__
+#else
+#define QMM_HD
+#endif
+
+QMM_HD inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Packed words along one packed dimension of size len.
+QMM_HD inline int64_t words_for(int64_t len, uint32_t d) { return ceil_div(len, (int64_t)d + 1); }
+
+bool path_is_fp64(uint32_t path);
+bool path_is_fp32(uint32_t path);
+bool path_is_qadic(uint32_t path);
+bool path_is_redq(uint32_t path);
+
+// True when every packed word (p-1)(1 + Q + ... + Q^d) is an exact float of the
+// plan's mantissa and fits the 64-bit integer the pack kernels build it in.
+bool words_exact(const qmm_plan &pl);
+
+// Word size in bytes for a plan (8 for beta 53, 4 for beta 24).
+int word_bytes(const qmm_plan &pl);
+
+// Launchers (qmm_kernels_*.hip).  All sizes already validated.
+qmm_status launch_pack_rows_rev(const qmm_plan &pl, int64_t m, int64_t k, const uint8_t *A,
+                                int64_t lda, void *CA, int64_t ldca, void *stream);
+qmm_status launch_pack_cols_fwd(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B,
+                                int64_t ldb, void *CB, int64_t ldcb, void *stream);
+qmm_status launch_pack_rows_fwd(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B,
+                                int64_t ldb, void *CBr, int64_t ldcbr, void *stream);
+qmm_status launch_unpack(const qmm_plan &pl, int which, int64_t rows, int64_t cols,
+                         const void *packed, int64_t ldp, uint8_t *out, int64_t ldo, void *stream);
+qmm_status launch_extract(const qmm_plan &pl, int64_t m, int64_t n, const void *T, int64_t ldt,
+                          uint8_t *C, int64_t ldc, void *stream);
+qmm_status launch_redq(const qmm_plan &pl, int64_t m, int64_t n, const void *CC, int64_t ldcc,
+                       uint8_t *C, int64_t ldc, void *stream);
+qmm_status launch_fill_u8(uint8_t *C, int64_t m, int64_t n, int64_t ldc, uint8_t v, void *stream);
+
+// Q-adic GEMM on packed words (procedure (1)): C = digit d of CA x CB mod p.
+qmm_status launch_gemm_qadic(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
+                             const void *CA, int64_t ldca, const void *CB, int64_t ldcb,
+                             uint8_t *C, int64_t ldc, void *stream);
+// Right-compressed GEMM + REDQ (procedure (5)): C = REDQ(A x CBr).
+qmm_status launch_gemm_redq(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
+                            const uint8_t *A, int64_t lda, const void *CBr, int64_t ldcbr,
+                            uint8_t *C, int64_t ldc, void *stream);
+// INT8: B is first centred and transposed into Bt (n x k, int8, ldbt = k rounded up).
+qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B,
+                                   int64_t ldb, int8_t *Bt, int64_t ldbt, void *stream);
+qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
+                            const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
+                            uint8_t *C, int64_t ldc, void *stream);
+int64_t int8_bt_ld(int64_t k);
+
+}  // namespace qmm

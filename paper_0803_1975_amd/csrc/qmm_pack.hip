@@ -1,0 +1,261 @@
+// Conversions between residues and packed words, and the standalone reductions.
+//
+//   pack_rows_rev   CompressRows  (section 2.1 reversed word, section 2.3 padding)
+//   pack_cols_fwd   CompressColumns (section 2.1 forward word)
+//   pack_rows_fwd   row compression of the right operand (section 3)
+//   unpack          Uncompress (procedure (5))
+//   extract         REDC of Table 2: digit d of an accumulated word, mod p (section 2.5)
+//   redq            REDQ + EXTRACT of Table 2 (section 3)
+//
+// All are HBM-bound elementwise passes: one thread per output word (or residue),
+// consecutive threads on consecutive outputs so both the byte reads and the word
+// writes of a wavefront are contiguous; grid-stride loops over 64-bit indices.
+#include <hip/hip_runtime.h>
+
+#include "qmm_device.h"
+#include "qmm_internal.h"
+
+namespace qmm {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline dim3 grid_for(int64_t total) {
+    int64_t b = ceil_div(total, kThreads);
+    if (b > (int64_t)1 << 20) b = (int64_t)1 << 20;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+// CA[i][l] = sum_s A[i][l(d+1)+s] Q^(d-s): Horner from the first residue of the chunk,
+// which ends with the top power (the paper's init3 order).
+template <typename W>
+__global__ __launch_bounds__(kThreads) void pack_rows_rev_kernel(int64_t m, int64_t k, int64_t nw,
+                                                                  const uint8_t *__restrict__ A, int64_t lda,
+                                                                  W *__restrict__ CA, int64_t ldca,
+                                                                  uint32_t t, uint32_t d) {
+    const int64_t total = m * nw;
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = idx / nw, l = idx - i * nw;
+        const uint8_t *a = A + i * lda;
+        const int64_t base = l * (d + 1);
+        uint64_t w = 0;
+        for (uint32_t s = 0; s <= d; ++s) {
+            const int64_t c = base + s;
+            w = (w << t) | (c < k ? (uint64_t)a[c] : 0ull);
+        }
+        CA[i * ldca + l] = word_from_u64<W>(w);
+    }
+}
+
+// CB[l][j] = sum_s B[l(d+1)+s][j] Q^s.
+template <typename W>
+__global__ __launch_bounds__(kThreads) void pack_cols_fwd_kernel(int64_t k, int64_t n, int64_t nw,
+                                                                  const uint8_t *__restrict__ B, int64_t ldb,
+                                                                  W *__restrict__ CB, int64_t ldcb,
+                                                                  uint32_t t, uint32_t d) {
+    const int64_t total = nw * n;
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t l = idx / n, j = idx - l * n;
+        const int64_t base = l * (d + 1);
+        uint64_t w = 0;
+        for (int32_t s = (int32_t)d; s >= 0; --s) {
+            const int64_t r = base + s;
+            w = (w << t) | (r < k ? (uint64_t)B[r * ldb + j] : 0ull);
+        }
+        CB[l * ldcb + j] = word_from_u64<W>(w);
+    }
+}
+
+// CBr[i][J] = sum_j B[i][J(d+1)+j] Q^j.
+template <typename W>
+__global__ __launch_bounds__(kThreads) void pack_rows_fwd_kernel(int64_t k, int64_t n, int64_t nw,
+                                                                  const uint8_t *__restrict__ B, int64_t ldb,
+                                                                  W *__restrict__ CBr, int64_t ldcbr,
+                                                                  uint32_t t, uint32_t d) {
+    const int64_t total = k * nw;
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = idx / nw, J = idx - i * nw;
+        const uint8_t *b = B + i * ldb;
+        const int64_t base = J * (d + 1);
+        uint64_t w = 0;
+        for (int32_t j = (int32_t)d; j >= 0; --j) {
+            const int64_t c = base + j;
+            w = (w << t) | (c < n ? (uint64_t)b[c] : 0ull);
+        }
+        CBr[i * ldcbr + J] = word_from_u64<W>(w);
+    }
+}
+
+// One thread per residue: which = 0 rows reversed, 1 columns forward, 2 rows forward.
+template <typename W>
+__global__ __launch_bounds__(kThreads) void unpack_kernel(int which, int64_t rows, int64_t cols,
+                                                           const W *__restrict__ P, int64_t ldp,
+                                                           uint8_t *__restrict__ out, int64_t ldo,
+                                                           uint32_t t, uint32_t d) {
+    const int64_t total = rows * cols;
+    const uint64_t qmask = (t >= 64) ? ~0ull : ((1ull << t) - 1);
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t r = idx / cols, c = idx - r * cols;
+        uint64_t w;
+        uint32_t pos;
+        if (which == 0) {  // residue (r, c) is digit d - s of word (r, c / (d+1))
+            w = u64_from_word(P[r * ldp + c / (d + 1)]);
+            pos = d - (uint32_t)(c % (d + 1));
+        } else if (which == 1) {  // residue (r, c) is digit s of word (r / (d+1), c)
+            w = u64_from_word(P[(r / (d + 1)) * ldp + c]);
+            pos = (uint32_t)(r % (d + 1));
+        } else {  // residue (r, c) is digit j of word (r, c / (d+1))
+            w = u64_from_word(P[r * ldp + c / (d + 1)]);
+            pos = (uint32_t)(c % (d + 1));
+        }
+        out[r * ldo + c] = (uint8_t)((w >> (t * pos)) & qmask);
+    }
+}
+
+template <typename W>
+__global__ __launch_bounds__(kThreads) void extract_kernel(int64_t m, int64_t n, const W *__restrict__ T,
+                                                            int64_t ldt, uint8_t *__restrict__ C, int64_t ldc,
+                                                            uint32_t td, uint64_t qmask, bool offset, uint32_t p,
+                                                            double invp) {
+    const int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = idx / n, j = idx - i * n;
+        const uint32_t c = qadic_digit<W>(T[i * ldt + j], offset, td, qmask);
+        C[i * ldc + j] = (uint8_t)mod_u64(c, p, invp);
+    }
+}
+
+// REDQ on r = sum_{j<=d} c_j Q^j: s = floor(r/p) once; mu_j = (r >> tj) - p (s >> tj)
+// equals floor(r/Q^j) mod p (since floor(floor(r/p)/Q^j) = floor(floor(r/Q^j)/p));
+// c_j = floor(r/Q^j) - Q floor(r/Q^(j+1)) gives c_j mod p = (mu_j - (Q mod p) mu_{j+1}) mod p.
+template <typename W>
+__global__ __launch_bounds__(kThreads) void redq_kernel(int64_t m, int64_t n, int64_t nw,
+                                                         const W *__restrict__ CC, int64_t ldcc,
+                                                         uint8_t *__restrict__ C, int64_t ldc,
+                                                         uint32_t t, uint32_t d, uint32_t p, double invp,
+                                                         uint32_t qmodp) {
+    const int64_t total = m * nw;
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = idx / nw, J = idx - i * nw;
+        const uint64_t r = u64_from_word(CC[i * ldcc + J]);
+        const uint64_t s = div_u64(r, p, invp);  // floor(r / p), the one division
+        uint32_t mu_next = 0;  // mu_{d+1} = 0
+        // walk j downwards so mu_{j+1} is at hand
+        for (int32_t j = (int32_t)d; j >= 0; --j) {
+            const uint32_t sh = t * (uint32_t)j;
+            const uint32_t mu = (uint32_t)((r >> sh) - (uint64_t)p * (s >> sh));
+            const uint64_t v = (uint64_t)mu + (uint64_t)qmodp * p - (uint64_t)qmodp * mu_next;
+            const int64_t col = J * (d + 1) + j;
+            if (col < n) C[i * ldc + col] = (uint8_t)mod_u64(v, p, invp);
+            mu_next = mu;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void fill_u8_kernel(uint8_t *C, int64_t m, int64_t n, int64_t ldc,
+                                                            uint8_t v) {
+    const int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = idx / n, j = idx - i * n;
+        C[i * ldc + j] = v;
+    }
+}
+
+qmm_status check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(QMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return QMM_OK;
+}
+
+}  // namespace
+
+qmm_status launch_pack_rows_rev(const qmm_plan &pl, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
+                                void *CA, int64_t ldca, void *stream) {
+    const int64_t nw = words_for(k, pl.d);
+    if (m * nw == 0) return QMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24)
+        pack_rows_rev_kernel<float><<<grid_for(m * nw), kThreads, 0, s>>>(m, k, nw, A, lda, (float *)CA, ldca, pl.t, pl.d);
+    else
+        pack_rows_rev_kernel<double><<<grid_for(m * nw), kThreads, 0, s>>>(m, k, nw, A, lda, (double *)CA, ldca, pl.t, pl.d);
+    return check_launch("pack_rows_rev");
+}
+
+qmm_status launch_pack_cols_fwd(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                void *CB, int64_t ldcb, void *stream) {
+    const int64_t nw = words_for(k, pl.d);
+    if (nw * n == 0) return QMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24)
+        pack_cols_fwd_kernel<float><<<grid_for(nw * n), kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CB, ldcb, pl.t, pl.d);
+    else
+        pack_cols_fwd_kernel<double><<<grid_for(nw * n), kThreads, 0, s>>>(k, n, nw, B, ldb, (double *)CB, ldcb, pl.t, pl.d);
+    return check_launch("pack_cols_fwd");
+}
+
+qmm_status launch_pack_rows_fwd(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                void *CBr, int64_t ldcbr, void *stream) {
+    const int64_t nw = words_for(n, pl.d);
+    if (k * nw == 0) return QMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24)
+        pack_rows_fwd_kernel<float><<<grid_for(k * nw), kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CBr, ldcbr, pl.t, pl.d);
+    else
+        pack_rows_fwd_kernel<double><<<grid_for(k * nw), kThreads, 0, s>>>(k, n, nw, B, ldb, (double *)CBr, ldcbr, pl.t, pl.d);
+    return check_launch("pack_rows_fwd");
+}
+
+qmm_status launch_unpack(const qmm_plan &pl, int which, int64_t rows, int64_t cols, const void *packed,
+                         int64_t ldp, uint8_t *out, int64_t ldo, void *stream) {
+    if (rows * cols == 0) return QMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24)
+        unpack_kernel<float><<<grid_for(rows * cols), kThreads, 0, s>>>(which, rows, cols, (const float *)packed, ldp, out, ldo, pl.t, pl.d);
+    else
+        unpack_kernel<double><<<grid_for(rows * cols), kThreads, 0, s>>>(which, rows, cols, (const double *)packed, ldp, out, ldo, pl.t, pl.d);
+    return check_launch("unpack");
+}
+
+qmm_status launch_extract(const qmm_plan &pl, int64_t m, int64_t n, const void *T, int64_t ldt, uint8_t *C,
+                          int64_t ldc, void *stream) {
+    if (m * n == 0) return QMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t qmask = (1ull << pl.t) - 1;
+    const bool offset = pl.regime == QMM_REGIME_OFFSET;
+    const double invp = 1.0 / (double)pl.p;
+    if (pl.beta == 24)
+        extract_kernel<float><<<grid_for(m * n), kThreads, 0, s>>>(m, n, (const float *)T, ldt, C, ldc, pl.t * pl.d, qmask, offset, pl.p, invp);
+    else
+        extract_kernel<double><<<grid_for(m * n), kThreads, 0, s>>>(m, n, (const double *)T, ldt, C, ldc, pl.t * pl.d, qmask, offset, pl.p, invp);
+    return check_launch("extract");
+}
+
+qmm_status launch_redq(const qmm_plan &pl, int64_t m, int64_t n, const void *CC, int64_t ldcc, uint8_t *C,
+                       int64_t ldc, void *stream) {
+    const int64_t nw = words_for(n, pl.d);
+    if (m * nw == 0) return QMM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const double invp = 1.0 / (double)pl.p;
+    const uint32_t qmodp = (uint32_t)((1ull << pl.t) % pl.p);
+    if (pl.beta == 24)
+        redq_kernel<float><<<grid_for(m * nw), kThreads, 0, s>>>(m, n, nw, (const float *)CC, ldcc, C, ldc, pl.t, pl.d, pl.p, invp, qmodp);
+    else
+        redq_kernel<double><<<grid_for(m * nw), kThreads, 0, s>>>(m, n, nw, (const double *)CC, ldcc, C, ldc, pl.t, pl.d, pl.p, invp, qmodp);
+    return check_launch("redq");
+}
+
+qmm_status launch_fill_u8(uint8_t *C, int64_t m, int64_t n, int64_t ldc, uint8_t v, void *stream) {
+    if (m * n == 0) return QMM_OK;
+    fill_u8_kernel<<<grid_for(m * n), kThreads, 0, (hipStream_t)stream>>>(C, m, n, ldc, v);
+    return check_launch("fill");
+}
+
+}  // namespace qmm

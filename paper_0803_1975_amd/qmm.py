@@ -1,0 +1,301 @@
+"""Python binding of libqmm (include/qmm.h): argument marshalling only.
+
+Every call goes to the HIP library; torch supplies device memory and the current
+stream.  There is no CPU fallback: if libqmm.so is missing the import of this
+module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqmm.so")
+
+# qmm_status
+OK, EINVAL, EBOUND, EVALUE, ENOSPACE, EDEVICE, EUNSUPPORTED = range(7)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EBOUND", 3: "EVALUE", 4: "ENOSPACE", 5: "EDEVICE", 6: "EUNSUPPORTED"}
+# qmm_path
+PATH_AUTO, PATH_FP64_QADIC, PATH_FP64_REDQ, PATH_FP32_QADIC, PATH_FP32_REDQ, PATH_INT8 = range(6)
+PATH_NAMES = {0: "auto", 1: "fp64_qadic", 2: "fp64_redq", 3: "fp32_qadic", 4: "fp32_redq", 5: "int8"}
+# qmm_regime
+REGIME_EXACT, REGIME_OFFSET, REGIME_PAPER, REGIME_INT = range(4)
+REGIME_NAMES = {0: "exact", 1: "offset", 2: "paper", 3: "int"}
+# flags
+BOUND_PROVEN, BOUND_PAPER, PLAN_UNBLOCKED, BOUND_G4, BOUND_EQ4 = 0, 1, 2, 4, 8
+BATCH_FORCE_FP64 = 1
+# unpack selectors
+ROWS_REV, COLS_FWD, ROWS_FWD = 0, 1, 2
+
+EXPORTS = [
+    "qmm_choose_Qd", "qmm_validate_plan", "qmm_pack_rows_rev", "qmm_pack_cols_fwd", "qmm_pack_rows_fwd",
+    "qmm_unpack", "qmm_extract", "qmm_redq", "qmm_gemm_workspace_size", "qmm_gemm_mod_p", "qmm_gemm_packed",
+    "qmm_batched_create", "qmm_gemm_mod_p_batched", "qmm_batched_plan", "qmm_batched_destroy",
+    "qmm_last_error", "qmm_version",
+]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint32), ("t", ctypes.c_uint32), ("d", ctypes.c_uint32),
+                ("beta", ctypes.c_uint32), ("k_block", ctypes.c_int64), ("path", ctypes.c_uint32),
+                ("regime", ctypes.c_uint32), ("g", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    def __repr__(self):
+        return (f"Plan(p={self.p}, t={self.t}, d={self.d}, beta={self.beta}, k_block={self.k_block}, "
+                f"path={PATH_NAMES.get(self.path, self.path)}, regime={REGIME_NAMES.get(self.regime, self.regime)}, "
+                f"g={self.g}, tile={self.tile})")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("p", ctypes.c_uint32),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
+
+
+class QmmError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {last_error()}")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libqmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0803_1975_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, u32, vp, sz = ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
+        P = ctypes.POINTER(Plan)
+        sig = {
+            "qmm_choose_Qd": [u32, i64, i64, i64, u32, ctypes.c_int, u32, P],
+            "qmm_validate_plan": [P, i64, i64, i64],
+            "qmm_pack_rows_rev": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_pack_cols_fwd": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_pack_rows_fwd": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_unpack": [P, ctypes.c_int, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_extract": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_redq": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_gemm_workspace_size": [P, i64, i64, i64, ctypes.POINTER(sz)],
+            "qmm_gemm_mod_p": [P, i64, i64, i64, u32, vp, i64, vp, i64, vp, i64, vp, sz, vp],
+            "qmm_gemm_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_batched_create": [i64, ctypes.POINTER(Problem), u32, ctypes.POINTER(vp)],
+            "qmm_gemm_mod_p_batched": [vp, vp],
+            "qmm_batched_plan": [vp, i64, P],
+            "qmm_batched_destroy": [vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.qmm_last_error.restype = ctypes.c_char_p
+        L.qmm_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().qmm_last_error().decode()
+
+
+def version() -> str:
+    return lib().qmm_version().decode()
+
+
+def _check(st, where):
+    if st != OK:
+        raise QmmError(st, where)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _ld(t):
+    """Leading dimension of a 2-D tensor with unit column stride."""
+    if t.dim() != 2:
+        raise ValueError("2-D tensors are required")
+    if t.numel() == 0:
+        return max(t.shape[1], 1)
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError("2-D tensors with contiguous rows are required")
+    return t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def _u8(t, name):
+    import torch
+    if t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError(f"{name} must be a uint8 CUDA tensor")
+
+
+def word_dtype(plan):
+    import torch
+    return torch.float32 if plan.beta == 24 else torch.float64
+
+
+# ---------------------------------------------------------------------------
+def choose_Qd(p, m, n, k, beta=0, path=PATH_AUTO, flags=0) -> Plan:
+    pl = Plan()
+    _check(lib().qmm_choose_Qd(p, m, n, k, beta, path, flags, ctypes.byref(pl)), "qmm_choose_Qd")
+    return pl
+
+
+def try_choose_Qd(p, m, n, k, beta=0, path=PATH_AUTO, flags=0):
+    """(status, plan) without raising."""
+    pl = Plan()
+    st = lib().qmm_choose_Qd(p, m, n, k, beta, path, flags, ctypes.byref(pl))
+    return st, pl
+
+
+def validate_plan(plan, m, n, k) -> int:
+    return lib().qmm_validate_plan(ctypes.byref(plan), m, n, k)
+
+
+def pack_rows_rev(plan, A, CA=None, stream=None):
+    import torch
+    _u8(A, "A")
+    m, k = A.shape
+    if CA is None:
+        CA = torch.empty((m, -(-k // (plan.d + 1))), dtype=word_dtype(plan), device=A.device)
+    _check(lib().qmm_pack_rows_rev(ctypes.byref(plan), m, k, _ptr(A), _ld(A), _ptr(CA), _ld(CA), _stream(stream)),
+           "qmm_pack_rows_rev")
+    return CA
+
+
+def pack_cols_fwd(plan, B, CB=None, stream=None):
+    import torch
+    _u8(B, "B")
+    k, n = B.shape
+    if CB is None:
+        CB = torch.empty((-(-k // (plan.d + 1)), n), dtype=word_dtype(plan), device=B.device)
+    _check(lib().qmm_pack_cols_fwd(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(CB), _ld(CB), _stream(stream)),
+           "qmm_pack_cols_fwd")
+    return CB
+
+
+def pack_rows_fwd(plan, B, CBr=None, stream=None):
+    import torch
+    _u8(B, "B")
+    k, n = B.shape
+    if CBr is None:
+        CBr = torch.empty((k, -(-n // (plan.d + 1))), dtype=word_dtype(plan), device=B.device)
+    _check(lib().qmm_pack_rows_fwd(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(CBr), _ld(CBr), _stream(stream)),
+           "qmm_pack_rows_fwd")
+    return CBr
+
+
+def unpack(plan, which, rows, cols, packed, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.uint8, device=packed.device)
+    _check(lib().qmm_unpack(ctypes.byref(plan), which, rows, cols, _ptr(packed), _ld(packed), _ptr(out), _ld(out),
+                            _stream(stream)), "qmm_unpack")
+    return out
+
+
+def extract(plan, T, C=None, stream=None):
+    import torch
+    m, n = T.shape
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=T.device)
+    _check(lib().qmm_extract(ctypes.byref(plan), m, n, _ptr(T), _ld(T), _ptr(C), _ld(C), _stream(stream)),
+           "qmm_extract")
+    return C
+
+
+def redq(plan, CC, n, C=None, stream=None):
+    import torch
+    m = CC.shape[0]
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=CC.device)
+    _check(lib().qmm_redq(ctypes.byref(plan), m, n, _ptr(CC), _ld(CC), _ptr(C), _ld(C), _stream(stream)), "qmm_redq")
+    return C
+
+
+def gemm_workspace_size(plan, m, n, k) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().qmm_gemm_workspace_size(ctypes.byref(plan), m, n, k, ctypes.byref(out)), "qmm_gemm_workspace_size")
+    return out.value
+
+
+def workspace(plan, m, n, k, device="cuda"):
+    """A device workspace tensor large enough for gemm_mod_p(plan, ...)."""
+    import torch
+    return torch.empty(max(gemm_workspace_size(plan, m, n, k), 1), dtype=torch.uint8, device=device)
+
+
+def gemm_mod_p(A, B, p, plan=None, C=None, ws=None, stream=None):
+    """C = A x B mod p (uint8 device tensors)."""
+    import torch
+    _u8(A, "A")
+    _u8(B, "B")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise ValueError("inner dimensions differ")
+    if plan is None:
+        plan = choose_Qd(p, m, n, k)
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+    if ws is None:
+        ws = workspace(plan, m, n, k, A.device)
+    _check(lib().qmm_gemm_mod_p(ctypes.byref(plan), m, n, k, p, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C),
+                                _ptr(ws), ws.numel(), _stream(stream)), "qmm_gemm_mod_p")
+    return C
+
+
+def gemm_packed(plan, k, CA, CB, C=None, stream=None):
+    """Procedure (1): C = digit d of CA x CB, mod p."""
+    import torch
+    m, n = CA.shape[0], CB.shape[1]
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=CA.device)
+    _check(lib().qmm_gemm_packed(ctypes.byref(plan), m, n, k, _ptr(CA), _ld(CA), _ptr(CB), _ld(CB), _ptr(C), _ld(C),
+                                 _stream(stream)), "qmm_gemm_packed")
+    return C
+
+
+@dataclass
+class Batch:
+    handle: ctypes.c_void_p
+    count: int
+    keep: list
+
+    def run(self, stream=None):
+        _check(lib().qmm_gemm_mod_p_batched(self.handle, _stream(stream)), "qmm_gemm_mod_p_batched")
+
+    def plan(self, i) -> Plan:
+        pl = Plan()
+        _check(lib().qmm_batched_plan(self.handle, i, ctypes.byref(pl)), "qmm_batched_plan")
+        return pl
+
+    def destroy(self):
+        if self.handle:
+            lib().qmm_batched_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+
+def batched_create(problems, flags=0) -> Batch:
+    """problems: list of (A, B, C, p) uint8 device tensors; C is written by run()."""
+    arr = (Problem * len(problems))()
+    for i, (A, B, C, p) in enumerate(problems):
+        m, k = A.shape
+        n = B.shape[1]
+        arr[i] = Problem(m, n, k, p, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), C.data_ptr(), _ld(C))
+    h = ctypes.c_void_p(0)
+    _check(lib().qmm_batched_create(len(problems), arr, flags, ctypes.byref(h)), "qmm_batched_create")
+    return Batch(h, len(problems), [problems])

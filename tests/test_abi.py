@@ -1,0 +1,82 @@
+"""The C-ABI library: it loads, exports every symbol include/qmm.h declares, and
+its host-side argument checks reject bad calls before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0803_1975_amd import qmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "qmm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qmm_[a-z0-9_A-Z]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = qmm.lib()
+    declared = header_functions()
+    assert len(declared) >= 17
+    missing = [f for f in declared if not hasattr(L, f)]
+    assert not missing, missing
+    assert sorted(qmm.EXPORTS) == declared
+
+
+def test_version_and_error_string():
+    assert re.match(r"^\d+\.\d+\.\d+$", qmm.version())
+    st, _ = qmm.try_choose_Qd(1, 4, 4, 4)
+    assert st == qmm.EINVAL and "p" in qmm.last_error()
+
+
+def test_plan_struct_layout():
+    assert ctypes.sizeof(qmm.Plan) == 40
+    assert qmm.Plan.k_block.offset == 16 and qmm.Plan.path.offset == 24
+
+
+def test_argument_checks_reject_before_any_device_work():
+    L = qmm.lib()
+    pl = qmm.choose_Qd(7, 64, 64, 64, path=qmm.PATH_FP64_QADIC)
+    null = ctypes.c_void_p(0)
+    # null matrix pointers with non-zero sizes
+    assert L.qmm_pack_rows_rev(ctypes.byref(pl), 4, 4, null, 4, null, 4, null) == qmm.EINVAL
+    assert L.qmm_gemm_mod_p(ctypes.byref(pl), 4, 4, 4, 7, null, 4, null, 4, null, 4, null, 0, null) == qmm.EINVAL
+    # short leading dimension
+    fake = ctypes.c_void_p(0x1000)
+    assert L.qmm_gemm_mod_p(ctypes.byref(pl), 4, 4, 4, 7, fake, 3, fake, 4, fake, 4, null, 0, null) == qmm.EINVAL
+    # p outside the byte range, p mismatch with the plan
+    assert L.qmm_gemm_mod_p(None, 4, 4, 4, 257, fake, 4, fake, 4, fake, 4, null, 0, null) == qmm.EINVAL
+    assert L.qmm_gemm_mod_p(ctypes.byref(pl), 4, 4, 4, 5, fake, 4, fake, 4, fake, 4, null, 0, null) == qmm.EINVAL
+    # workspace too small
+    assert L.qmm_gemm_mod_p(ctypes.byref(pl), 4, 4, 4, 7, fake, 4, fake, 4, fake, 4, fake, 8, null) == qmm.ENOSPACE
+    # an unknown unpack selector, a REDQ plan for procedure (1)
+    assert L.qmm_unpack(ctypes.byref(pl), 3, 4, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    rq = qmm.choose_Qd(7, 64, 64, 64, path=qmm.PATH_FP64_REDQ)
+    assert L.qmm_gemm_packed(ctypes.byref(rq), 4, 4, 4, fake, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    # zero-sized products are valid no-ops
+    assert L.qmm_gemm_mod_p(ctypes.byref(pl), 0, 4, 4, 7, null, 4, fake, 4, null, 4, null, 0, null) == qmm.OK
+
+
+def test_plans_that_break_the_bounds_are_refused():
+    pl = qmm.choose_Qd(3, 64, 64, 64, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
+    assert (pl.t, pl.d, pl.regime) == (9, 4, qmm.REGIME_OFFSET)
+    assert qmm.validate_plan(pl, 64, 64, 64) == qmm.OK
+    bad = qmm.Plan.from_buffer_copy(pl)
+    bad.t = 8                                    # Table 1's Q = 2^8 at k = 64 breaks eq. (3)
+    bad.d = 5
+    assert qmm.validate_plan(bad, 64, 64, 64) == qmm.EBOUND
+    bad = qmm.Plan.from_buffer_copy(pl)
+    bad.regime = qmm.REGIME_EXACT                # S_max >= 2^53 here
+    assert qmm.validate_plan(bad, 64, 64, 64) == qmm.EBOUND
+    paper = qmm.choose_Qd(3, 64, 64, 64, flags=qmm.BOUND_PAPER, path=qmm.PATH_FP64_QADIC)
+    assert paper.regime == qmm.REGIME_PAPER and qmm.validate_plan(paper, 64, 64, 64) == qmm.EBOUND
+    i8 = qmm.choose_Qd(251, 4, 4, 200000, path=qmm.PATH_INT8)
+    assert i8.k_block < 200000 and i8.k_block % 64 == 0
+    big = qmm.Plan.from_buffer_copy(i8)
+    big.k_block = 200000
+    assert qmm.validate_plan(big, 4, 4, 200000) == qmm.EBOUND
+    with pytest.raises(qmm.QmmError):
+        qmm.choose_Qd(300, 4, 4, 4, path=qmm.PATH_INT8)

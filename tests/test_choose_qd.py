@@ -1,0 +1,143 @@
+"""The library's planner (qmm_choose_Qd) against the oracle's bound predicates.
+
+Every plan it returns must satisfy the oracle's regime test, and no plan that the
+oracle accepts may be cheaper under the planner's stated objective (packed words
+per output plus 8 words per extra block, blocks a multiple of 16 words)."""
+import pytest
+
+from oracle import bounds
+from paper_0803_1975_amd import qmm
+
+KT_WORDS = 16
+BLOCK_COST = 8
+
+
+def brute_force_best(p, k, beta, g=1, unblocked=False, eq4=False):
+    best = None
+    for t in range(1, beta):
+        kbmax = ((1 << t) - 1) // ((p - 1) ** 2)
+        if kbmax < 1:
+            continue
+        for d in range(0, beta // t + 1):
+            if k <= kbmax:
+                kb = k
+            elif unblocked:
+                continue
+            else:
+                unit = (d + 1) * KT_WORDS
+                kb = (kbmax // unit) * unit
+                if kb < 1:
+                    continue
+            if d > 0 and d + 1 > kb:
+                continue
+            if eq4 and not bounds.eq4_upper_ok(t, d, beta):
+                continue
+            if bounds.qadic_regime(p, kb, t, d, beta, g) is None:
+                continue
+            blocks = -(-k // kb)
+            cost = -(-k // (d + 1)) + (blocks - 1) * BLOCK_COST
+            if best is None or cost < best[0] or (cost == best[0] and blocks < best[1]):
+                best = (cost, blocks)
+    return best
+
+
+CASES = [(p, k) for p in (2, 3, 5, 7, 11, 13, 31, 101, 251)
+         for k in (1, 2, 5, 15, 16, 63, 64, 100, 255, 256, 511, 1000, 4096, 8192, 16384, 100000)]
+
+
+@pytest.mark.parametrize("p,k", CASES)
+def test_fp64_qadic_plan_is_valid_and_optimal(p, k):
+    for unblocked in (False, True):
+      for eq4 in (False, True):
+        flags = (qmm.PLAN_UNBLOCKED if unblocked else 0) | (qmm.BOUND_EQ4 if eq4 else 0)
+        st, pl = qmm.try_choose_Qd(p, 32, 32, k, path=qmm.PATH_FP64_QADIC, flags=flags)
+        best = brute_force_best(p, k, 53, unblocked=unblocked, eq4=eq4)
+        if best is None:
+            assert st == qmm.EBOUND
+            continue
+        assert st == qmm.OK, qmm.last_error()
+        kb = min(pl.k_block, k)
+        reg = bounds.qadic_regime(p, kb, pl.t, pl.d, 53, pl.g)
+        assert reg == ("exact" if pl.regime == qmm.REGIME_EXACT else "offset")
+        blocks = -(-k // pl.k_block)
+        if pl.k_block < k:
+            assert pl.k_block % ((pl.d + 1) * KT_WORDS) == 0
+        cost = -(-k // (pl.d + 1)) + (blocks - 1) * BLOCK_COST
+        assert (cost, blocks) == best
+        assert qmm.validate_plan(pl, 32, 32, k) == qmm.OK
+
+
+@pytest.mark.parametrize("p,k", [(3, 15), (3, 255), (7, 56), (2, 300), (101, 1000), (3, 511)])
+def test_fp32_qadic_plans(p, k):
+    st, pl = qmm.try_choose_Qd(p, 8, 8, k, path=qmm.PATH_FP32_QADIC)
+    best = brute_force_best(p, k, 24)
+    assert (st == qmm.OK) == (best is not None)
+    if st == qmm.OK:
+        assert bounds.qadic_regime(p, min(pl.k_block, k), pl.t, pl.d, 24, pl.g) is not None
+
+
+def test_fp32_compression_for_p101_is_d0():
+    # Q > 10^4 for p = 101 already, so Q^2 > 2^24: only d = 0 is possible in 24 bits.
+    pl = qmm.choose_Qd(101, 8, 8, 8192, path=qmm.PATH_FP32_QADIC)
+    assert pl.d == 0 and pl.k_block < 8192
+
+
+def test_paper_rule_flag_matches_oracle():
+    for p in (2, 3, 7, 101):
+        for k in (1, 2, 7, 15, 64, 257, 4096, 32767, 32768):
+            pl = qmm.choose_Qd(p, 1, 1, k, path=qmm.PATH_FP64_QADIC, flags=qmm.BOUND_PAPER)
+            assert (pl.t, pl.d) == bounds.paper_choice(p, k, 53)
+
+
+def test_proven_unblocked_plans_reproduce_table1_interior():
+    # Strictly inside each printed range from Q = 2^6 on, the proven unblocked plan is
+    # the paper's (t, d): the offset regime admits Table 1 there.
+    for k, t, d in [(15, 6, 7), (31, 7, 6), (63, 8, 5), (255, 10, 4), (2047, 13, 3), (32767, 17, 2)]:
+        pl = qmm.choose_Qd(3, 8, 8, k, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
+        assert (pl.t, pl.d) == (t, d), (k, pl)
+
+
+def test_workload_plans():
+    # small: eq. (4) as printed gives t = 9, d = 4 (offset regime); its sharper sum
+    # form admits d = 5 at the same Q (words stay below 2^46, high part below 2^51)
+    pl = qmm.choose_Qd(3, 64, 64, 64, path=qmm.PATH_FP64_QADIC, flags=qmm.BOUND_EQ4)
+    assert (pl.t, pl.d, pl.k_block, pl.regime) == (9, 4, 64, qmm.REGIME_OFFSET)
+    pl = qmm.choose_Qd(3, 64, 64, 64, path=qmm.PATH_FP64_QADIC)
+    assert (pl.t, pl.d, pl.k_block, pl.regime) == (9, 5, 64, qmm.REGIME_OFFSET)
+    # square, unblocked: t = 18, d = 1, exact regime (S_max < 2^53)
+    pl = qmm.choose_Qd(7, 4096, 4096, 4096, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
+    assert (pl.t, pl.d, pl.regime) == (18, 1, qmm.REGIME_EXACT)
+    # large, p = 101: unblocked only d = 0; blocked d = 1
+    pl = qmm.choose_Qd(101, 8192, 8192, 8192, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
+    assert (pl.t, pl.d) == (27, 0)
+    pl = qmm.choose_Qd(101, 8192, 8192, 8192, path=qmm.PATH_FP64_QADIC)
+    assert pl.d == 1 and pl.k_block < 8192
+    # graph: unblocked t = 17, d = 2
+    pl = qmm.choose_Qd(3, 16384, 16384, 16384, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
+    assert (pl.t, pl.d, pl.regime) == (17, 2, qmm.REGIME_OFFSET)
+    # INT8: no blocking needed at these sizes, and AUTO picks it for byte residues
+    for p, k in ((7, 4096), (101, 8192), (3, 16384)):
+        pl = qmm.choose_Qd(p, k, k, k)
+        assert pl.path == qmm.PATH_INT8 and pl.k_block == k
+
+
+def test_redq_plans():
+    pl = qmm.choose_Qd(7, 4096, 4096, 4096, path=qmm.PATH_FP64_REDQ)
+    assert (pl.t, pl.d) == (18, 1)
+    assert bounds.redq_ok(7, 4096, pl.t, pl.d, 53)
+    pl = qmm.choose_Qd(3, 64, 64, 64, path=qmm.PATH_FP64_REDQ)
+    assert bounds.redq_ok(3, 64, pl.t, pl.d, 53) and not bounds.redq_ok(3, 64, pl.t, pl.d + 1, 53)
+    pl = qmm.choose_Qd(3, 64, 64, 300, path=qmm.PATH_FP32_REDQ)
+    assert bounds.redq_ok(3, 300, pl.t, pl.d, 24)
+    pl = qmm.choose_Qd(3, 64, 2, 64, path=qmm.PATH_FP64_REDQ)
+    assert pl.d == 1                           # never more residues per word than columns
+
+
+def test_int8_blocks():
+    for p in (2, 101, 251, 256):
+        k = 10 ** 6
+        pl = qmm.choose_Qd(p, 4, 4, k, path=qmm.PATH_INT8)
+        h = p // 2
+        assert pl.k_block * h * h + (p - 1) <= 2 ** 31 - 1
+        if pl.k_block < k:
+            assert pl.k_block % 64 == 0 and (pl.k_block + 64) * h * h + (p - 1) > 2 ** 31 - 1

@@ -1,0 +1,331 @@
+"""Parity of the HIP library against the CPU oracle, through the C ABI (needs an MI355X).
+
+Integer results must match bit for bit.  Small shapes are checked entry by entry
+against the full oracle product; the workload-size products are checked on
+sampled entries (each a plain dot product in the oracle), on whole rows, and on
+closed forms that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from oracle import bounds
+from paper_0803_1975_amd import qmm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+PATHS = (qmm.PATH_FP64_QADIC, qmm.PATH_FP64_REDQ, qmm.PATH_FP32_QADIC, qmm.PATH_FP32_REDQ, qmm.PATH_INT8)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("these tests need a GPU")
+    return _t
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def run_gemm(torch, A, B, p, path, flags=0):
+    m, k = A.shape
+    n = B.shape[1]
+    st, plan = qmm.try_choose_Qd(p, m, n, k, path=path, flags=flags)
+    if st != qmm.OK:
+        return None, None
+    C = qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan)
+    torch.cuda.synchronize()
+    return host(C), plan
+
+
+def test_native_library_is_loaded(torch):
+    qmm.lib()
+    maps = open("/proc/self/maps").read()
+    assert "libqmm.so" in maps
+
+
+# --- conversions --------------------------------------------------------------
+@pytest.mark.parametrize("p,t,d,beta", [(3, 9, 4, 53), (7, 18, 1, 53), (2, 5, 9, 53), (101, 27, 0, 53),
+                                        (3, 11, 1, 24), (5, 7, 2, 24)])
+def test_pack_and_unpack_match_oracle(torch, p, t, d, beta):
+    note("pack", p, t, d, beta)
+    rng = np.random.default_rng(t * 7 + d)
+    plan = qmm.Plan(p=p, t=t, d=d, beta=beta, k_block=1 << 40,
+                    path=qmm.PATH_FP64_QADIC if beta == 53 else qmm.PATH_FP32_QADIC)
+    A = rng.integers(0, p, (37, 101), dtype=np.uint8)
+    B = rng.integers(0, p, (101, 45), dtype=np.uint8)
+    CA = qmm.pack_rows_rev(plan, dev(torch, A))
+    CB = qmm.pack_cols_fwd(plan, dev(torch, B))
+    CBr = qmm.pack_rows_fwd(plan, dev(torch, B))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(CA).astype(np.uint64), ref.compress_rows_rev(A, t, d))
+    np.testing.assert_array_equal(host(CB).astype(np.uint64), ref.compress_cols_fwd(B, t, d))
+    np.testing.assert_array_equal(host(CBr).astype(np.uint64), ref.compress_rows_fwd(B, t, d))
+    np.testing.assert_array_equal(host(qmm.unpack(plan, qmm.ROWS_REV, 37, 101, CA)), A)
+    np.testing.assert_array_equal(host(qmm.unpack(plan, qmm.COLS_FWD, 101, 45, CB)), B)
+    np.testing.assert_array_equal(host(qmm.unpack(plan, qmm.ROWS_FWD, 101, 45, CBr)), B)
+
+
+def test_extract_matches_oracle_in_both_regimes(torch):
+    rng = np.random.default_rng(11)
+    # exact regime: p = 7, k = 4096, t = 18, d = 1; T is the exact sum S
+    p, t, d, k = 7, 18, 1, 4096
+    A = rng.integers(0, p, (20, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, 24), dtype=np.uint8)
+    S = ref.packed_product_exact(ref.compress_rows_rev(A, t, d), ref.compress_cols_fwd(B, t, d))
+    assert max(int(x) for x in S.ravel()) < 2 ** 53
+    T = np.array([[float(int(x)) for x in row] for row in S])
+    plan = qmm.choose_Qd(p, 20, 24, k, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
+    assert (plan.t, plan.d, plan.regime) == (t, d, qmm.REGIME_EXACT)
+    got = host(qmm.extract(plan, dev(torch, T)))
+    np.testing.assert_array_equal(got, ref.extract(S, t, d, p))
+    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+    # offset regime: p = 3, k = 64, t = 9, d = 4; T = M + floor(S / Q^d) Q^d
+    p, t, d, k = 3, 9, 4, 64
+    A = rng.integers(0, p, (20, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, 24), dtype=np.uint8)
+    S = ref.packed_product_exact(ref.compress_rows_rev(A, t, d), ref.compress_cols_fwd(B, t, d))
+    M = (1 << 52) << (t * d)
+    Tint = [[M + ((int(x) >> (t * d)) << (t * d)) for x in row] for row in S]
+    T = np.array([[float(v) for v in row] for row in Tint])
+    assert all(int(T[i, j]) == Tint[i][j] for i in range(20) for j in range(24))
+    plan = qmm.choose_Qd(p, 20, 24, k, path=qmm.PATH_FP64_QADIC, flags=qmm.BOUND_EQ4)
+    assert plan.regime == qmm.REGIME_OFFSET and (plan.t, plan.d) == (t, d)
+    got = host(qmm.extract(plan, dev(torch, T)))
+    np.testing.assert_array_equal(got, ref.extract(np.array(Tint, dtype=object), t, d, p, offset=M))
+    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+
+
+@pytest.mark.parametrize("p,k,n", [(7, 4096, 50), (3, 64, 33), (101, 1000, 7), (2, 5, 100)])
+def test_redq_matches_oracle(torch, p, k, n):
+    note("redq", p, k, n)
+    rng = np.random.default_rng(p + k)
+    A = rng.integers(0, p, (9, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    plan = qmm.choose_Qd(p, 9, n, k, path=qmm.PATH_FP64_REDQ)
+    CBr = ref.compress_rows_fwd(B, plan.t, plan.d)
+    CC = A.astype(object).dot(CBr.astype(object))
+    T = np.array([[float(int(x)) for x in row] for row in CC])
+    got = host(qmm.redq(plan, dev(torch, T), n))
+    np.testing.assert_array_equal(got, ref.redq(CC, plan.t, plan.d, p, n))
+    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+
+
+# --- full products at oracle-sized shapes ----------------------------------------
+SHAPES = [(1, 1, 1), (64, 64, 64), (17, 33, 5), (130, 257, 300), (300, 129, 1000), (128, 128, 16),
+          (129, 127, 4097), (5, 200, 3)]
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("p", (2, 3, 7, 101, 251))
+def test_gemm_matches_oracle(torch, path, p):
+    rng = np.random.default_rng(path * 1000 + p)
+    for m, n, k in SHAPES:
+        note("gemm", qmm.PATH_NAMES[path], p, m, n, k)
+        A = rng.integers(0, p, (m, k), dtype=np.uint8)
+        B = rng.integers(0, p, (k, n), dtype=np.uint8)
+        got, plan = run_gemm(torch, A, B, p, path)
+        if got is None:
+            continue
+        np.testing.assert_array_equal(got, ref.modmul(A, B, p), err_msg=f"{plan} {m}x{n}x{k}")
+
+
+@pytest.mark.parametrize("path", (qmm.PATH_FP64_QADIC, qmm.PATH_FP32_QADIC))
+def test_unblocked_and_eq4_plans(torch, path):
+    rng = np.random.default_rng(5)
+    for p, (m, n, k) in ((3, (70, 90, 2047)), (7, (64, 64, 4096)), (101, (33, 65, 800))):
+        A = rng.integers(0, p, (m, k), dtype=np.uint8)
+        B = rng.integers(0, p, (k, n), dtype=np.uint8)
+        for flags in (qmm.PLAN_UNBLOCKED, qmm.BOUND_EQ4, qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4):
+            got, plan = run_gemm(torch, A, B, p, path, flags)
+            if got is None:
+                continue
+            note("flags", flags, plan)
+            np.testing.assert_array_equal(got, ref.modmul(A, B, p), err_msg=str(plan))
+
+
+def test_gemm_packed_procedure_1(torch):
+    rng = np.random.default_rng(9)
+    for p, (m, n, k) in ((3, (64, 64, 64)), (7, (100, 70, 4096)), (3, (33, 31, 16384))):
+        A = rng.integers(0, p, (m, k), dtype=np.uint8)
+        B = rng.integers(0, p, (k, n), dtype=np.uint8)
+        plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP64_QADIC)
+        note("packed", plan)
+        CA = qmm.pack_rows_rev(plan, dev(torch, A))
+        CB = qmm.pack_cols_fwd(plan, dev(torch, B))
+        got = host(qmm.gemm_packed(plan, k, CA, CB))
+        np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+
+
+# --- edge cases --------------------------------------------------------------------
+@pytest.mark.parametrize("path", PATHS)
+def test_degenerate_shapes(torch, path):
+    p = 7
+    A = np.zeros((5, 0), np.uint8)
+    B = np.zeros((0, 6), np.uint8)
+    plan = qmm.choose_Qd(p, 5, 6, 0, path=path)
+    C = torch.full((5, 6), 99, dtype=torch.uint8, device="cuda")
+    qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan, C=C)
+    assert int(C.max()) == 0
+    C0 = qmm.gemm_mod_p(torch.zeros((0, 4), dtype=torch.uint8, device="cuda"),
+                        torch.zeros((4, 3), dtype=torch.uint8, device="cuda"), p,
+                        plan=qmm.choose_Qd(p, 0, 3, 4, path=path))
+    assert C0.shape == (0, 3)
+
+
+@pytest.mark.parametrize("path,p,k", [(qmm.PATH_FP64_QADIC, 3, 16384), (qmm.PATH_FP64_QADIC, 7, 4096),
+                                      (qmm.PATH_FP64_QADIC, 101, 8192), (qmm.PATH_FP64_QADIC, 2, 100000),
+                                      (qmm.PATH_FP64_REDQ, 7, 4096), (qmm.PATH_FP64_REDQ, 101, 8192),
+                                      (qmm.PATH_FP32_QADIC, 3, 5000), (qmm.PATH_FP32_QADIC, 101, 4000),
+                                      (qmm.PATH_FP32_REDQ, 3, 511), (qmm.PATH_INT8, 251, 1000),
+                                      (qmm.PATH_INT8, 101, 8192)])
+def test_worst_case_all_p_minus_one(torch, path, p, k):
+    # every residue p-1: C = k (p-1)^2 = k (mod p); the largest digits, words and low parts
+    st, plan = qmm.try_choose_Qd(p, 48, 40, k, path=path)
+    assert st == qmm.OK, qmm.last_error()
+    note("worst", plan, k)
+    A = torch.full((48, k), p - 1, dtype=torch.uint8, device="cuda")
+    B = torch.full((k, 40), p - 1, dtype=torch.uint8, device="cuda")
+    C = host(qmm.gemm_mod_p(A, B, p, plan=plan))
+    assert (C == (k * (p - 1) ** 2) % p).all(), (plan, np.unique(C))
+
+
+def test_int8_blocked_accumulation(torch):
+    # centred residue 125 of p = 251: products 15625 overflow int32 after 137438 terms
+    p, k = 251, 140000
+    plan = qmm.choose_Qd(p, 16, 16, k, path=qmm.PATH_INT8)
+    assert plan.k_block < k
+    A = torch.full((16, k), 125, dtype=torch.uint8, device="cuda")
+    B = torch.full((k, 16), 125, dtype=torch.uint8, device="cuda")
+    C = host(qmm.gemm_mod_p(A, B, p, plan=plan))
+    assert (C == (k * 125 * 125) % p).all()
+    rng = np.random.default_rng(3)
+    A = rng.integers(0, p, (20, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, 9), dtype=np.uint8)
+    got, _ = run_gemm(torch, A, B, p, qmm.PATH_INT8)
+    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+
+
+def test_offset_regime_relies_on_one_rounding_per_product(torch):
+    # p = 3, t = 7, d = 5, k = 24: every product's low part sits just below Q^d/2.
+    # One correctly rounded step per product (what the matrix cores do) floors each
+    # product; four products summed before one rounding would not (see the oracle's
+    # emulation).  All-(p-1) operands make every low part maximal.
+    p, t, d, k = 3, 7, 5, 24
+    assert bounds.offset_ok(p, k, t, d, 53, g=1) and not bounds.offset_ok(p, k, t, d, 53, g=4)
+    plan = qmm.Plan(p=p, t=t, d=d, beta=53, k_block=k, path=qmm.PATH_FP64_QADIC, regime=qmm.REGIME_OFFSET, g=1)
+    assert qmm.validate_plan(plan, 64, 64, k) == qmm.OK
+    A = torch.full((64, k), p - 1, dtype=torch.uint8, device="cuda")
+    B = torch.full((k, 64), p - 1, dtype=torch.uint8, device="cuda")
+    C = host(qmm.gemm_mod_p(A, B, p, plan=plan))
+    assert (C == (k * (p - 1) ** 2) % p).all()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_repeat_launches_are_bit_identical(torch, path):
+    p = 7
+    rng = np.random.default_rng(1)
+    A = dev(torch, rng.integers(0, p, (300, 700), dtype=np.uint8))
+    B = dev(torch, rng.integers(0, p, (700, 260), dtype=np.uint8))
+    plan = qmm.choose_Qd(p, 300, 260, 700, path=path)
+    ws = qmm.workspace(plan, 300, 260, 700)
+    first = qmm.gemm_mod_p(A, B, p, plan=plan, ws=ws).clone()
+    for _ in range(9):
+        assert torch.equal(qmm.gemm_mod_p(A, B, p, plan=plan, ws=ws), first)
+
+
+def test_strided_operands(torch):
+    p = 5
+    rng = np.random.default_rng(2)
+    Abig = rng.integers(0, p, (90, 300), dtype=np.uint8)
+    Bbig = rng.integers(0, p, (250, 180), dtype=np.uint8)
+    A, B = Abig[:, 7:207], Bbig[:200, 3:163]
+    dA, dB = dev(torch, Abig)[:, 7:207], dev(torch, Bbig)[:200, 3:163]
+    Cbig = torch.zeros((90, 400), dtype=torch.uint8, device="cuda")
+    for path in PATHS:
+        plan = qmm.choose_Qd(p, 90, 160, 200, path=path)
+        C = Cbig[:, 10:170]
+        qmm.gemm_mod_p(dA, dB, p, plan=plan, C=C)
+        np.testing.assert_array_equal(host(C), ref.modmul(np.ascontiguousarray(A), np.ascontiguousarray(B), p))
+        assert int(Cbig[:, :10].max()) == 0 and int(Cbig[:, 170:].max()) == 0
+
+
+# --- workload sizes -------------------------------------------------------------------
+def sampled_check(torch, A, B, p, C, nsamp=20000, rows=4, seed=0):
+    rng = np.random.default_rng(seed)
+    m, n = C.shape
+    ri = rng.integers(0, m, nsamp)
+    ci = rng.integers(0, n, nsamp)
+    np.testing.assert_array_equal(C[ri, ci], ref.modmul_entries(A, B, p, ri, ci))
+    for i in rng.integers(0, m, rows):
+        np.testing.assert_array_equal(C[i], ref.modmul(A[i:i + 1], B, p)[0])
+    # the last row and column cross the ragged tile edges when there are any
+    np.testing.assert_array_equal(C[m - 1], ref.modmul(A[m - 1:m], B, p)[0])
+
+
+@pytest.mark.parametrize("name", ("small", "square", "large"))
+def test_workloads_all_paths(torch, name):
+    p, A, B = synth.workload(name)
+    m, k = A.shape
+    n = B.shape[1]
+    dA, dB = dev(torch, A), dev(torch, B)
+    for path in PATHS:
+        for flags in (0, qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4):
+            st, plan = qmm.try_choose_Qd(p, m, n, k, path=path, flags=flags)
+            if st != qmm.OK:
+                note(name, "no plan", qmm.PATH_NAMES[path], flags, qmm.last_error())
+                continue
+            note(name, plan)
+            C = host(qmm.gemm_mod_p(dA, dB, p, plan=plan))
+            if m * n * k <= 64 ** 3:
+                np.testing.assert_array_equal(C, ref.modmul(A, B, p))
+            else:
+                sampled_check(torch, A, B, p, C)
+
+
+def test_graph_workload_and_paley_closed_form(torch):
+    # Paley graph on q = 16381 (prime, q = 1 mod 4): strongly regular, so
+    # A^2 = (q-1)/2 I + (q-5)/4 A + (q-1)/4 (J - I - A) holds entry by entry.
+    q = 16381
+    assert all(q % f for f in range(2, 128))
+    x = torch.arange(q, device="cuda", dtype=torch.int64)
+    is_sq = torch.zeros(q, dtype=torch.bool, device="cuda")
+    is_sq[(x[1:] * x[1:]) % q] = True
+    diff = (x[:, None] - x[None, :]) % q
+    Ad = is_sq[diff].to(torch.uint8)
+    del diff
+    for path in (qmm.PATH_INT8, qmm.PATH_FP64_QADIC):
+        for flags in (0, qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4):
+            if path == qmm.PATH_INT8 and flags:
+                continue
+            plan = qmm.choose_Qd(3, q, q, q, path=path, flags=flags)
+            note("paley", plan)
+            C = qmm.gemm_mod_p(Ad, Ad, 3, plan=plan)
+            a, b, c = ((q - 5) // 4) % 3, ((q - 1) // 4) % 3, ((q - 1) // 2) % 3
+            want = ((b + (a - b + 3) * Ad.to(torch.int16)) % 3).to(torch.uint8)
+            want.fill_diagonal_(c)
+            assert torch.equal(C, want)
+            del C, want
+    # the random graph of the workload itself, on sampled entries
+    p, A, B = synth.workload("graph")
+    dA = dev(torch, A)
+    for path in (qmm.PATH_INT8, qmm.PATH_FP64_QADIC):
+        plan = qmm.choose_Qd(p, A.shape[0], A.shape[0], A.shape[0], path=path)
+        note("graph", plan)
+        C = host(qmm.gemm_mod_p(dA, dA, p, plan=plan))
+        sampled_check(torch, A, A, p, C, nsamp=5000, rows=2)
+        assert (C == C.T).all()
