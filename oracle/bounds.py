@@ -84,6 +84,11 @@ def high_max(p: int, kb: int, t: int, d: int) -> int:
     return sum(coeff_max(p, N, d, j) * Q ** (j - d) for j in range(d, 2 * d + 1))
 
 
+def word_max(p: int, t: int, d: int) -> int:
+    """Largest packed word (p-1)(1 + Q + ... + Q^d)."""
+    return (p - 1) * sum(1 << (t * j) for j in range(d + 1))
+
+
 def low_max(p: int, t: int, d: int) -> int:
     """Largest low part sum_{j<d} c_j Q^j of ONE product of two chunk words."""
     Q = 1 << t
@@ -93,7 +98,8 @@ def low_max(p: int, t: int, d: int) -> int:
 def exact_ok(p: int, kb: int, t: int, d: int, beta: int) -> bool:
     """Exact regime: eq. (3) and S_max < 2^beta.  Every product and partial sum is an
     integer below 2^beta, so any summation order is exact and the word holds S."""
-    return d >= 0 and t >= 1 and eq3_lower_ok(p, kb, t) and s_max(p, kb, t, d) < (1 << beta)
+    return (d >= 0 and t >= 1 and eq3_lower_ok(p, kb, t) and word_max(p, t, d) < (1 << beta)
+            and s_max(p, kb, t, d) < (1 << beta))
 
 
 def offset_ok(p: int, kb: int, t: int, d: int, beta: int, g: int = 1) -> bool:
@@ -105,8 +111,9 @@ def offset_ok(p: int, kb: int, t: int, d: int, beta: int, g: int = 1) -> bool:
       (iii) g * low_max < Q^d / 2, so each rounding step (g products per step) lands
             on the multiple of Q^d just below.
     The word then holds M + floor(S / Q^d) Q^d, whatever the order of the steps.
+    The packed words themselves must be exact floats: word_max < 2^beta.
     """
-    return (d >= 0 and t >= 1 and eq3_lower_ok(p, kb, t)
+    return (d >= 0 and t >= 1 and eq3_lower_ok(p, kb, t) and word_max(p, t, d) < (1 << beta)
             and high_max(p, kb, t, d) < (1 << (beta - 1))
             and 2 * g * low_max(p, t, d) < (1 << (t * d)))
 
