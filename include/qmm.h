@@ -161,6 +161,27 @@ qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k
                            const void *CA, int64_t ldca, const void *CB, int64_t ldcb,
                            uint8_t *C, int64_t ldc, void *stream);
 
+/* Procedure (5) on an already row-compressed right operand: C = REDQ(A x CBr).
+ * A: m x k residues (converted to words on the fly); CBr: k x ceil(n/(d+1)) words
+ * from qmm_pack_rows_fwd with this plan.  REDQ paths only. */
+qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                                 const uint8_t *A, int64_t lda, const void *CBr, int64_t ldcbr,
+                                 uint8_t *C, int64_t ldc, void *stream);
+
+/* INT8 path, conversion step: Bt[j][l] = centred(B[l][j]) as int8, where
+ * centred(x) = x - p if x > (p-1)/2, else x; Bt is n x ldbt with ldbt a multiple
+ * of 64 and >= k, columns l >= k are zero.  Bt must be 16-byte aligned.
+ * (The int8 matrix cores take both operands contiguous along k.) */
+qmm_status qmm_pack_centred_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B,
+                                 int64_t ldb, int8_t *Bt, int64_t ldbt, void *stream);
+
+/* INT8 path, product step: C = (centred(A) x Bt^T) mod p with int32 accumulation,
+ * k cut into plan->k_block blocks reduced mod p.  A: m x k bytes; Bt from
+ * qmm_pack_centred_cols with the same plan. */
+qmm_status qmm_gemm_centred(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                            const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
+                            uint8_t *C, int64_t ldc, void *stream);
+
 /* ---- batches of independent products --------------------------------------- */
 typedef struct {
     int64_t m, n, k;

@@ -188,3 +188,41 @@ extern "C" qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n
     if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
     return launch_gemm_qadic(*plan, m, n, k, CA, ldca, CB, ldcb, C, ldc, stream);
 }
+
+extern "C" qmm_status qmm_pack_centred_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                            int8_t *Bt, int64_t ldbt, void *stream) {
+    if (!plan || plan->path != QMM_PATH_INT8) return fail(QMM_EINVAL, "an INT8 plan is required");
+    if (plan->p < 2 || plan->p > 256) return fail(QMM_EINVAL, "INT8 needs 2 <= p <= 256");
+    if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad size, pointer or ldb");
+    if (n > 0 && (Bt == nullptr || ldbt % 64 != 0 || ldbt < k || ((uintptr_t)Bt % 16) != 0))
+        return fail(QMM_EINVAL, "Bt: needs a 16-byte aligned pointer and ldbt a multiple of 64, >= k");
+    if (k == 0 && ldbt == 0) return QMM_OK;
+    return launch_centre_transpose(*plan, k, n, B, ldb, Bt, ldbt, stream);
+}
+
+extern "C" qmm_status qmm_gemm_centred(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                                       int64_t lda, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc,
+                                       void *stream) {
+    if (!plan || plan->path != QMM_PATH_INT8) return fail(QMM_EINVAL, "an INT8 plan is required");
+    qmm_status st = qmm_validate_plan(plan, m, n, k);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(m, k, A, lda) || bad_matrix(m, n, C, ldc)) return fail(QMM_EINVAL, "bad pointer or leading dimension");
+    if (n > 0 && k > 0 && (Bt == nullptr || ldbt % 64 != 0 || ldbt < k || ((uintptr_t)Bt % 16) != 0))
+        return fail(QMM_EINVAL, "Bt: needs a 16-byte aligned pointer and ldbt a multiple of 64, >= k");
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
+    return launch_gemm_int8(*plan, m, n, k, A, lda, Bt, ldbt, C, ldc, stream);
+}
+
+extern "C" qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                                            int64_t lda, const void *CBr, int64_t ldcbr, uint8_t *C, int64_t ldc,
+                                            void *stream) {
+    if (!plan || !path_is_redq(plan->path)) return fail(QMM_EINVAL, "a REDQ plan is required");
+    qmm_status st = qmm_validate_plan(plan, m, n, k);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(m, k, A, lda) || bad_matrix(k, words_for(n, plan->d), CBr, ldcbr) || bad_matrix(m, n, C, ldc))
+        return fail(QMM_EINVAL, "bad pointer or leading dimension");
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
+    return launch_gemm_redq(*plan, m, n, k, A, lda, CBr, ldcbr, C, ldc, stream);
+}

@@ -32,7 +32,8 @@ EXPORTS = [
     "qmm_choose_Qd", "qmm_validate_plan", "qmm_pack_rows_rev", "qmm_pack_cols_fwd", "qmm_pack_rows_fwd",
     "qmm_unpack", "qmm_extract", "qmm_redq", "qmm_gemm_workspace_size", "qmm_gemm_mod_p", "qmm_gemm_packed",
     "qmm_batched_create", "qmm_gemm_mod_p_batched", "qmm_batched_plan", "qmm_batched_destroy",
-    "qmm_last_error", "qmm_version",
+    "qmm_last_error", "qmm_version", "qmm_pack_centred_cols", "qmm_gemm_centred",
+    "qmm_gemm_right_packed",
 ]
 
 
@@ -86,6 +87,9 @@ def lib():
             "qmm_gemm_workspace_size": [P, i64, i64, i64, ctypes.POINTER(sz)],
             "qmm_gemm_mod_p": [P, i64, i64, i64, u32, vp, i64, vp, i64, vp, i64, vp, sz, vp],
             "qmm_gemm_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_gemm_right_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_pack_centred_cols": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_gemm_centred": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
             "qmm_batched_create": [i64, ctypes.POINTER(Problem), u32, ctypes.POINTER(vp)],
             "qmm_gemm_mod_p_batched": [vp, vp],
             "qmm_batched_plan": [vp, i64, P],
@@ -266,6 +270,47 @@ def gemm_packed(plan, k, CA, CB, C=None, stream=None):
         C = torch.empty((m, n), dtype=torch.uint8, device=CA.device)
     _check(lib().qmm_gemm_packed(ctypes.byref(plan), m, n, k, _ptr(CA), _ld(CA), _ptr(CB), _ld(CB), _ptr(C), _ld(C),
                                  _stream(stream)), "qmm_gemm_packed")
+    return C
+
+
+def gemm_right_packed(plan, A, CBr, n, C=None, stream=None):
+    """Procedure (5) with B already row-compressed: C = REDQ(A x CBr)."""
+    import torch
+    _u8(A, "A")
+    m, k = A.shape
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+    _check(lib().qmm_gemm_right_packed(ctypes.byref(plan), m, n, k, _ptr(A), _ld(A), _ptr(CBr), _ld(CBr), _ptr(C),
+                                       _ld(C), _stream(stream)), "qmm_gemm_right_packed")
+    return C
+
+
+def centred_ld(k) -> int:
+    """Leading dimension of the centred, transposed right operand: k rounded up to 64."""
+    return max(1, -(-k // 64)) * 64
+
+
+def pack_centred_cols(plan, B, Bt=None, stream=None):
+    """INT8 conversion step: Bt = centred(B)^T (n x centred_ld(k), int8)."""
+    import torch
+    _u8(B, "B")
+    k, n = B.shape
+    if Bt is None:
+        Bt = torch.empty((n, centred_ld(k)), dtype=torch.int8, device=B.device)
+    _check(lib().qmm_pack_centred_cols(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(Bt), _ld(Bt), _stream(stream)),
+           "qmm_pack_centred_cols")
+    return Bt
+
+
+def gemm_centred(plan, A, Bt, n, C=None, stream=None):
+    """INT8 product step: C = centred(A) x Bt^T mod p."""
+    import torch
+    _u8(A, "A")
+    m, k = A.shape
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+    _check(lib().qmm_gemm_centred(ctypes.byref(plan), m, n, k, _ptr(A), _ld(A), _ptr(Bt), _ld(Bt), _ptr(C), _ld(C),
+                                  _stream(stream)), "qmm_gemm_centred")
     return C
 
 
