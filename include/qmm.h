@@ -82,7 +82,8 @@ typedef struct {
     uint32_t path;     /* qmm_path; never QMM_PATH_AUTO in a returned plan */
     uint32_t regime;   /* qmm_regime */
     uint32_t g;        /* products per rounding assumed by the offset regime (1 or 4) */
-    uint32_t tile;     /* kernel tile variant (0 = default) */
+    uint32_t tile;     /* kernel tile variant: 0 = chosen from the shape; INT8: 1 = 128 x 128,
+                          2 = 256 x 256 output tiles */
 } qmm_plan;
 
 /* Choose (Q = 2^t, d, k_block, path) for a product of shape m x k times k x n
@@ -170,7 +171,7 @@ qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int64_t n, int
 
 /* INT8 path, conversion step: Bt[j][l] = centred(B[l][j]) as int8, where
  * centred(x) = x - p if x > (p-1)/2, else x; Bt is n x ldbt with ldbt a multiple
- * of 64 and >= k, columns l >= k are zero.  Bt must be 16-byte aligned.
+ * of 128 and >= k, columns l >= k are zero.  Bt must be 16-byte aligned.
  * (The int8 matrix cores take both operands contiguous along k.) */
 qmm_status qmm_pack_centred_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B,
                                  int64_t ldb, int8_t *Bt, int64_t ldbt, void *stream);
@@ -197,15 +198,34 @@ typedef struct qmm_batched qmm_batched;
  * descriptor table and tile list, and records one launch of the persistent kernel
  * in a HIP graph.  probs is a host array; the device buffers it names must stay
  * valid until qmm_batched_destroy.  The batch owns the device memory it allocates.
- * flags: 0, or QMM_BATCH_FORCE_FP64 (every product on the FP64 Q-adic tile path). */
-#define QMM_BATCH_FORCE_FP64 1u
+ * flags: QMM_BATCH_FORCE_FP64 puts every product on the FP64 Q-adic tile path (the
+ * paper's method, unblocked plans); QMM_BATCH_SHAPE_* fixes the INT8 output tile
+ * instead of letting the autotuner pick it per product.  Products whose k would
+ * need blocked int32 accumulation are refused (QMM_EUNSUPPORTED). */
+#define QMM_BATCH_FORCE_FP64   1u
+#define QMM_BATCH_SHAPE_64x64  0x100u
+#define QMM_BATCH_SHAPE_32x128 0x200u
+#define QMM_BATCH_SHAPE_128x32 0x300u
+#define QMM_BATCH_SHAPE_MASK   0x300u
 qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t flags,
                               qmm_batched **out);
 
 /* Replays the recorded launch on `stream`: every product of the batch. */
 qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream);
 
-/* Plan chosen for product i of the batch (host copy). */
+/* Autotuner calibration: times the persistent kernel on synthetic batches of each
+ * INT8 tile shape (allocating and freeing its own device buffers, synchronising
+ * `stream`) and fits per-tile cost = fixed + per_stage * (k / 64).  Later
+ * qmm_batched_create calls use the fit.  costs (may be NULL) receives 6 doubles:
+ * (fixed, per_stage) for 64x64, 32x128 and 128x32, in units of one 64-byte stage
+ * of a 64x64 tile. */
+qmm_status qmm_batched_tune(void *stream, double *costs);
+
+/* Installs previously measured costs (6 doubles, as qmm_batched_tune returns). */
+qmm_status qmm_batched_set_costs(const double *costs);
+
+/* Plan chosen for product i of the batch (host copy); plan->tile holds the INT8
+ * tile shape (0 = 64x64, 1 = 32x128, 2 = 128x32). */
 qmm_status qmm_batched_plan(const qmm_batched *batch, int64_t i, qmm_plan *out);
 
 /* Frees the batch's device memory and graph.  NULL is accepted. */

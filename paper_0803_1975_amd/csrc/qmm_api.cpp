@@ -194,9 +194,8 @@ extern "C" qmm_status qmm_pack_centred_cols(const qmm_plan *plan, int64_t k, int
     if (!plan || plan->path != QMM_PATH_INT8) return fail(QMM_EINVAL, "an INT8 plan is required");
     if (plan->p < 2 || plan->p > 256) return fail(QMM_EINVAL, "INT8 needs 2 <= p <= 256");
     if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad size, pointer or ldb");
-    if (n > 0 && (Bt == nullptr || ldbt % 64 != 0 || ldbt < k || ((uintptr_t)Bt % 16) != 0))
-        return fail(QMM_EINVAL, "Bt: needs a 16-byte aligned pointer and ldbt a multiple of 64, >= k");
-    if (k == 0 && ldbt == 0) return QMM_OK;
+    if (n > 0 && (Bt == nullptr || ldbt % 128 != 0 || ldbt < k || ((uintptr_t)Bt % 16) != 0))
+        return fail(QMM_EINVAL, "Bt: needs a 16-byte aligned pointer and ldbt a multiple of 128, >= k");
     return launch_centre_transpose(*plan, k, n, B, ldb, Bt, ldbt, stream);
 }
 
@@ -207,8 +206,8 @@ extern "C" qmm_status qmm_gemm_centred(const qmm_plan *plan, int64_t m, int64_t 
     qmm_status st = qmm_validate_plan(plan, m, n, k);
     if (st != QMM_OK) return st;
     if (bad_matrix(m, k, A, lda) || bad_matrix(m, n, C, ldc)) return fail(QMM_EINVAL, "bad pointer or leading dimension");
-    if (n > 0 && k > 0 && (Bt == nullptr || ldbt % 64 != 0 || ldbt < k || ((uintptr_t)Bt % 16) != 0))
-        return fail(QMM_EINVAL, "Bt: needs a 16-byte aligned pointer and ldbt a multiple of 64, >= k");
+    if (n > 0 && k > 0 && (Bt == nullptr || ldbt % 128 != 0 || ldbt < k || ((uintptr_t)Bt % 16) != 0))
+        return fail(QMM_EINVAL, "Bt: needs a 16-byte aligned pointer and ldbt a multiple of 128, >= k");
     if (m == 0 || n == 0) return QMM_OK;
     if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
     return launch_gemm_int8(*plan, m, n, k, A, lda, Bt, ldbt, C, ldc, stream);

@@ -1,28 +1,608 @@
-// Batches of independent products (placeholder until the persistent kernel lands).
+// Batches of independent products C_i = A_i x B_i mod p_i in ONE persistent launch.
+//
+// Host side (qmm_batched_create):
+//   - plans every product: INT8 on centred residues whenever p_i <= 256 (the fast
+//     path on these matrix cores), or the FP64 Q-adic product when the batch is
+//     forced onto it (QMM_BATCH_FORCE_FP64, the paper's method as a baseline);
+//   - the autotuner picks the output tile shape per product (see tune_shape);
+//   - one descriptor per product and one entry per output tile go to device
+//     memory once; tiles are sorted longest first and dealt round-robin to the
+//     persistent workgroups (a static longest-processing-time schedule: no
+//     atomics, no counters to reset between replays);
+//   - the launch is recorded in a HIP graph; qmm_gemm_mod_p_batched replays it.
+//
+// Device side: each workgroup (256 threads, 4 wavefronts) walks its tiles.  A
+// tile loads its A rows and B columns straight from the byte matrices (any
+// leading dimension, any alignment), converts them on the way into LDS
+// (centring for INT8; Q-adic packing of rows reversed / columns forward for
+// FP64) and runs the matching MFMA loop, then reduces and stores its outputs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qmm_device.h"
 #include "qmm_internal.h"
+
+namespace qmm {
+namespace {
+
+typedef int ix4 __attribute__((ext_vector_type(4)));
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;
+constexpr int KB = 64;          // INT8 K stage (bytes)
+constexpr int PITCH = KB + 16;  // LDS row pitch of INT8 stages
+constexpr int KW = 16;          // FP64 K stage (packed words)
+
+// Tile shapes of the batched kernel (rows x columns of C per tile).
+enum Shape : uint32_t { SHAPE_64x64 = 0, SHAPE_32x128 = 1, SHAPE_128x32 = 2, SHAPE_COUNT = 3 };
+constexpr int shape_bm(uint32_t s) { return s == SHAPE_32x128 ? 32 : (s == SHAPE_128x32 ? 128 : 64); }
+constexpr int shape_bn(uint32_t s) { return s == SHAPE_32x128 ? 128 : (s == SHAPE_128x32 ? 32 : 64); }
+
+struct Desc {
+    const uint8_t *A;
+    const uint8_t *B;
+    uint8_t *C;
+    int64_t lda, ldb, ldc;
+    int32_t m, n, k;
+    uint32_t p;
+    uint32_t path;    // QMM_PATH_INT8 or QMM_PATH_FP64_QADIC
+    uint32_t shape;   // Shape (INT8); FP64 tiles are 64 x 64
+    uint32_t add_h, neg_p, off;
+    uint64_t magic;
+    // FP64 Q-adic
+    uint32_t t, d, offset_regime;
+    double start, invp;
+    int32_t a_vec;    // A rows 16-byte aligned
+};
+
+struct TileRef {
+    int32_t desc;
+    int32_t tm, tn;
+    int32_t pad;
+};
+
+__device__ __forceinline__ uint32_t centre4(uint32_t w, uint32_t add_h, uint32_t neg_p) {
+    const uint32_t flag = ((w + add_h) >> 7) & 0x01010101u;
+    return w + flag * neg_p;
+}
+
+// 16 bytes of a byte matrix starting at src, any alignment, zero past `valid`
+// bytes.  When all 16 are valid and the dword-aligned 20-byte window around them
+// lies inside the matrix's data [lo, hi), the bytes come from five dword loads
+// and byte-aligning shifts; otherwise from single byte loads.
+typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ uint4 load16(const uint8_t *src, int valid, const uint8_t *lo, const uint8_t *hi) {
+    if (valid >= 16) {
+        const uintptr_t a = (uintptr_t)src;
+        const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
+        if (base >= lo && base + 20 <= hi) {
+            const u32x4a4 v = *(const u32x4a4 *)base;
+            const uint32_t w4 = *(const uint32_t *)(base + 16);
+            const uint32_t sh = (uint32_t)(a & 3);
+            if (sh == 0) return make_uint4(v.x, v.y, v.z, v.w);
+            return make_uint4(__builtin_amdgcn_alignbyte(v.y, v.x, sh), __builtin_amdgcn_alignbyte(v.z, v.y, sh),
+                              __builtin_amdgcn_alignbyte(v.w, v.z, sh), __builtin_amdgcn_alignbyte(w4, v.w, sh));
+        }
+    }
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int b = 0; b < 16; ++b)
+        if (b < valid) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// 4 bytes at src, same rules with an 8-byte window.
+__device__ __forceinline__ uint32_t load4(const uint8_t *src, int valid, const uint8_t *lo, const uint8_t *hi) {
+    if (valid >= 4) {
+        const uintptr_t a = (uintptr_t)src;
+        const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
+        if (base >= lo && base + 8 <= hi) {
+            const uint32_t w0 = *(const uint32_t *)base, w1 = *(const uint32_t *)(base + 4);
+            return __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(a & 3));
+        }
+    }
+    uint32_t v = 0;
+    for (int b = 0; b < 4; ++b)
+        if (b < valid) v |= (uint32_t)src[b] << (8 * b);
+    return v;
+}
+
+// One INT8 tile of BM x BN outputs: wavefronts laid out WGM x WGN, each owning
+// (BM/WGM) x (BN/WGN) outputs in 16 x 16 MFMA blocks.  Stages of 64 k-bytes go
+// through two LDS buffers: the loads of stage s+1 are issued before the MFMAs of
+// stage s and stored after them, one barrier per stage.
+template <int BM, int BN, int WGM, int WGN>
+__device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
+    constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 16, FN = WTN / 16;
+    constexpr int A_SEGS = BM * (KB / 16);   // 16-byte A segments per stage
+    constexpr int B_GRPS = BN * KB / 16;     // 4 x 4-byte B groups per stage
+    constexpr int A_PER = (A_SEGS + NT - 1) / NT, B_PER = (B_GRPS + NT - 1) / NT;
+    constexpr int STAGE = 128 * PITCH * 2;   // bytes of one A + B buffer pair
+    static_assert(WGM * WGN == 4, "four wavefronts");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+    const uint8_t *a_lo = D.A, *a_hi = D.A + (D.m > 0 && D.k > 0 ? (int64_t)(D.m - 1) * D.lda + D.k : 0);
+    const uint8_t *b_lo = D.B, *b_hi = D.B + (D.k > 0 && D.n > 0 ? (int64_t)(D.k - 1) * D.ldb + D.n : 0);
+    ix4 acc[FM][FN];
+#pragma unroll
+    for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix4{0, 0, 0, 0};
+
+    uint4 ra[A_PER];
+    uint32_t rb[B_PER][4];
+    auto load_stage = [&](int st) {
+        const int k0 = st * KB;
+#pragma unroll
+        for (int i = 0; i < A_PER; ++i) {
+            const int c = tid + NT * i;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (c < A_SEGS) {
+                const int r = c >> 2, s = c & 3;
+                const int64_t row = row0 + r;
+                const int kk = k0 + 16 * s;
+                if (row < D.m && kk < D.k) v = load16(D.A + row * D.lda + kk, D.k - kk, a_lo, a_hi);
+            }
+            v.x = centre4(v.x, D.add_h, D.neg_p);
+            v.y = centre4(v.y, D.add_h, D.neg_p);
+            v.z = centre4(v.z, D.add_h, D.neg_p);
+            v.w = centre4(v.w, D.add_h, D.neg_p);
+            ra[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER; ++i) {
+            const int c = tid + NT * i;
+            const int cq = c % (BN / 4), kq = c / (BN / 4);
+            const int64_t col = col0 + 4 * cq;
+            const int cvalid = (int)(D.n - col);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int kk = k0 + 4 * kq + j;
+                rb[i][j] = (c < B_GRPS && kk < D.k && cvalid > 0) ? load4(D.B + (int64_t)kk * D.ldb + col, cvalid, b_lo, b_hi) : 0u;
+            }
+        }
+    };
+    auto store_stage = [&](int buf) {
+        uint8_t *sA = lds + buf * STAGE, *sB = sA + 128 * PITCH;
+#pragma unroll
+        for (int i = 0; i < A_PER; ++i) {
+            const int c = tid + NT * i;
+            if (c < A_SEGS) *(uint4 *)&sA[(c >> 2) * PITCH + 16 * (c & 3)] = ra[i];
+        }
+        // B: a 4 (k) x 4 (columns) byte group, transposed in registers so that each
+        // column's four k-bytes form one dword of the k-contiguous LDS row.
+#pragma unroll
+        for (int i = 0; i < B_PER; ++i) {
+            const int c = tid + NT * i;
+            if (c >= B_GRPS) continue;
+            const int cq = c % (BN / 4), kq = c / (BN / 4);
+            const uint32_t *rw = rb[i];
+            // column b gathers byte b of rw[0..3]
+            const uint32_t lo01 = __builtin_amdgcn_perm(rw[1], rw[0], 0x05010400u);  // r0b0 r1b0 r0b1 r1b1
+            const uint32_t lo23 = __builtin_amdgcn_perm(rw[3], rw[2], 0x05010400u);
+            const uint32_t hi01 = __builtin_amdgcn_perm(rw[1], rw[0], 0x07030602u);  // r0b2 r1b2 r0b3 r1b3
+            const uint32_t hi23 = __builtin_amdgcn_perm(rw[3], rw[2], 0x07030602u);
+            uint32_t col[4];
+            col[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+            col[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+            col[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+            col[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                *(uint32_t *)&sB[(4 * cq + b) * PITCH + 4 * kq] = centre4(col[b], D.add_h, D.neg_p);
+        }
+    };
+
+    const int nst = (D.k + KB - 1) / KB;
+    if (nst > 0) {
+        load_stage(0);
+        store_stage(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) load_stage(st + 1);
+        const uint8_t *sA = lds + buf * STAGE, *sB = sA + 128 * PITCH;
+        ix4 bf[FN];
+#pragma unroll
+        for (int ni = 0; ni < FN; ++ni)
+            bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
+#pragma unroll
+        for (int mi = 0; mi < FM; ++mi) {
+            const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
+#pragma unroll
+            for (int ni = 0; ni < FN; ++ni)
+                acc[mi][ni] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+        }
+        if (st + 1 < nst) store_stage(buf ^ 1);
+        __syncthreads();
+    }
+    // lane l, register r holds D[4 (l >> 4) + r][l & 15]
+#pragma unroll
+    for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < FN; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + wm * WTM + mi * 16 + 4 * (lane >> 4) + r;
+                const int64_t col = col0 + wn * WTN + ni * 16 + (lane & 15);
+                if (row < D.m && col < D.n)
+                    D.C[row * D.ldc + col] = (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
+            }
+}
+
+// One FP64 Q-adic tile of 64 x 64 outputs: rows of A packed reversed and columns
+// of B packed forward straight from the bytes (Horner over the d+1 residues of a
+// chunk), 16 words per stage, MFMA f64 16x16x4, digit d of every word mod p.
+__device__ void fp64_tile(const Desc &D, int tm, int tn, double *sA, double *sB) {
+    // sA: 64 rows x (KW + 1) words; sB: KW rows x 64 words
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t row0 = (int64_t)tm * 64, col0 = (int64_t)tn * 64;
+    const uint32_t e = D.d + 1;
+    const int nw = (int)((D.k + e - 1) / e);
+    dx4 acc[2][2];
+    const double start = D.start;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = dx4{start, start, start, start};
+    const int nst = (nw + KW - 1) / KW;
+    for (int st = 0; st < nst; ++st) {
+        const int l0 = st * KW;
+        // 64 x 16 A words and 16 x 64 B words: four of each per thread
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = tid + NT * i;
+            {   // A word (row r, word l)
+                const int r = c >> 4, l = l0 + (c & 15);
+                const int64_t row = row0 + r;
+                uint64_t w = 0;
+                if (row < D.m && l < nw) {
+                    const uint8_t *a = D.A + row * D.lda;
+                    for (uint32_t s = 0; s < e; ++s) {
+                        const int64_t kk = (int64_t)l * e + s;
+                        w = (w << D.t) | (kk < D.k ? (uint64_t)a[kk] : 0ull);
+                    }
+                }
+                sA[r * (KW + 1) + (c & 15)] = (double)w;
+            }
+            {   // B word (word l, column j)
+                const int lr = c >> 6, j = c & 63;
+                const int l = l0 + lr;
+                const int64_t col = col0 + j;
+                uint64_t w = 0;
+                if (col < D.n && l < nw) {
+                    for (int32_t s = (int32_t)e - 1; s >= 0; --s) {
+                        const int64_t kk = (int64_t)l * e + s;
+                        w = (w << D.t) | (kk < D.k ? (uint64_t)D.B[kk * D.ldb + col] : 0ull);
+                    }
+                }
+                sB[lr * 64 + j] = (double)w;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KW / 4; ++ks) {
+            double af[2], bf[2];
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi) af[mi] = sA[(wm * 32 + mi * 16 + (lane & 15)) * (KW + 1) + ks * 4 + (lane >> 4)];
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) bf[ni] = sB[(ks * 4 + (lane >> 4)) * 64 + wn * 32 + ni * 16 + (lane & 15)];
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const uint32_t td = D.t * D.d;
+    const uint64_t qmask = (1ull << D.t) - 1;
+    const bool offset = D.offset_regime != 0;
+    // lane l, register r holds D[(l >> 4) + 4 r][l & 15]
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + wm * 32 + mi * 16 + (lane >> 4) + 4 * r;
+                const int64_t col = col0 + wn * 32 + ni * 16 + (lane & 15);
+                if (row < D.m && col < D.n)
+                    D.C[row * D.ldc + col] = (uint8_t)mod_u64(qadic_digit<double>(acc[mi][ni][r], offset, td, qmask), D.p, D.invp);
+            }
+}
+
+constexpr int kLdsInt8 = 2 * 2 * 128 * PITCH;                              // two A + B stages, largest shape
+constexpr int kLdsFp64 = (64 * (KW + 1) + KW * 64) * (int)sizeof(double);
+constexpr int kLdsBytes = kLdsInt8 > kLdsFp64 ? kLdsInt8 : kLdsFp64;
+
+__global__ __launch_bounds__(NT, 2) void batched_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles,
+                                                         int32_t ntiles) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
+        const TileRef tr = tiles[i];
+        const Desc D = descs[tr.desc];
+        if (D.path == QMM_PATH_FP64_QADIC) {
+            fp64_tile(D, tr.tm, tr.tn, (double *)lds, (double *)lds + 64 * (KW + 1));
+        } else if (D.shape == SHAPE_32x128) {
+            int8_tile<32, 128, 1, 4>(D, tr.tm, tr.tn, lds);
+        } else if (D.shape == SHAPE_128x32) {
+            int8_tile<128, 32, 4, 1>(D, tr.tm, tr.tn, lds);
+        } else {
+            int8_tile<64, 64, 2, 2>(D, tr.tm, tr.tn, lds);
+        }
+    }
+}
+
+// Autotuner cost model of one INT8 tile: a fixed part (tile set-up, epilogue) and a
+// part per 64-byte K stage, in units of one K stage of the 64 x 64 shape.  Every
+// shape does the same MFMA work per stage (four 16x16x64 blocks per wavefront);
+// the defaults are the analytic prior and qmm_batched_tune replaces them with a
+// fit to timed launches of each shape.
+struct ShapeCost {
+    double fixed, per_stage;
+};
+ShapeCost g_costs[SHAPE_COUNT] = {{2.0, 1.0}, {2.0, 1.1}, {2.0, 1.1}};
+
+double tile_cost(uint32_t shape, int64_t m, int64_t n, int64_t k) {
+    const int64_t tiles = ceil_div(m, shape_bm(shape)) * ceil_div(n, shape_bn(shape));
+    return (double)tiles * (g_costs[shape].fixed + g_costs[shape].per_stage * (double)ceil_div(k, KB));
+}
+
+uint32_t tune_shape(int64_t m, int64_t n, int64_t k) {
+    uint32_t best = SHAPE_64x64;
+    double bc = tile_cost(SHAPE_64x64, m, n, k);
+    for (uint32_t s = 1; s < SHAPE_COUNT; ++s) {
+        const double c = tile_cost(s, m, n, k);
+        if (c < bc) {
+            bc = c;
+            best = s;
+        }
+    }
+    return best;
+}
+
+qmm_status hip_fail(hipError_t e, const char *what) {
+    return fail(QMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+}  // namespace qmm
 
 using namespace qmm;
 
 struct qmm_batched {
-    int64_t count;
+    int64_t count = 0;
+    std::vector<qmm_plan> plans;
+    Desc *d_desc = nullptr;
+    TileRef *d_tiles = nullptr;
+    int32_t ntiles = 0;
+    int grid = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
+namespace {
+
+void release(qmm_batched *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    delete b;
+}
+
+qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, qmm_batched *b) {
+    b->count = count;
+    b->plans.resize((size_t)count);
+    std::vector<Desc> descs((size_t)count);
+    std::vector<std::pair<double, TileRef>> tiles;
+    for (int64_t i = 0; i < count; ++i) {
+        const qmm_problem &P = probs[i];
+        if (P.p < 2 || P.p > 256) return fail(QMM_EINVAL, "problem " + std::to_string(i) + ": byte residues need 2 <= p <= 256");
+        if (P.m < 0 || P.n < 0 || P.k < 0 || P.m > INT32_MAX / 2 || P.n > INT32_MAX / 2 || P.k > INT32_MAX / 2)
+            return fail(QMM_EINVAL, "problem " + std::to_string(i) + ": bad size");
+        if ((P.m && P.k && (!P.A || P.lda < P.k)) || (P.k && P.n && (!P.B || P.ldb < P.n)) ||
+            (P.m && P.n && (!P.C || P.ldc < P.n)))
+            return fail(QMM_EINVAL, "problem " + std::to_string(i) + ": bad pointer or leading dimension");
+        qmm_plan pl;
+        qmm_status st;
+        if (flags & QMM_BATCH_FORCE_FP64)
+            st = qmm_choose_Qd(P.p, P.m, P.n, P.k, 53, QMM_PATH_FP64_QADIC, QMM_PLAN_UNBLOCKED, &pl);
+        else
+            st = qmm_choose_Qd(P.p, P.m, P.n, P.k, 0, QMM_PATH_INT8, 0, &pl);
+        if (st != QMM_OK) return st;
+        if (pl.path == QMM_PATH_INT8 && pl.k_block < P.k)
+            return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": k needs blocked int32 accumulation, "
+                                          "which the batched kernel does not do");
+        Desc &D = descs[(size_t)i];
+        std::memset(&D, 0, sizeof(D));
+        D.A = P.A;
+        D.B = P.B;
+        D.C = P.C;
+        D.lda = P.lda;
+        D.ldb = P.ldb;
+        D.ldc = P.ldc;
+        D.m = (int32_t)P.m;
+        D.n = (int32_t)P.n;
+        D.k = (int32_t)P.k;
+        D.p = P.p;
+        D.path = pl.path;
+        D.magic = mod_magic(P.p);
+        D.off = P.p * ((1u << 31) / P.p);
+        D.invp = 1.0 / (double)P.p;
+        D.a_vec = ((uintptr_t)P.A % 16 == 0) && (P.lda % 16 == 0);
+        int bm = 64, bn = 64;
+        if (pl.path == QMM_PATH_INT8) {
+            const uint32_t h = (P.p - 1) / 2;
+            D.add_h = (127u - h) * 0x01010101u;
+            D.neg_p = (256u - P.p) & 0xffu;
+            const uint32_t forced = (flags & QMM_BATCH_SHAPE_MASK) >> 8;
+            D.shape = forced ? forced - 1 : tune_shape(P.m, P.n, P.k);
+            pl.tile = D.shape;
+            bm = shape_bm(D.shape);
+            bn = shape_bn(D.shape);
+        } else {
+            D.t = pl.t;
+            D.d = pl.d;
+            D.offset_regime = pl.regime == QMM_REGIME_OFFSET;
+            D.start = D.offset_regime ? std::ldexp(1.0, 52 + (int)(pl.t * pl.d)) : 0.0;
+        }
+        b->plans[(size_t)i] = pl;
+        if (P.m == 0 || P.n == 0) continue;
+        const int32_t tmax = (int32_t)ceil_div(P.m, bm), nmax = (int32_t)ceil_div(P.n, bn);
+        const double cost = pl.path == QMM_PATH_INT8 ? tile_cost(D.shape, bm, bn, P.k)
+                                                     : (double)ceil_div(words_for(P.k < 1 ? 1 : P.k, pl.d), KW) * 4.0;
+        for (int32_t tm = 0; tm < tmax; ++tm)
+            for (int32_t tn = 0; tn < nmax; ++tn) tiles.push_back({cost, TileRef{(int32_t)i, tm, tn, 0}});
+    }
+    // longest first, ties by product and position so the order is deterministic
+    std::stable_sort(tiles.begin(), tiles.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::vector<TileRef> flat(tiles.size());
+    for (size_t i = 0; i < tiles.size(); ++i) flat[i] = tiles[i].second;
+    b->ntiles = (int32_t)flat.size();
+
+    hipError_t e;
+    if ((e = hipMalloc(&b->d_desc, sizeof(Desc) * std::max<size_t>(1, descs.size()))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&b->d_tiles, sizeof(TileRef) * std::max<size_t>(1, flat.size()))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if (!descs.empty() && (e = hipMemcpy(b->d_desc, descs.data(), sizeof(Desc) * descs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy");
+    if (!flat.empty() && (e = hipMemcpy(b->d_tiles, flat.data(), sizeof(TileRef) * flat.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy");
+
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return hip_fail(e, "attribute");
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel, NT, 0)) != hipSuccess)
+        return hip_fail(e, "occupancy");
+    b->grid = std::max(1, std::min<int>(b->ntiles, cus * std::max(1, per_cu)));
+
+    // Record the launch in a graph.  The graph holds only the kernel node: the
+    // schedule is static, so there is nothing to clear between replays.
+    if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e, "capture");
+    if (b->ntiles > 0) batched_kernel<<<b->grid, NT, 0, b->capture_stream>>>(b->d_desc, b->d_tiles, b->ntiles);
+    const hipError_t le = hipGetLastError();
+    if ((e = hipStreamEndCapture(b->capture_stream, &b->graph)) != hipSuccess) return hip_fail(e, "end capture");
+    if (le != hipSuccess) return hip_fail(le, "batched launch");
+    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
+    return QMM_OK;
+}
+
+}  // namespace
+
 extern "C" qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t flags, qmm_batched **out) {
-    (void)count; (void)probs; (void)flags;
-    if (out) *out = nullptr;
-    return fail(QMM_EUNSUPPORTED, "batched products are not built yet");
+    if (!out) return fail(QMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 0 || (count > 0 && !probs)) return fail(QMM_EINVAL, "bad problem array");
+    if (flags & ~(QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK)) return fail(QMM_EINVAL, "unknown flags");
+    qmm_batched *b = new qmm_batched();
+    const qmm_status st = build_batch(count, probs, flags, b);
+    if (st != QMM_OK) {
+        release(b);
+        return st;
+    }
+    *out = b;
+    return QMM_OK;
 }
+
 extern "C" qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream) {
-    (void)batch; (void)stream;
-    return fail(QMM_EUNSUPPORTED, "batched products are not built yet");
+    if (!batch) return fail(QMM_EINVAL, "batch is NULL");
+    if (batch->ntiles == 0) return QMM_OK;
+    const hipError_t e = hipGraphLaunch(batch->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return QMM_OK;
 }
+
+extern "C" qmm_status qmm_batched_tune(void *stream, double *costs) {
+    // Times the persistent kernel on two synthetic batches per tile shape (a short
+    // and a long k) and fits cost = fixed + per_stage * stages per tile, in units of
+    // one 64-byte stage of the 64 x 64 shape.
+    const int64_t mm = 256, nn = 256, reps = 10;
+    const int64_t ks[2] = {128, 1024};
+    const int count = 256;
+    hipError_t e;
+    uint8_t *buf = nullptr;
+    const size_t abytes = (size_t)mm * 1024, bbytes = (size_t)1024 * nn, cbytes = (size_t)mm * nn;
+    if ((e = hipMalloc(&buf, abytes + bbytes + cbytes * count)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMemsetAsync(buf, 1, abytes + bbytes, (hipStream_t)stream)) != hipSuccess) {
+        (void)hipFree(buf);
+        return hip_fail(e, "hipMemsetAsync");
+    }
+    double ms[SHAPE_COUNT][2];
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    qmm_status st = QMM_OK;
+    for (uint32_t sh = 0; sh < SHAPE_COUNT && st == QMM_OK; ++sh) {
+        for (int ki = 0; ki < 2 && st == QMM_OK; ++ki) {
+            std::vector<qmm_problem> probs((size_t)count);
+            for (int i = 0; i < count; ++i)
+                probs[(size_t)i] = qmm_problem{mm, nn, ks[ki], 7, buf, 1024, buf + abytes, nn,
+                                               buf + abytes + bbytes + (size_t)i * cbytes, nn};
+            qmm_batched *b = nullptr;
+            st = qmm_batched_create(count, probs.data(), (sh + 1) << 8, &b);
+            if (st != QMM_OK) break;
+            (void)qmm_gemm_mod_p_batched(b, stream);
+            (void)hipEventRecord(e0, (hipStream_t)stream);
+            for (int r = 0; r < reps; ++r) (void)qmm_gemm_mod_p_batched(b, stream);
+            (void)hipEventRecord(e1, (hipStream_t)stream);
+            (void)hipEventSynchronize(e1);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            const double tiles = (double)(ceil_div(mm, shape_bm(sh)) * ceil_div(nn, shape_bn(sh)) * count);
+            ms[sh][ki] = (double)t / reps / tiles;  // per tile
+            qmm_batched_destroy(b);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    if (st != QMM_OK) return st;
+    // per-tile time = fixed + per_stage * stages; unit: one stage of the 64 x 64 shape
+    const double s0 = (double)ceil_div(ks[0], KB), s1 = (double)ceil_div(ks[1], KB);
+    const double unit = (ms[0][1] - ms[0][0]) / (s1 - s0);
+    if (!(unit > 0)) return fail(QMM_EDEVICE, "tuning runs gave no usable timing");
+    for (uint32_t sh = 0; sh < SHAPE_COUNT; ++sh) {
+        const double per = (ms[sh][1] - ms[sh][0]) / (s1 - s0) / unit;
+        const double fixed = ms[sh][0] / unit - per * s0;
+        g_costs[sh].per_stage = per > 0.05 ? per : 0.05;
+        g_costs[sh].fixed = fixed > 0 ? fixed : 0;
+        if (costs) {
+            costs[2 * sh] = g_costs[sh].fixed;
+            costs[2 * sh + 1] = g_costs[sh].per_stage;
+        }
+    }
+    return QMM_OK;
+}
+
+extern "C" qmm_status qmm_batched_set_costs(const double *costs) {
+    if (!costs) return fail(QMM_EINVAL, "costs is NULL");
+    for (uint32_t sh = 0; sh < SHAPE_COUNT; ++sh) {
+        if (!(costs[2 * sh] >= 0) || !(costs[2 * sh + 1] > 0)) return fail(QMM_EINVAL, "costs must be positive");
+    }
+    for (uint32_t sh = 0; sh < SHAPE_COUNT; ++sh) g_costs[sh] = ShapeCost{costs[2 * sh], costs[2 * sh + 1]};
+    return QMM_OK;
+}
+
 extern "C" qmm_status qmm_batched_plan(const qmm_batched *batch, int64_t i, qmm_plan *out) {
-    (void)batch; (void)i; (void)out;
-    return fail(QMM_EUNSUPPORTED, "batched products are not built yet");
+    if (!batch || !out) return fail(QMM_EINVAL, "NULL argument");
+    if (i < 0 || i >= batch->count) return fail(QMM_EINVAL, "index out of range");
+    *out = batch->plans[(size_t)i];
+    return QMM_OK;
 }
+
 extern "C" qmm_status qmm_batched_destroy(qmm_batched *batch) {
-    delete batch;
+    release(batch);
     return QMM_OK;
 }

@@ -26,6 +26,23 @@ __device__ __forceinline__ uint64_t div_u64(uint64_t x, uint32_t p, double invp)
     return q;
 }
 
+// u mod p for any 32-bit u and 2 <= p < 2^32, with magic = 2^64/p + e, 0 <= e <= 1
+// (mod_magic).  Then u/p <= u * magic / 2^64 < u/p + 2^-32, which never reaches the
+// next integer since the fractional part of u/p is at most 1 - 1/p: the high word
+// is floor(u/p) exactly.
+__device__ __forceinline__ uint32_t mod_u32(uint32_t u, uint32_t p, uint64_t magic) {
+    const uint64_t lo = (uint64_t)u * (uint32_t)magic;
+    const uint64_t hi = (uint64_t)u * (uint32_t)(magic >> 32);
+    const uint32_t q = (uint32_t)((hi + (lo >> 32)) >> 32);
+    return u - q * p;
+}
+
+// x mod p for a signed 32-bit x with |x| <= 2^31 - p: off = p floor(2^31 / p) is a
+// multiple of p that makes x + off land in [1, 2^32).
+__device__ __forceinline__ uint32_t mod_i32_magic(int32_t x, uint32_t p, uint64_t magic, uint32_t off) {
+    return mod_u32((uint32_t)x + off, p, magic);
+}
+
 // x mod p in [0, p) for a signed 32-bit x.
 __device__ __forceinline__ uint32_t mod_i32(int32_t x, uint32_t p, double invp) {
     const double q = floor((double)x * invp);

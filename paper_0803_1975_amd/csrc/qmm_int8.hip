@@ -5,13 +5,18 @@
 // int32 while k (p/2)^2 < 2^31 (longer k is cut into blocks reduced mod p).
 //
 //   centre_transpose  B (k x n bytes) -> Bt (n x ldbt int8, k contiguous, zero
-//                     padded to a multiple of 64): the int8 MFMA wants both
+//                     padded to a multiple of 128): the int8 MFMA wants both
 //                     operands contiguous along k.  HBM-bound, 64 x 64 tiles
 //                     through LDS so reads and writes are both row-contiguous.
 //   gemm_int8         C = (A_centred x Bt^T) mod p.  A is centred in registers on
-//                     its way into LDS, four residues per 32-bit word.  128 x 128
-//                     tile per 256-thread workgroup, 2 x 2 wavefronts of 64 x 64,
-//                     MFMA i32_16x16x64_i8, K stage of 64 bytes, double-buffered.
+//                     its way into LDS, four residues per 32-bit word.  MFMA
+//                     i32_16x16x64_i8, 256-thread workgroups of 2 x 2 wavefronts,
+//                     double-buffered LDS stages.  Two tile shapes: 256 x 256 with
+//                     512 threads (2 x 4 wavefronts of 128 x 64) and 128-byte K
+//                     stages (one workgroup per CU, 144 KB of LDS; each row of a
+//                     stage is one 128-byte line) for products that fill the chip;
+//                     128 x 128 with 256 threads (2 x 2 wavefronts of 64 x 64) and
+//                     64-byte stages below that.
 #include <hip/hip_runtime.h>
 
 #include "qmm_device.h"
@@ -22,8 +27,9 @@ namespace {
 
 typedef int ix4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128, KT = kInt8KT, NT = 256, PITCH = KT + 16;
-static_assert(KT == 64, "the staging map below assumes 64-byte K stages");
+// Transposed operand rows are padded to a multiple of the largest K stage.
+constexpr int kBtAlign = 128;
+static_assert(kBtAlign % kInt8KT == 0, "blocks must be whole stages");
 
 // Centre four packed residues: x -> x - p where x > h = (p-1)/2.  With x <= p-1
 // every byte of w + (127-h) stays below 256, so its top bit is exactly [x > h];
@@ -54,6 +60,7 @@ __global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_
     }
 }
 
+template <int BM, int BN>
 __device__ __forceinline__ void tile_coords(int64_t m, int64_t n, int &tm, int &tn) {
     const int tiles_m = (int)ceil_div(m, BM), tiles_n = (int)ceil_div(n, BN);
     const int nb = gridDim.x;
@@ -79,35 +86,48 @@ struct Int8Args {
     int64_t ldc;
     int32_t kb_tiles;  // K stages per block (0 = unblocked)
     uint32_t p, add_h, neg_p;
-    double invp;
+    uint64_t magic;    // floor(2^64 / p) + 1
+    uint32_t off;      // p floor(2^31 / p)
     bool a_vec;        // A rows 16-byte aligned: vector loads allowed
 };
 
-template <bool BLOCKED>
-__global__ __launch_bounds__(NT, 2) void gemm_int8_kernel(Int8Args g) {
+// BM x BN output tile, WGM x WGN wavefronts, K stage of KT bytes.  Each wavefront
+// owns a (BM/WGM) x (BN/WGN) sub-tile of 16 x 16 MFMA blocks.  Rows of both LDS
+// stages are padded by 16 bytes: the 16 lanes that read one 16-byte fragment
+// column then fall on distinct bank groups.
+template <int BM, int BN, int KT, int WGM, int WGN, bool BLOCKED>
+__global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * WGN) ? 1 : 2) void gemm_int8_kernel(Int8Args g) {
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int PITCH = KT + 16;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int SEGS = KT / 16;
+    constexpr int A_LOADS = BM * SEGS / NT, B_LOADS = BN * SEGS / NT;
+    static_assert(BM * SEGS % NT == 0 && BN * SEGS % NT == 0, "staging must divide evenly");
+    static_assert(KT % 64 == 0, "K stage is a whole number of MFMA steps");
     __shared__ __attribute__((aligned(16))) uint8_t sA[2][BM * PITCH];
     __shared__ __attribute__((aligned(16))) uint8_t sB[2][BN * PITCH];
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
     int tm, tn;
-    tile_coords(g.m, g.n, tm, tn);
+    tile_coords<BM, BN>(g.m, g.n, tm, tn);
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
 
-    ix4 acc[4][4];
+    ix4 acc[FM][FN];
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+    for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = ix4{0, 0, 0, 0};
+        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix4{0, 0, 0, 0};
 
-    // Staging: two 16-byte segments of A and two of Bt per thread and stage.
-    // Segment c = tid + 256 i: row c >> 2, bytes 16 (c & 3) .. +15 of the stage.
-    uint4 ra[2], rb[2];
+    // Staging: segment c = tid + NT i covers row c / SEGS, bytes 16 (c % SEGS) .. +15.
+    uint4 ra[A_LOADS], rb[B_LOADS];
     auto load_stage = [&](int kt) {
         const int64_t k0 = (int64_t)kt * KT;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < A_LOADS; ++i) {
             const int c = tid + NT * i;
-            const int r = c >> 2, seg = c & 3;
+            const int r = c / SEGS, seg = c % SEGS;
             const int64_t kk = k0 + seg * 16;
             const int64_t arow = row0 + r;
             uint4 v = make_uint4(0, 0, 0, 0);
@@ -127,18 +147,27 @@ __global__ __launch_bounds__(NT, 2) void gemm_int8_kernel(Int8Args g) {
             v.z = centre4(v.z, g.add_h, g.neg_p);
             v.w = centre4(v.w, g.add_h, g.neg_p);
             ra[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < B_LOADS; ++i) {
+            const int c = tid + NT * i;
+            const int r = c / SEGS, seg = c % SEGS;
+            const int64_t kk = k0 + seg * 16;
             const int64_t brow = col0 + r;
-            // Bt rows are zero-padded to ldbt (a multiple of 64), so whole stages are in bounds.
+            // Bt rows are zero-padded to ldbt (a multiple of the stage), so whole stages are in bounds.
             rb[i] = (brow < g.n) ? *(const uint4 *)(g.Bt + brow * g.ldbt + kk) : make_uint4(0, 0, 0, 0);
         }
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < A_LOADS; ++i) {
             const int c = tid + NT * i;
-            const int r = c >> 2, seg = c & 3;
-            *(uint4 *)&sA[buf][r * PITCH + seg * 16] = ra[i];
-            *(uint4 *)&sB[buf][r * PITCH + seg * 16] = rb[i];
+            *(uint4 *)&sA[buf][(c / SEGS) * PITCH + (c % SEGS) * 16] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < B_LOADS; ++i) {
+            const int c = tid + NT * i;
+            *(uint4 *)&sB[buf][(c / SEGS) * PITCH + (c % SEGS) * 16] = rb[i];
         }
     };
 
@@ -149,26 +178,32 @@ __global__ __launch_bounds__(NT, 2) void gemm_int8_kernel(Int8Args g) {
     for (int kt = 0; kt < ntiles; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < ntiles) load_stage(kt + 1);
-        ix4 af[4], bf[4];
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
-            af[mi] = *(const ix4 *)&sA[buf][(wm * 64 + mi * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
+        for (int ks = 0; ks < KT / 64; ++ks) {
+            // All B fragments of the step, then one A fragment at a time: the
+            // 4 x FN MFMAs that use an A fragment follow its load.
+            ix4 bf[FN];
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
-            bf[ni] = *(const ix4 *)&sB[buf][(wn * 64 + ni * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
+            for (int ni = 0; ni < FN; ++ni)
+                bf[ni] = *(const ix4 *)&sB[buf][(wn * WTN + ni * 16 + (lane & 15)) * PITCH + ks * 64 + 16 * (lane >> 4)];
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
+            for (int mi = 0; mi < FM; ++mi) {
+                const ix4 af =
+                    *(const ix4 *)&sA[buf][(wm * WTM + mi * 16 + (lane & 15)) * PITCH + ks * 64 + 16 * (lane >> 4)];
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni)
-                acc[mi][ni] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+                for (int ni = 0; ni < FN; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+            }
+        }
         if constexpr (BLOCKED) {
             if ((kt + 1) % g.kb_tiles == 0 && kt + 1 < ntiles) {
 #pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
+                for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-                    for (int ni = 0; ni < 4; ++ni)
+                    for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[mi][ni][r] = (int)mod_i32(acc[mi][ni][r], g.p, g.invp);
+                        for (int r = 0; r < 4; ++r)
+                            acc[mi][ni][r] = (int)mod_i32_magic(acc[mi][ni][r], g.p, g.magic, g.off);
             }
         }
         if (kt + 1 < ntiles) {
@@ -179,14 +214,17 @@ __global__ __launch_bounds__(NT, 2) void gemm_int8_kernel(Int8Args g) {
 
     // lane l, register r holds D[4 (l >> 4) + r][l & 15]
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+    for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
+        for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + wm * 64 + mi * 16 + 4 * (lane >> 4) + r;
-                const int64_t col = col0 + wn * 64 + ni * 16 + (lane & 15);
-                if (row < g.m && col < g.n) g.C[row * g.ldc + col] = (uint8_t)mod_i32(acc[mi][ni][r], g.p, g.invp);
+                const int64_t row = row0 + wm * WTM + mi * 16 + 4 * (lane >> 4) + r;
+                const int64_t col = col0 + wn * WTN + ni * 16 + (lane & 15);
+                if (row < g.m && col < g.n)
+                    g.C[row * g.ldc + col] = (uint8_t)mod_i32_magic(acc[mi][ni][r], g.p, g.magic, g.off);
+                // keep the scheduler from hoisting every accumulator out at once
+                if (r == 3) __builtin_amdgcn_sched_barrier(0);
             }
 }
 
@@ -204,7 +242,7 @@ void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
 
 }  // namespace
 
-int64_t int8_bt_ld(int64_t k) { return ceil_div(k < 1 ? 1 : k, KT) * KT; }
+int64_t int8_bt_ld(int64_t k) { return ceil_div(k < 1 ? 1 : k, kBtAlign) * kBtAlign; }
 
 qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
                                    int8_t *Bt, int64_t ldbt, void *stream) {
@@ -214,6 +252,23 @@ qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, con
     const dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(ldbt, 64));
     centre_transpose_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt, ldbt, add_h, neg_p);
     return check_launch("centre_transpose");
+}
+
+namespace {
+template <int BM, int BN, int KT, int WGM, int WGN>
+qmm_status run_int8(const Int8Args &g, bool blocked, hipStream_t s) {
+    const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)));
+    if (blocked)
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+    else
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+    return check_launch("gemm_int8");
+}
+}  // namespace
+
+int int8_tile_for(int64_t m, int64_t n) {
+    // 256 x 256 tiles once they (nearly) fill the 256 CUs, 128 x 128 below that.
+    return (ceil_div(m, 256) * ceil_div(n, 256) >= 192) ? 2 : 1;
 }
 
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
@@ -230,18 +285,19 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
     g.C = C;
     g.ldc = ldc;
     const bool blocked = pl.k_block < k;
-    g.kb_tiles = blocked ? (int32_t)(pl.k_block / KT) : 0;
     g.p = pl.p;
     centre_consts(pl.p, g.add_h, g.neg_p);
-    g.invp = 1.0 / (double)pl.p;
+    g.magic = mod_magic(pl.p);
+    g.off = pl.p * ((1u << 31) / pl.p);
     g.a_vec = ((uintptr_t)A % 16 == 0) && (lda % 16 == 0);
-    const dim3 grid((unsigned)(ceil_div(m, BM) * ceil_div(n, BN)));
     hipStream_t s = (hipStream_t)stream;
-    if (blocked)
-        gemm_int8_kernel<true><<<grid, NT, 0, s>>>(g);
-    else
-        gemm_int8_kernel<false><<<grid, NT, 0, s>>>(g);
-    return check_launch("gemm_int8");
+    const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n);
+    if (tile == 2) {
+        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
+        return run_int8<256, 256, 128, 2, 4>(g, blocked, s);
+    }
+    g.kb_tiles = blocked ? (int32_t)(pl.k_block / 64) : 0;
+    return run_int8<128, 128, 64, 2, 2>(g, blocked, s);
 }
 
 }  // namespace qmm

@@ -11,8 +11,9 @@ namespace qmm {
 // K-tile of the Q-adic GEMM kernels, in packed words.  A k-block always spans a
 // whole number of K-tiles of words, so block boundaries fall between tiles.
 constexpr int kQadicKT = 16;
-// K-tile of the INT8 kernel, in bytes.  Blocks of the INT8 path are multiples of it.
-constexpr int kInt8KT = 64;
+// Largest K stage of the INT8 kernels, in bytes.  Blocks of the INT8 path are
+// multiples of it (and so whole stages of every INT8 kernel).
+constexpr int kInt8KT = 128;
 // Cost of one block boundary (extraction + reduction of every output) in units of
 // one packed word of MFMA work per output; used to rank blocked plans.
 constexpr int kBlockCostWords = 8;
@@ -30,6 +31,10 @@ QMM_HD inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Packed words along one packed dimension of size len.
 QMM_HD inline int64_t words_for(int64_t len, uint32_t d) { return ceil_div(len, (int64_t)d + 1); }
+
+// Multiplier of mod_u32: floor((2^64 - 1) / p) + 1, which is floor(2^64 / p) + 1 when
+// p is not a power of two and exactly 2^64 / p when it is; both keep the quotient exact.
+inline uint64_t mod_magic(uint32_t p) { return ~0ull / p + 1; }
 
 bool path_is_fp64(uint32_t path);
 bool path_is_fp32(uint32_t path);
@@ -73,5 +78,6 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
                             uint8_t *C, int64_t ldc, void *stream);
 int64_t int8_bt_ld(int64_t k);
+int int8_tile_for(int64_t m, int64_t n);
 
 }  // namespace qmm

@@ -25,6 +25,7 @@ REGIME_NAMES = {0: "exact", 1: "offset", 2: "paper", 3: "int"}
 # flags
 BOUND_PROVEN, BOUND_PAPER, PLAN_UNBLOCKED, BOUND_G4, BOUND_EQ4 = 0, 1, 2, 4, 8
 BATCH_FORCE_FP64 = 1
+BATCH_SHAPE_64x64, BATCH_SHAPE_32x128, BATCH_SHAPE_128x32 = 0x100, 0x200, 0x300
 # unpack selectors
 ROWS_REV, COLS_FWD, ROWS_FWD = 0, 1, 2
 
@@ -33,7 +34,7 @@ EXPORTS = [
     "qmm_unpack", "qmm_extract", "qmm_redq", "qmm_gemm_workspace_size", "qmm_gemm_mod_p", "qmm_gemm_packed",
     "qmm_batched_create", "qmm_gemm_mod_p_batched", "qmm_batched_plan", "qmm_batched_destroy",
     "qmm_last_error", "qmm_version", "qmm_pack_centred_cols", "qmm_gemm_centred",
-    "qmm_gemm_right_packed",
+    "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs",
 ]
 
 
@@ -94,6 +95,8 @@ def lib():
             "qmm_gemm_mod_p_batched": [vp, vp],
             "qmm_batched_plan": [vp, i64, P],
             "qmm_batched_destroy": [vp],
+            "qmm_batched_tune": [vp, ctypes.POINTER(ctypes.c_double)],
+            "qmm_batched_set_costs": [ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -286,8 +289,8 @@ def gemm_right_packed(plan, A, CBr, n, C=None, stream=None):
 
 
 def centred_ld(k) -> int:
-    """Leading dimension of the centred, transposed right operand: k rounded up to 64."""
-    return max(1, -(-k // 64)) * 64
+    """Leading dimension of the centred, transposed right operand: k rounded up to 128."""
+    return max(1, -(-k // 128)) * 128
 
 
 def pack_centred_cols(plan, B, Bt=None, stream=None):
@@ -344,3 +347,15 @@ def batched_create(problems, flags=0) -> Batch:
     h = ctypes.c_void_p(0)
     _check(lib().qmm_batched_create(len(problems), arr, flags, ctypes.byref(h)), "qmm_batched_create")
     return Batch(h, len(problems), [problems])
+
+
+def batched_tune(stream=None):
+    """Calibrate the batched autotuner on this GPU; returns the 6 fitted costs."""
+    out = (ctypes.c_double * 6)()
+    _check(lib().qmm_batched_tune(_stream(stream), out), "qmm_batched_tune")
+    return list(out)
+
+
+def batched_set_costs(costs):
+    arr = (ctypes.c_double * 6)(*costs)
+    _check(lib().qmm_batched_set_costs(arr), "qmm_batched_set_costs")

@@ -74,7 +74,7 @@ def test_plans_that_break_the_bounds_are_refused():
     paper = qmm.choose_Qd(3, 64, 64, 64, flags=qmm.BOUND_PAPER, path=qmm.PATH_FP64_QADIC)
     assert paper.regime == qmm.REGIME_PAPER and qmm.validate_plan(paper, 64, 64, 64) == qmm.EBOUND
     i8 = qmm.choose_Qd(251, 4, 4, 200000, path=qmm.PATH_INT8)
-    assert i8.k_block < 200000 and i8.k_block % 64 == 0
+    assert i8.k_block < 200000 and i8.k_block % 128 == 0
     big = qmm.Plan.from_buffer_copy(i8)
     big.k_block = 200000
     assert qmm.validate_plan(big, 4, 4, 200000) == qmm.EBOUND

@@ -140,4 +140,4 @@ def test_int8_blocks():
         h = p // 2
         assert pl.k_block * h * h + (p - 1) <= 2 ** 31 - 1
         if pl.k_block < k:
-            assert pl.k_block % 64 == 0 and (pl.k_block + 64) * h * h + (p - 1) > 2 ** 31 - 1
+            assert pl.k_block % 128 == 0 and (pl.k_block + 128) * h * h + (p - 1) > 2 ** 31 - 1

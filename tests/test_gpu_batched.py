@@ -1,0 +1,134 @@
+"""Batched products in one persistent, graph-recorded launch, against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from paper_0803_1975_amd import qmm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("these tests need a GPU")
+    return _t
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def make_problems(torch, shapes, seed):
+    rng = np.random.default_rng(seed)
+    host, dev = [], []
+    for p, m, n, k in shapes:
+        A = rng.integers(0, p, (m, k), dtype=np.uint8)
+        B = rng.integers(0, p, (k, n), dtype=np.uint8)
+        dA = torch.from_numpy(A).cuda()
+        dB = torch.from_numpy(B).cuda()
+        dC = torch.full((m, n), 255, dtype=torch.uint8, device="cuda")
+        host.append((A, B, p))
+        dev.append((dA, dB, dC, p))
+    return host, dev
+
+
+def check_all(host, dev):
+    for i, ((A, B, p), (_, _, dC, _)) in enumerate(zip(host, dev)):
+        np.testing.assert_array_equal(dC.cpu().numpy(), ref.modmul(A, B, p), err_msg=f"product {i}")
+
+
+EDGE_SHAPES = [(7, 1, 1, 1), (3, 16, 16, 16), (101, 17, 33, 5), (2, 513, 31, 70), (251, 64, 64, 64),
+               (256, 65, 129, 200), (5, 3, 300, 1), (13, 200, 1, 90), (31, 128, 32, 512), (11, 32, 128, 17),
+               (3, 0, 5, 5), (3, 5, 0, 5), (7, 9, 9, 0)]
+
+
+@pytest.mark.parametrize("flags", [0, qmm.BATCH_SHAPE_64x64, qmm.BATCH_SHAPE_32x128, qmm.BATCH_SHAPE_128x32,
+                                   qmm.BATCH_FORCE_FP64])
+def test_batched_edge_shapes(torch, flags):
+    note("edge", flags)
+    host, dev = make_problems(torch, EDGE_SHAPES, 10 + flags)
+    batch = qmm.batched_create(dev, flags)
+    try:
+        batch.run()
+        torch.cuda.synchronize()
+        check_all(host, dev)
+        for i, (p, m, n, k) in enumerate(EDGE_SHAPES):
+            pl = batch.plan(i)
+            assert pl.p == p
+            assert pl.path == (qmm.PATH_FP64_QADIC if flags & qmm.BATCH_FORCE_FP64 else qmm.PATH_INT8)
+    finally:
+        batch.destroy()
+
+
+def test_graph_replays_match_eager_results(torch):
+    shapes = synth.batched_shapes(count=300, seed=7)
+    host, dev = make_problems(torch, shapes, 7)
+    batch = qmm.batched_create(dev)
+    try:
+        for replay in range(4):
+            note("replay", replay)
+            for _, _, dC, _ in dev:
+                dC.zero_()                              # eager work between replays
+            torch.cuda.synchronize()
+            batch.run()
+            torch.cuda.synchronize()
+            check_all(host, dev)
+    finally:
+        batch.destroy()
+
+
+def test_batched_workload_2000_products(torch):
+    shapes = synth.batched_shapes()
+    assert len(shapes) == 2000
+    inputs = synth.batched_inputs(shapes)
+    dev = []
+    for (p, m, n, k), (A, B) in zip(shapes, inputs):
+        dev.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
+                    torch.full((m, n), 255, dtype=torch.uint8, device="cuda"), p))
+    for flags in (0, qmm.BATCH_FORCE_FP64):
+        note("workload", flags)
+        batch = qmm.batched_create(dev, flags)
+        try:
+            batch.run()
+            torch.cuda.synchronize()
+            for i, ((p, m, n, k), (A, B)) in enumerate(zip(shapes, inputs)):
+                np.testing.assert_array_equal(dev[i][2].cpu().numpy(), ref.modmul(A, B, p), err_msg=f"product {i}")
+                dev[i][2].fill_(255)
+        finally:
+            batch.destroy()
+
+
+def test_autotuner_calibration_and_choices(torch):
+    costs = qmm.batched_tune()
+    note("costs", costs)
+    assert len(costs) == 6 and all(c >= 0 for c in costs) and all(costs[i] > 0 for i in (1, 3, 5))
+    qmm.batched_set_costs(costs)
+    shapes = [(7, 32, 512, 256), (7, 512, 32, 256), (7, 256, 256, 256)]
+    host, dev = make_problems(torch, shapes, 3)
+    batch = qmm.batched_create(dev)
+    try:
+        tiles = [batch.plan(i).tile for i in range(3)]
+        note("tiles", tiles)
+        batch.run()
+        torch.cuda.synchronize()
+        check_all(host, dev)
+    finally:
+        batch.destroy()
+
+
+def test_batched_rejects_bad_problems(torch):
+    A = torch.zeros((4, 4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(qmm.QmmError):
+        qmm.batched_create([(A, A, A, 300)])
+    big = torch.zeros((2, 140000), dtype=torch.uint8, device="cuda")
+    bigB = torch.zeros((140000, 2), dtype=torch.uint8, device="cuda")
+    C = torch.zeros((2, 2), dtype=torch.uint8, device="cuda")
+    with pytest.raises(qmm.QmmError) as ei:
+        qmm.batched_create([(big, bigB, C, 251)])
+    assert ei.value.status == qmm.EUNSUPPORTED
