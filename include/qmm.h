@@ -157,7 +157,7 @@ qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
 
 /* Procedure (1) on already compressed operands: C = digit d of CA x CB, mod p.
  * CA: m x ceil(k/(d+1)) words from qmm_pack_rows_rev; CB: ceil(k/(d+1)) x n words
- * from qmm_pack_cols_fwd, both with this plan.  QADIC paths only. */
+ * from qmm_pack_cols_fwd, both with this plan.  QADIC paths only; p <= 256. */
 qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
                            const void *CA, int64_t ldca, const void *CB, int64_t ldcb,
                            uint8_t *C, int64_t ldc, void *stream);

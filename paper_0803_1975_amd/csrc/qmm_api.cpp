@@ -116,6 +116,7 @@ extern "C" qmm_status qmm_extract(const qmm_plan *plan, int64_t m, int64_t n, co
         return fail(QMM_EINVAL, "extract needs an EXACT or OFFSET plan");
     if (plan->regime == QMM_REGIME_OFFSET && plan->t > 32)
         return fail(QMM_EINVAL, "offset extraction needs t <= 32");
+    if (plan->p > 256) return fail(QMM_EINVAL, "byte results need p <= 256");
     if (bad_matrix(m, n, T, ldt) || bad_matrix(m, n, C, ldc)) return fail(QMM_EINVAL, "bad size, pointer or ld");
     return launch_extract(*plan, m, n, T, ldt, C, ldc, stream);
 }
@@ -125,6 +126,7 @@ extern "C" qmm_status qmm_redq(const qmm_plan *plan, int64_t m, int64_t n, const
     qmm_status st = check_plan_for_words(plan);
     if (st != QMM_OK) return st;
     if ((uint64_t)plan->t * (plan->d + 1) > 52) return fail(QMM_EINVAL, "REDQ words need t (d+1) <= 52");
+    if (plan->p > 256) return fail(QMM_EINVAL, "byte results need p <= 256");
     if (bad_matrix(m, words_for(n, plan->d), CC, ldcc) || bad_matrix(m, n, C, ldc))
         return fail(QMM_EINVAL, "bad size, pointer or ld");
     return launch_redq(*plan, m, n, CC, ldcc, C, ldc, stream);
@@ -178,6 +180,7 @@ extern "C" qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n
                                       void *stream) {
     if (!plan) return fail(QMM_EINVAL, "plan is NULL");
     if (!path_is_qadic(plan->path)) return fail(QMM_EINVAL, "qmm_gemm_packed takes a QADIC plan");
+    if (plan->p > 256) return fail(QMM_EINVAL, "byte results need p <= 256");
     qmm_status st = qmm_validate_plan(plan, m, n, k);
     if (st != QMM_OK) return st;
     if (m < 0 || n < 0 || k < 0) return fail(QMM_EINVAL, "negative size");
@@ -217,6 +220,7 @@ extern "C" qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int
                                             int64_t lda, const void *CBr, int64_t ldcbr, uint8_t *C, int64_t ldc,
                                             void *stream) {
     if (!plan || !path_is_redq(plan->path)) return fail(QMM_EINVAL, "a REDQ plan is required");
+    if (plan->p > 256) return fail(QMM_EINVAL, "byte results need p <= 256");
     qmm_status st = qmm_validate_plan(plan, m, n, k);
     if (st != QMM_OK) return st;
     if (bad_matrix(m, k, A, lda) || bad_matrix(k, words_for(n, plan->d), CBr, ldcbr) || bad_matrix(m, n, C, ldc))

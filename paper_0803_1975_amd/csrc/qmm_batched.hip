@@ -31,6 +31,7 @@ namespace qmm {
 namespace {
 
 typedef int ix4 __attribute__((ext_vector_type(4)));
+typedef int ix16 __attribute__((ext_vector_type(16)));
 typedef double dx4 __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 256;
@@ -112,12 +113,12 @@ __device__ __forceinline__ uint32_t load4(const uint8_t *src, int valid, const u
 }
 
 // One INT8 tile of BM x BN outputs: wavefronts laid out WGM x WGN, each owning
-// (BM/WGM) x (BN/WGN) outputs in 16 x 16 MFMA blocks.  Stages of 64 k-bytes go
+// (BM/WGM) x (BN/WGN) outputs in 32 x 32 MFMA blocks (i32_32x32x32_i8).  Stages of 64 k-bytes go
 // through two LDS buffers: the loads of stage s+1 are issued before the MFMAs of
 // stage s and stored after them, one barrier per stage.
 template <int BM, int BN, int WGM, int WGN>
 __device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
-    constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 16, FN = WTN / 16;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
     constexpr int A_SEGS = BM * (KB / 16);   // 16-byte A segments per stage
     constexpr int B_GRPS = BN * KB / 16;     // 4 x 4-byte B groups per stage
     constexpr int A_PER = (A_SEGS + NT - 1) / NT, B_PER = (B_GRPS + NT - 1) / NT;
@@ -128,11 +129,11 @@ __device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
     const uint8_t *a_lo = D.A, *a_hi = D.A + (D.m > 0 && D.k > 0 ? (int64_t)(D.m - 1) * D.lda + D.k : 0);
     const uint8_t *b_lo = D.B, *b_hi = D.B + (D.k > 0 && D.n > 0 ? (int64_t)(D.k - 1) * D.ldb + D.n : 0);
-    ix4 acc[FM][FN];
+    ix16 acc[FM][FN];
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix4{0, 0, 0, 0};
+        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
 
     uint4 ra[A_PER];
     uint32_t rb[B_PER][4];
@@ -148,10 +149,6 @@ __device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
                 const int kk = k0 + 16 * s;
                 if (row < D.m && kk < D.k) v = load16(D.A + row * D.lda + kk, D.k - kk, a_lo, a_hi);
             }
-            v.x = centre4(v.x, D.add_h, D.neg_p);
-            v.y = centre4(v.y, D.add_h, D.neg_p);
-            v.z = centre4(v.z, D.add_h, D.neg_p);
-            v.w = centre4(v.w, D.add_h, D.neg_p);
             ra[i] = v;
         }
 #pragma unroll
@@ -172,7 +169,12 @@ __device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
 #pragma unroll
         for (int i = 0; i < A_PER; ++i) {
             const int c = tid + NT * i;
-            if (c < A_SEGS) *(uint4 *)&sA[(c >> 2) * PITCH + 16 * (c & 3)] = ra[i];
+            uint4 v = ra[i];
+            v.x = centre4(v.x, D.add_h, D.neg_p);
+            v.y = centre4(v.y, D.add_h, D.neg_p);
+            v.z = centre4(v.z, D.add_h, D.neg_p);
+            v.w = centre4(v.w, D.add_h, D.neg_p);
+            if (c < A_SEGS) *(uint4 *)&sA[(c >> 2) * PITCH + 16 * (c & 3)] = v;
         }
         // B: a 4 (k) x 4 (columns) byte group, transposed in registers so that each
         // column's four k-bytes form one dword of the k-contiguous LDS row.
@@ -208,29 +210,32 @@ __device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
         const int buf = st & 1;
         if (st + 1 < nst) load_stage(st + 1);
         const uint8_t *sA = lds + buf * STAGE, *sB = sA + 128 * PITCH;
-        ix4 bf[FN];
 #pragma unroll
-        for (int ni = 0; ni < FN; ++ni)
-            bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
-#pragma unroll
-        for (int mi = 0; mi < FM; ++mi) {
-            const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 16 + (lane & 15)) * PITCH + 16 * (lane >> 4)];
+        for (int ks = 0; ks < KB / 32; ++ks) {
+            ix4 bf[FN];
 #pragma unroll
             for (int ni = 0; ni < FN; ++ni)
-                acc[mi][ni] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+                bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PITCH + ks * 32 + 16 * (lane >> 5)];
+#pragma unroll
+            for (int mi = 0; mi < FM; ++mi) {
+                const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PITCH + ks * 32 + 16 * (lane >> 5)];
+#pragma unroll
+                for (int ni = 0; ni < FN; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+            }
         }
         if (st + 1 < nst) store_stage(buf ^ 1);
         __syncthreads();
     }
-    // lane l, register r holds D[4 (l >> 4) + r][l & 15]
+    // lane l, register r holds D[8 (r/4) + 4 (l/32) + r % 4][l % 32]
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
         for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + wm * WTM + mi * 16 + 4 * (lane >> 4) + r;
-                const int64_t col = col0 + wn * WTN + ni * 16 + (lane & 15);
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + wm * WTM + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t col = col0 + wn * WTN + ni * 32 + (lane & 31);
                 if (row < D.m && col < D.n)
                     D.C[row * D.ldc + col] = (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
             }

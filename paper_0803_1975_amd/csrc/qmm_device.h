@@ -68,6 +68,15 @@ __device__ __forceinline__ uint32_t low_mantissa_bits(double w) {
 }
 __device__ __forceinline__ uint32_t low_mantissa_bits(float w) { return __float_as_uint(w); }
 
+// Digit d of an accumulated word with only exact floating-point steps, as the
+// paper's init routine does: scale by Q^-d (a power of two), floor, and keep the
+// low t bits as x - Q floor(x / Q).  Exact regime only (the word is S < 2^beta).
+template <typename W>
+__device__ __forceinline__ uint32_t exact_digit(W acc, W inv_qd, W inv_q, W q) {
+    const W x = floor(acc * inv_qd);
+    return (uint32_t)(x - q * floor(x * inv_q));
+}
+
 // Digit d of an accumulated word, for either regime.
 template <typename W>
 __device__ __forceinline__ uint32_t qadic_digit(W acc, bool offset, uint32_t td, uint64_t qmask) {

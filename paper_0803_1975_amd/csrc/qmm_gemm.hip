@@ -71,6 +71,9 @@ struct GemmArgs {
     double invp;
     double start;            // accumulator start value (M or 0)
     uint32_t qmodp;          // Q mod p (REDQ)
+    uint64_t magic;          // mod_u32 multiplier for p
+    double inv_qd, inv_q, q; // 2^-td, 2^-t, 2^t (exact-regime digit)
+    int32_t small_digit;     // t <= 31: digits fit 32 bits
 };
 
 // Output tile of this workgroup.  Workgroups are dealt round-robin to the 8 XCDs;
@@ -92,10 +95,8 @@ __device__ __forceinline__ void tile_coords(int64_t m, int64_t n, int &tm, int &
     tn = local / gsize;
 }
 
-// Blocked plans keep 64 residue registers besides the 64 accumulator words:
-// they run one workgroup per CU pair of SIMD slots so nothing spills.
 template <typename W, typename AT, int EPI, bool OFFSET, bool BLOCKED>
-__global__ __launch_bounds__(NT, BLOCKED ? 1 : 2) void gemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     using MM = Mma<W>;
     using acc_t = typename MM::acc_t;
     __shared__ W sA[2][BM][KT + APAD];
@@ -113,14 +114,14 @@ __global__ __launch_bounds__(NT, BLOCKED ? 1 : 2) void gemm_kernel(GemmArgs g) {
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = acc_t{start, start, start, start};
-    uint32_t res[4][4][4];
+    // Blocked plans: the residues of the finished blocks, reduced mod p (< 256, since
+    // results are bytes), four to a register.
+    uint32_t res[4][4];
     if constexpr (BLOCKED) {
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) res[mi][ni][r] = 0;
+            for (int ni = 0; ni < 4; ++ni) res[mi][ni] = 0;
     }
 
     // Staging: A row ra_r, elements ra_k..ra_k+7; B row rb_k, columns rb_c..rb_c+7.
@@ -154,14 +155,21 @@ __global__ __launch_bounds__(NT, BLOCKED ? 1 : 2) void gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) sB[buf][rb_k][rb_c + e] = rb[e];
     };
+    // Digit d of one accumulated word (t <= 31 when blocked, so it fits 32 bits).
+    auto digit32 = [&](W a) -> uint32_t {
+        if constexpr (OFFSET) return low_mantissa_bits(a) & (uint32_t)g.qmask;
+        else return exact_digit<W>(a, (W)g.inv_qd, (W)g.inv_q, (W)g.q);
+    };
     auto reduce_block = [&]() {
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni) {
+                uint32_t packed = 0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    res[mi][ni][r] += mod_u64(qadic_digit<W>(acc[mi][ni][r], OFFSET, g.td, g.qmask), g.p, g.invp);
+                    packed |= mod_u32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.magic) << (8 * r);
+                res[mi][ni] = packed;
                 acc[mi][ni] = acc_t{start, start, start, start};
             }
     };
@@ -205,8 +213,11 @@ __global__ __launch_bounds__(NT, BLOCKED ? 1 : 2) void gemm_kernel(GemmArgs g) {
                 const int64_t col = col0 + wn * 64 + ni * 16 + (lane & 15);
                 if (row >= g.m || col >= g.n) continue;
                 if constexpr (EPI == EPI_QADIC) {
-                    uint32_t v = mod_u64(qadic_digit<W>(acc[mi][ni][r], OFFSET, g.td, g.qmask), g.p, g.invp);
-                    if constexpr (BLOCKED) v = mod_u64((uint64_t)res[mi][ni][r] + v, g.p, g.invp);
+                    uint32_t v;
+                    if constexpr (BLOCKED)
+                        v = mod_u32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.magic);
+                    else if (g.small_digit) v = mod_u32(digit32(acc[mi][ni][r]), g.p, g.magic);
+                    else v = mod_u64(qadic_digit<W>(acc[mi][ni][r], OFFSET, g.td, g.qmask), g.p, g.invp);
                     g.C[row * g.ldc + col] = (uint8_t)v;
                 } else {
                     // REDQ of the exact word, then its d+1 residues to consecutive columns.
@@ -256,6 +267,12 @@ qmm_status launch_qadic_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     g.invp = 1.0 / (double)pl.p;
     const bool offset = pl.regime == QMM_REGIME_OFFSET;
     g.start = offset ? ldexp(1.0, WordTraits<W>::beta - 1 + (int)(pl.t * pl.d)) : 0.0;
+    g.magic = mod_magic(pl.p);
+    g.inv_qd = ldexp(1.0, -(int)(pl.t * pl.d));
+    g.inv_q = ldexp(1.0, -(int)pl.t);
+    g.q = ldexp(1.0, (int)pl.t);
+    g.small_digit = pl.t <= 31;
+    if (blocked && pl.t > 31) return fail(QMM_EUNSUPPORTED, "blocked plans need t <= 31");
     const dim3 grid((unsigned)(ceil_div(m, BM) * ceil_div(n, BN)));
     if (offset && blocked)
         gemm_kernel<W, W, EPI_QADIC, true, true><<<grid, NT, 0, s>>>(g);
