@@ -96,33 +96,24 @@ __device__ __forceinline__ uint4 load16(const uint8_t *src, int valid, const uin
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// 4 bytes at src, same rules with an 8-byte window.
-__device__ __forceinline__ uint32_t load4(const uint8_t *src, int valid, const uint8_t *lo, const uint8_t *hi) {
-    if (valid >= 4) {
-        const uintptr_t a = (uintptr_t)src;
-        const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
-        if (base >= lo && base + 8 <= hi) {
-            const uint32_t w0 = *(const uint32_t *)base, w1 = *(const uint32_t *)(base + 4);
-            return __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(a & 3));
-        }
-    }
-    uint32_t v = 0;
-    for (int b = 0; b < 4; ++b)
-        if (b < valid) v |= (uint32_t)src[b] << (8 * b);
-    return v;
+// One INT8 tile of BM x BN outputs: wavefronts laid out WGM x WGN, each owning
+// (BM/WGM) x (BN/WGN) outputs in 32 x 32 MFMA blocks (i32_32x32x32_i8).  k goes
+// through LDS in batches of KC bytes: all global loads of a batch are issued
+// together (one memory latency per batch, not per MFMA step), then centred and
+// stored, then multiplied.  B arrives as 4 (k) x 16 (column) byte blocks that are
+// transposed in registers into the k-contiguous LDS layout the MFMA reads.
+__device__ __forceinline__ uint32_t lane_word(const uint4 &v, int q) {
+    return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
 }
 
-// One INT8 tile of BM x BN outputs: wavefronts laid out WGM x WGN, each owning
-// (BM/WGM) x (BN/WGN) outputs in 32 x 32 MFMA blocks (i32_32x32x32_i8).  Stages of 64 k-bytes go
-// through two LDS buffers: the loads of stage s+1 are issued before the MFMAs of
-// stage s and stored after them, one barrier per stage.
+constexpr int KC = 256;           // k-bytes per LDS batch
+constexpr int PC = KC + 16;       // LDS row pitch of a batch
 template <int BM, int BN, int WGM, int WGN>
-__device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
+__device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *sA, uint8_t *sB) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
-    constexpr int A_SEGS = BM * (KB / 16);   // 16-byte A segments per stage
-    constexpr int B_GRPS = BN * KB / 16;     // 4 x 4-byte B groups per stage
-    constexpr int A_PER = (A_SEGS + NT - 1) / NT, B_PER = (B_GRPS + NT - 1) / NT;
-    constexpr int STAGE = 128 * PITCH * 2;   // bytes of one A + B buffer pair
+    constexpr int A_SEGS = BM * (KC / 16);          // 16-byte A segments per batch
+    constexpr int B_ITEMS = (KC / 4) * (BN / 16);   // 4 x 16-byte B blocks per batch
+    constexpr int A_PER = (A_SEGS + NT - 1) / NT, B_PER = (B_ITEMS + NT - 1) / NT;
     static_assert(WGM * WGN == 4, "four wavefronts");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
@@ -135,98 +126,84 @@ __device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
 #pragma unroll
         for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
 
-    uint4 ra[A_PER];
-    uint32_t rb[B_PER][4];
-    auto load_stage = [&](int st) {
-        const int k0 = st * KB;
+    for (int k0 = 0; k0 < D.k; k0 += KC) {
+        uint4 ra[A_PER], rb[B_PER][4];
 #pragma unroll
         for (int i = 0; i < A_PER; ++i) {
             const int c = tid + NT * i;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (c < A_SEGS) {
-                const int r = c >> 2, s = c & 3;
-                const int64_t row = row0 + r;
-                const int kk = k0 + 16 * s;
-                if (row < D.m && kk < D.k) v = load16(D.A + row * D.lda + kk, D.k - kk, a_lo, a_hi);
-            }
-            ra[i] = v;
+            const int r = c / (KC / 16), s = c % (KC / 16);
+            const int64_t row = row0 + r;
+            const int kk = k0 + 16 * s;
+            ra[i] = (c < A_SEGS && row < D.m && kk < D.k) ? load16(D.A + row * D.lda + kk, D.k - kk, a_lo, a_hi)
+                                                          : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < B_PER; ++i) {
             const int c = tid + NT * i;
-            const int cq = c % (BN / 4), kq = c / (BN / 4);
-            const int64_t col = col0 + 4 * cq;
+            const int kq = c / (BN / 16), cg = c % (BN / 16);
+            const int64_t col = col0 + 16 * cg;
             const int cvalid = (int)(D.n - col);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int kk = k0 + 4 * kq + j;
-                rb[i][j] = (c < B_GRPS && kk < D.k && cvalid > 0) ? load4(D.B + (int64_t)kk * D.ldb + col, cvalid, b_lo, b_hi) : 0u;
+                rb[i][j] = (c < B_ITEMS && kk < D.k && cvalid > 0)
+                               ? load16(D.B + (int64_t)kk * D.ldb + col, cvalid, b_lo, b_hi)
+                               : make_uint4(0, 0, 0, 0);
             }
         }
-    };
-    auto store_stage = [&](int buf) {
-        uint8_t *sA = lds + buf * STAGE, *sB = sA + 128 * PITCH;
+        __syncthreads();  // the previous batch's MFMAs are done with LDS
 #pragma unroll
         for (int i = 0; i < A_PER; ++i) {
             const int c = tid + NT * i;
+            if (c >= A_SEGS) continue;
             uint4 v = ra[i];
             v.x = centre4(v.x, D.add_h, D.neg_p);
             v.y = centre4(v.y, D.add_h, D.neg_p);
             v.z = centre4(v.z, D.add_h, D.neg_p);
             v.w = centre4(v.w, D.add_h, D.neg_p);
-            if (c < A_SEGS) *(uint4 *)&sA[(c >> 2) * PITCH + 16 * (c & 3)] = v;
+            *(uint4 *)&sA[(c / (KC / 16)) * PC + 16 * (c % (KC / 16))] = v;
         }
-        // B: a 4 (k) x 4 (columns) byte group, transposed in registers so that each
-        // column's four k-bytes form one dword of the k-contiguous LDS row.
 #pragma unroll
         for (int i = 0; i < B_PER; ++i) {
             const int c = tid + NT * i;
-            if (c >= B_GRPS) continue;
-            const int cq = c % (BN / 4), kq = c / (BN / 4);
-            const uint32_t *rw = rb[i];
-            // column b gathers byte b of rw[0..3]
-            const uint32_t lo01 = __builtin_amdgcn_perm(rw[1], rw[0], 0x05010400u);  // r0b0 r1b0 r0b1 r1b1
-            const uint32_t lo23 = __builtin_amdgcn_perm(rw[3], rw[2], 0x05010400u);
-            const uint32_t hi01 = __builtin_amdgcn_perm(rw[1], rw[0], 0x07030602u);  // r0b2 r1b2 r0b3 r1b3
-            const uint32_t hi23 = __builtin_amdgcn_perm(rw[3], rw[2], 0x07030602u);
-            uint32_t col[4];
-            col[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
-            col[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
-            col[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
-            col[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+            if (c >= B_ITEMS) continue;
+            const int kq = c / (BN / 16), cg = c % (BN / 16);
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                *(uint32_t *)&sB[(4 * cq + b) * PITCH + 4 * kq] = centre4(col[b], D.add_h, D.neg_p);
+            for (int q = 0; q < 4; ++q) {
+                // dword q of each of the 4 rows: columns 16 cg + 4 q .. + 3
+                const uint32_t r0 = lane_word(rb[i][0], q), r1 = lane_word(rb[i][1], q);
+                const uint32_t r2 = lane_word(rb[i][2], q), r3 = lane_word(rb[i][3], q);
+                const uint32_t lo01 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);  // r0b0 r1b0 r0b1 r1b1
+                const uint32_t lo23 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+                const uint32_t hi01 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);  // r0b2 r1b2 r0b3 r1b3
+                const uint32_t hi23 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+                uint32_t colw[4];
+                colw[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+                colw[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+                colw[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+                colw[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    *(uint32_t *)&sB[(16 * cg + 4 * q + b) * PC + 4 * kq] = centre4(colw[b], D.add_h, D.neg_p);
+            }
         }
-    };
-
-    const int nst = (D.k + KB - 1) / KB;
-    if (nst > 0) {
-        load_stage(0);
-        store_stage(0);
-    }
-    __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst) load_stage(st + 1);
-        const uint8_t *sA = lds + buf * STAGE, *sB = sA + 128 * PITCH;
-#pragma unroll
-        for (int ks = 0; ks < KB / 32; ++ks) {
+        __syncthreads();
+        const int ksteps = (min(KC, D.k - k0) + 31) / 32;
+        for (int ks = 0; ks < ksteps; ++ks) {
             ix4 bf[FN];
 #pragma unroll
             for (int ni = 0; ni < FN; ++ni)
-                bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PITCH + ks * 32 + 16 * (lane >> 5)];
+                bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PC + ks * 32 + 16 * (lane >> 5)];
 #pragma unroll
             for (int mi = 0; mi < FM; ++mi) {
-                const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PITCH + ks * 32 + 16 * (lane >> 5)];
+                const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PC + ks * 32 + 16 * (lane >> 5)];
 #pragma unroll
                 for (int ni = 0; ni < FN; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
             }
         }
-        if (st + 1 < nst) store_stage(buf ^ 1);
-        __syncthreads();
     }
+    __syncthreads();  // LDS is free for the next tile
     // lane l, register r holds D[8 (r/4) + 4 (l/32) + r % 4][l % 32]
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
@@ -244,7 +221,7 @@ __device__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
 // One FP64 Q-adic tile of 64 x 64 outputs: rows of A packed reversed and columns
 // of B packed forward straight from the bytes (Horner over the d+1 residues of a
 // chunk), 16 words per stage, MFMA f64 16x16x4, digit d of every word mod p.
-__device__ void fp64_tile(const Desc &D, int tm, int tn, double *sA, double *sB) {
+__device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double *sA, double *sB) {
     // sA: 64 rows x (KW + 1) words; sB: KW rows x 64 words
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -324,25 +301,28 @@ __device__ void fp64_tile(const Desc &D, int tm, int tn, double *sA, double *sB)
             }
 }
 
-constexpr int kLdsInt8 = 2 * 2 * 128 * PITCH;                              // two A + B stages, largest shape
-constexpr int kLdsFp64 = (64 * (KW + 1) + KW * 64) * (int)sizeof(double);
-constexpr int kLdsBytes = kLdsInt8 > kLdsFp64 ? kLdsInt8 : kLdsFp64;
-
-__global__ __launch_bounds__(NT, 2) void batched_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles,
-                                                         int32_t ntiles) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+// One persistent kernel per tile class (so each gets the registers and occupancy
+// of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
+// list, which is sorted longest first.
+template <uint32_t SHAPE>
+__global__ __launch_bounds__(NT) void batched_int8_kernel(const Desc *__restrict__ descs,
+                                                          const TileRef *__restrict__ tiles, int32_t ntiles) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PC];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
-        if (D.path == QMM_PATH_FP64_QADIC) {
-            fp64_tile(D, tr.tm, tr.tn, (double *)lds, (double *)lds + 64 * (KW + 1));
-        } else if (D.shape == SHAPE_32x128) {
-            int8_tile<32, 128, 1, 4>(D, tr.tm, tr.tn, lds);
-        } else if (D.shape == SHAPE_128x32) {
-            int8_tile<128, 32, 4, 1>(D, tr.tm, tr.tn, lds);
-        } else {
-            int8_tile<64, 64, 2, 2>(D, tr.tm, tr.tn, lds);
-        }
+        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_bm(SHAPE) / 32, shape_bn(SHAPE) / 32>(D, tr.tm, tr.tn, lds,
+                                                                                              lds + shape_bm(SHAPE) * PC);
+    }
+}
+
+__global__ __launch_bounds__(NT) void batched_fp64_kernel(const Desc *__restrict__ descs,
+                                                          const TileRef *__restrict__ tiles, int32_t ntiles) {
+    __shared__ __attribute__((aligned(16))) double lds[64 * (KW + 1) + KW * 64];
+    for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
+        const TileRef tr = tiles[i];
+        const Desc D = descs[tr.desc];
+        fp64_tile(D, tr.tm, tr.tn, lds, lds + 64 * (KW + 1));
     }
 }
 
@@ -383,14 +363,18 @@ qmm_status hip_fail(hipError_t e, const char *what) {
 
 using namespace qmm;
 
+// Tile classes: the three INT8 shapes and the FP64 Q-adic tile.
+constexpr int kClasses = SHAPE_COUNT + 1;
+
 struct qmm_batched {
     int64_t count = 0;
     std::vector<qmm_plan> plans;
     Desc *d_desc = nullptr;
     TileRef *d_tiles = nullptr;
     int32_t ntiles = 0;
-    int grid = 0;
-    hipStream_t capture_stream = nullptr;
+    int32_t class_first[kClasses] = {0, 0, 0, 0}, class_count[kClasses] = {0, 0, 0, 0};
+    hipStream_t streams[kClasses] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -401,7 +385,11 @@ void release(qmm_batched *b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    for (int c = 0; c < kClasses; ++c) {
+        if (b->join[c]) (void)hipEventDestroy(b->join[c]);
+        if (b->streams[c]) (void)hipStreamDestroy(b->streams[c]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     delete b;
@@ -411,7 +399,7 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     b->count = count;
     b->plans.resize((size_t)count);
     std::vector<Desc> descs((size_t)count);
-    std::vector<std::pair<double, TileRef>> tiles;
+    std::vector<std::pair<double, TileRef>> tiles[kClasses];
     for (int64_t i = 0; i < count; ++i) {
         const qmm_problem &P = probs[i];
         if (P.p < 2 || P.p > 256) return fail(QMM_EINVAL, "problem " + std::to_string(i) + ": byte residues need 2 <= p <= 256");
@@ -468,13 +456,18 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         const int32_t tmax = (int32_t)ceil_div(P.m, bm), nmax = (int32_t)ceil_div(P.n, bn);
         const double cost = pl.path == QMM_PATH_INT8 ? tile_cost(D.shape, bm, bn, P.k)
                                                      : (double)ceil_div(words_for(P.k < 1 ? 1 : P.k, pl.d), KW) * 4.0;
+        const int cls = pl.path == QMM_PATH_INT8 ? (int)D.shape : SHAPE_COUNT;
         for (int32_t tm = 0; tm < tmax; ++tm)
-            for (int32_t tn = 0; tn < nmax; ++tn) tiles.push_back({cost, TileRef{(int32_t)i, tm, tn, 0}});
+            for (int32_t tn = 0; tn < nmax; ++tn) tiles[cls].push_back({cost, TileRef{(int32_t)i, tm, tn, 0}});
     }
-    // longest first, ties by product and position so the order is deterministic
-    std::stable_sort(tiles.begin(), tiles.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
-    std::vector<TileRef> flat(tiles.size());
-    for (size_t i = 0; i < tiles.size(); ++i) flat[i] = tiles[i].second;
+    // per class, longest first (stable, so the order is deterministic)
+    std::vector<TileRef> flat;
+    for (int c = 0; c < kClasses; ++c) {
+        std::stable_sort(tiles[c].begin(), tiles[c].end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        b->class_first[c] = (int32_t)flat.size();
+        b->class_count[c] = (int32_t)tiles[c].size();
+        for (const auto &t : tiles[c]) flat.push_back(t.second);
+    }
     b->ntiles = (int32_t)flat.size();
 
     hipError_t e;
@@ -485,20 +478,55 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     if (!flat.empty() && (e = hipMemcpy(b->d_tiles, flat.data(), sizeof(TileRef) * flat.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "hipMemcpy");
 
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return hip_fail(e, "attribute");
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel, NT, 0)) != hipSuccess)
-        return hip_fail(e, "occupancy");
-    b->grid = std::max(1, std::min<int>(b->ntiles, cus * std::max(1, per_cu)));
 
-    // Record the launch in a graph.  The graph holds only the kernel node: the
-    // schedule is static, so there is nothing to clear between replays.
-    if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-    if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e, "capture");
-    if (b->ntiles > 0) batched_kernel<<<b->grid, NT, 0, b->capture_stream>>>(b->d_desc, b->d_tiles, b->ntiles);
-    const hipError_t le = hipGetLastError();
-    if ((e = hipStreamEndCapture(b->capture_stream, &b->graph)) != hipSuccess) return hip_fail(e, "end capture");
+    // Record the launches in one graph: the classes' persistent kernels are
+    // parallel branches between a fork and a join.  The schedule is static, so
+    // the graph holds only kernel nodes and nothing needs clearing between replays.
+    for (int c = 0; c < kClasses; ++c) {
+        if ((e = hipStreamCreateWithFlags(&b->streams[c], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+        if ((e = hipEventCreateWithFlags(&b->join[c], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    }
+    if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    hipStream_t s0 = b->streams[0];
+    if ((e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e, "capture");
+    hipError_t le = hipSuccess;
+    (void)hipEventRecord(b->fork, s0);
+    for (int c = 0; c < kClasses; ++c) {
+        if (b->class_count[c] == 0) continue;
+        hipStream_t sc = b->streams[c];
+        if (c != 0) (void)hipStreamWaitEvent(sc, b->fork, 0);
+        const Desc *dd = b->d_desc;
+        const TileRef *tt = b->d_tiles + b->class_first[c];
+        const int32_t nt = b->class_count[c];
+        int per_cu = 1;
+        switch (c) {
+        case SHAPE_64x64:
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_int8_kernel<SHAPE_64x64>, NT, 0);
+            batched_int8_kernel<SHAPE_64x64><<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
+            break;
+        case SHAPE_32x128:
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_int8_kernel<SHAPE_32x128>, NT, 0);
+            batched_int8_kernel<SHAPE_32x128><<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
+            break;
+        case SHAPE_128x32:
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_int8_kernel<SHAPE_128x32>, NT, 0);
+            batched_int8_kernel<SHAPE_128x32><<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
+            break;
+        default:
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_fp64_kernel, NT, 0);
+            batched_fp64_kernel<<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
+            break;
+        }
+        if (le == hipSuccess) le = hipGetLastError();
+        if (c != 0) {
+            (void)hipEventRecord(b->join[c], sc);
+            (void)hipStreamWaitEvent(s0, b->join[c], 0);
+        }
+    }
+    if ((e = hipStreamEndCapture(s0, &b->graph)) != hipSuccess) return hip_fail(e, "end capture");
     if (le != hipSuccess) return hip_fail(le, "batched launch");
     if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
     return QMM_OK;

@@ -6,7 +6,7 @@
 //
 //   centre_transpose  B (k x n bytes) -> Bt (n x ldbt int8, k contiguous, zero
 //                     padded to a multiple of 128): the int8 MFMA wants both
-//                     operands contiguous along k.  HBM-bound, 64 x 64 tiles
+//                     operands contiguous along k.  HBM-bound, 128 x 128 tiles
 //                     through LDS so reads and writes are both row-contiguous.
 //   gemm_int8         C = (A_centred x Bt^T) mod p.  A is centred in registers on
 //                     its way into LDS, four residues per 32-bit word.  MFMA
@@ -42,43 +42,64 @@ __device__ __forceinline__ uint32_t centre4(uint32_t w, uint32_t add_h, uint32_t
     return w + flag * neg_p;
 }
 
-// Bt[n0 + c][k0 + r] = centred(B[k0 + r][n0 + c]) for a 64 (k) x 64 (n) tile:
-// each thread reads 16 consecutive bytes of one B row (a vector load when the row
-// segment is aligned and whole) into an LDS tile, then gathers 16 consecutive k
-// of one column from LDS and writes them as one 16-byte store to Bt.
+// Bt[n0 + c][k0 + r] = centred(B[k0 + r][n0 + c]) for a 128 (k) x 128 (n) tile:
+// each thread reads 16 consecutive bytes of four B rows (vector loads when the
+// row segments are aligned and whole, all four in flight together) into an LDS
+// tile, then gathers 64 consecutive k of one column from LDS and writes them as
+// four 16-byte stores to Bt.
+constexpr int CT = 128;
 __global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
                                                                 int64_t ldb, int8_t *__restrict__ Bt, int64_t ldbt,
                                                                 uint32_t add_h, uint32_t neg_p, int b_vec) {
-    __shared__ __attribute__((aligned(16))) uint8_t tile[64][64 + 4];
-    const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+    __shared__ __attribute__((aligned(16))) uint8_t tile[CT][CT + 4];
+    const int64_t k0 = (int64_t)blockIdx.y * CT, n0 = (int64_t)blockIdx.x * CT;
     const int t = threadIdx.x;
     {
-        const int r = t >> 2, seg = t & 3;
-        const int64_t kk = k0 + r, nn = n0 + 16 * seg;
-        uint32_t w[4] = {0, 0, 0, 0};
-        if (kk < k) {
-            const uint8_t *src = B + kk * ldb + nn;
-            if (b_vec && nn + 16 <= n) {
-                const uint4 v = *(const uint4 *)src;
-                w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-            } else {
-                for (int b = 0; b < 16; ++b)
-                    if (nn + b < n) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+        const int seg = t & 7, r0 = t >> 3;  // 16-byte segment of a 128-byte row; rows r0 + 32 i
+        const int64_t nn = n0 + 16 * seg;
+        uint4 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t kk = k0 + r0 + 32 * i;
+            v[i] = make_uint4(0, 0, 0, 0);
+            if (kk < k) {
+                const uint8_t *src = B + kk * ldb + nn;
+                if (b_vec && nn + 16 <= n) {
+                    v[i] = *(const uint4 *)src;
+                } else {
+                    uint32_t w[4] = {0, 0, 0, 0};
+                    for (int b = 0; b < 16; ++b)
+                        if (nn + b < n) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+                    v[i] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(uint32_t *)&tile[r][16 * seg + 4 * q] = centre4(w[q], add_h, neg_p);
+        for (int i = 0; i < 4; ++i) {
+            uint32_t *dst = (uint32_t *)&tile[r0 + 32 * i][16 * seg];
+            dst[0] = centre4(v[i].x, add_h, neg_p);
+            dst[1] = centre4(v[i].y, add_h, neg_p);
+            dst[2] = centre4(v[i].z, add_h, neg_p);
+            dst[3] = centre4(v[i].w, add_h, neg_p);
+        }
     }
     __syncthreads();
     {
-        const int c = t >> 2, seg = t & 3;  // column c, k-bytes 16 seg .. +15
-        const int64_t nn = n0 + c, kk = k0 + 16 * seg;
-        if (nn < n && kk < ldbt) {
-            uint32_t w[4] = {0, 0, 0, 0};
+        const int c = t >> 1, half = t & 1;  // column c, k-bytes 64 half .. +63
+        const int64_t nn = n0 + c;
+        if (nn < n) {
 #pragma unroll
-            for (int b = 0; b < 16; ++b) w[b >> 2] |= (uint32_t)tile[16 * seg + b][c] << (8 * (b & 3));
-            // rows past k were loaded as zero (and centre4(0) = 0), so Bt's padding is zero
-            *(uint4 *)(Bt + nn * ldbt + kk) = make_uint4(w[0], w[1], w[2], w[3]);
+            for (int q = 0; q < 4; ++q) {
+                const int kb = 64 * half + 16 * q;
+                const int64_t kk = k0 + kb;
+                if (kk < ldbt) {
+                    uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+                    for (int b = 0; b < 16; ++b) w[b >> 2] |= (uint32_t)tile[kb + b][c] << (8 * (b & 3));
+                    // rows past k were loaded as zero (and centre4(0) = 0), so Bt's padding is zero
+                    *(uint4 *)(Bt + nn * ldbt + kk) = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
         }
     }
 }
@@ -278,7 +299,7 @@ qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, con
     if (n == 0) return QMM_OK;
     uint32_t add_h, neg_p;
     centre_consts(pl.p, add_h, neg_p);
-    const dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(ldbt, 64));
+    const dim3 grid((unsigned)ceil_div(n, CT), (unsigned)ceil_div(ldbt, CT));
     const int b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
     centre_transpose_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt, ldbt, add_h, neg_p, b_vec);
     return check_launch("centre_transpose");
