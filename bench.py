@@ -82,25 +82,49 @@ class Stepper:
         else:
             wd = qmm.word_dtype(plan)
             self.CBr = torch.empty((k, -(-n // (plan.d + 1))), dtype=wd, device=dev)
+        self._prepare()
+
+    def _prepare(self):
+        """Pre-marshal the C calls of both stages (the same calls the binding makes), so
+        the host issues a step in a few microseconds and the GPU never waits for it."""
+        import ctypes
+        q, pl, torch = self.qmm, self.plan, self.torch
+        L = q.lib()
+        P = ctypes.byref(pl)
+        vp = ctypes.c_void_p
+        st = vp(torch.cuda.current_stream().cuda_stream)
+        A, B, C = self.dA, self.dB, self.C
+        m, n, k = self.m, self.n, self.k
+        if pl.path == q.PATH_INT8:
+            Bt = self.Bt
+            self.conv_calls = [(L.qmm_pack_centred_cols, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(Bt.data_ptr()),
+                                                          q._ld(Bt), st))]
+            self.prod_calls = [(L.qmm_gemm_centred, (P, m, n, k, vp(A.data_ptr()), q._ld(A), vp(Bt.data_ptr()),
+                                                     q._ld(Bt), vp(C.data_ptr()), q._ld(C), st))]
+        elif pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):
+            CA, CB = self.CA, self.CB
+            self.conv_calls = [(L.qmm_pack_rows_rev, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CA.data_ptr()), q._ld(CA), st)),
+                               (L.qmm_pack_cols_fwd, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CB.data_ptr()), q._ld(CB), st))]
+            self.prod_calls = [(L.qmm_gemm_packed, (P, m, n, k, vp(CA.data_ptr()), q._ld(CA), vp(CB.data_ptr()),
+                                                    q._ld(CB), vp(C.data_ptr()), q._ld(C), st))]
+        else:
+            CBr = self.CBr
+            self.conv_calls = [(L.qmm_pack_rows_fwd, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CBr.data_ptr()),
+                                                      q._ld(CBr), st))]
+            self.prod_calls = [(L.qmm_gemm_right_packed, (P, m, n, k, vp(A.data_ptr()), q._ld(A), vp(CBr.data_ptr()),
+                                                          q._ld(CBr), vp(C.data_ptr()), q._ld(C), st))]
+
+    def _run(self, calls):
+        for fn, args in calls:
+            rc = fn(*args)
+            if rc != 0:
+                raise self.qmm.QmmError(rc, fn.__name__)
 
     def convert(self):
-        q, pl = self.qmm, self.plan
-        if pl.path == q.PATH_INT8:
-            q.pack_centred_cols(pl, self.dB, self.Bt)
-        elif pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):
-            q.pack_rows_rev(pl, self.dA, self.CA)
-            q.pack_cols_fwd(pl, self.dB, self.CB)
-        else:
-            q.pack_rows_fwd(pl, self.dB, self.CBr)
+        self._run(self.conv_calls)
 
     def product(self):
-        q, pl = self.qmm, self.plan
-        if pl.path == q.PATH_INT8:
-            q.gemm_centred(pl, self.dA, self.Bt, self.n, self.C)
-        elif pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):
-            q.gemm_packed(pl, self.k, self.CA, self.CB, self.C)
-        else:
-            q.gemm_right_packed(pl, self.dA, self.CBr, self.n, self.C)
+        self._run(self.prod_calls)
 
     def kernel_work(self):
         """(algorithmic ops of one product-kernel launch, peak, unit, kind)."""
@@ -281,7 +305,19 @@ def main():
     ap.add_argument("--paths", default="all", help="'all' or 'chosen'")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes three times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        a = torch.ones(args.copy_bytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_bytes} bytes three times")
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
