@@ -36,7 +36,6 @@ typedef double dx4 __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 256;
 constexpr int KB = 64;          // INT8 K stage (bytes)
-constexpr int PITCH = KB + 16;  // LDS row pitch of INT8 stages
 constexpr int KW = 16;          // FP64 K stage (packed words)
 
 // Tile shapes of the batched kernel (rows x columns of C per tile).

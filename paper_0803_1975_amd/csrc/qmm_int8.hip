@@ -141,7 +141,11 @@ struct Int8Args {
 // D[8 (r/4) + 4 (l/32) + r % 4][l % 32] in register r).  Rows of both LDS stages
 // are padded by 16 bytes: the 8 lanes that one LDS cycle serves then read 8
 // consecutive rows on distinct bank groups.
-template <int BM, int BN, int KT, int WGM, int WGN, bool BLOCKED>
+// AVEC: every row of A is 16-byte aligned and k is a multiple of 16, so each
+// 16-byte segment below k is one vector load; segments past k or rows past m
+// load from a clamped, valid address and are zeroed by a select (no branches in
+// the loop).  Otherwise segments are assembled from byte loads.
+template <int BM, int BN, int KT, int WGM, int WGN, bool BLOCKED, bool AVEC>
 __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * WGN) ? 1 : 2) void gemm_int8_kernel(Int8Args g) {
     constexpr int NT = 64 * WGM * WGN;
     constexpr int PITCH = KT + 16;
@@ -167,37 +171,52 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
         for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
 
     // Staging: segment c = tid + NT i covers row c / SEGS, bytes 16 (c % SEGS) .. +15.
+    // Row pointers and validity are fixed for the whole k loop.
     uint4 ra[A_LOADS], rb[B_LOADS];
+    const uint8_t *a_ptr[A_LOADS];
+    const int8_t *b_ptr[B_LOADS];
+    bool a_ok[A_LOADS], b_ok[B_LOADS];
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+        const int c = tid + NT * i;
+        const int64_t arow = row0 + c / SEGS;
+        a_ok[i] = arow < g.m;
+        a_ptr[i] = g.A + (a_ok[i] ? arow : 0) * g.lda + (c % SEGS) * 16;
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+        const int c = tid + NT * i;
+        const int64_t brow = col0 + c / SEGS;
+        b_ok[i] = brow < g.n;
+        b_ptr[i] = g.Bt + (b_ok[i] ? brow : 0) * g.ldbt + (c % SEGS) * 16;
+    }
     auto load_stage = [&](int kt) {
         const int64_t k0 = (int64_t)kt * KT;
 #pragma unroll
         for (int i = 0; i < A_LOADS; ++i) {
-            const int c = tid + NT * i;
-            const int r = c / SEGS, seg = c % SEGS;
-            const int64_t kk = k0 + seg * 16;
-            const int64_t arow = row0 + r;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (arow < g.m) {
-                const uint8_t *src = g.A + arow * g.lda + kk;
-                if (g.a_vec && kk + 16 <= g.k) {
-                    v = *(const uint4 *)src;
-                } else {
+            const int64_t kk = k0 + ((tid + NT * i) % SEGS) * 16;
+            if constexpr (AVEC) {
+                // a segment past k (or a row past m) reads A's first 16 bytes instead
+                const bool ok = a_ok[i] && kk < g.k;
+                const uint4 v = *(const uint4 *)(ok ? a_ptr[i] + k0 : g.A);
+                ra[i] = ok ? v : make_uint4(0, 0, 0, 0);
+            } else {
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (a_ok[i]) {
+                    const uint8_t *src = a_ptr[i] + k0;
                     uint32_t w[4] = {0, 0, 0, 0};
                     for (int b = 0; b < 16; ++b)
                         if (kk + b < g.k) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
                     v = make_uint4(w[0], w[1], w[2], w[3]);
                 }
+                ra[i] = v;
             }
-            ra[i] = v;
         }
 #pragma unroll
         for (int i = 0; i < B_LOADS; ++i) {
-            const int c = tid + NT * i;
-            const int r = c / SEGS, seg = c % SEGS;
-            const int64_t kk = k0 + seg * 16;
-            const int64_t brow = col0 + r;
             // Bt rows are zero-padded to ldbt (a multiple of the stage), so whole stages are in bounds.
-            rb[i] = (brow < g.n) ? *(const uint4 *)(g.Bt + brow * g.ldbt + kk) : make_uint4(0, 0, 0, 0);
+            const uint4 v = *(const uint4 *)(b_ptr[i] + k0);
+            rb[i] = b_ok[i] ? v : make_uint4(0, 0, 0, 0);
         }
     };
     // The loads of a stage are only consumed here, after the MFMAs of the previous
@@ -309,10 +328,15 @@ namespace {
 template <int BM, int BN, int KT, int WGM, int WGN>
 qmm_status run_int8(const Int8Args &g, bool blocked, hipStream_t s) {
     const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)));
-    if (blocked)
-        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+    const bool avec = g.a_vec && g.k % 16 == 0;
+    if (blocked && avec)
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+    else if (blocked)
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+    else if (avec)
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
     else
-        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
     return check_launch("gemm_int8");
 }
 }  // namespace
