@@ -329,3 +329,30 @@ def test_graph_workload_and_paley_closed_form(torch):
         C = host(qmm.gemm_mod_p(dA, dA, p, plan=plan))
         sampled_check(torch, A, A, p, C, nsamp=5000, rows=2)
         assert (C == C.T).all()
+
+
+
+@pytest.mark.parametrize("p,m,n,k", [(7, 300, 272, 1040), (2, 1, 16, 16), (251, 257, 512, 4096), (3, 640, 48, 130048),
+                                     (101, 33, 1024, 16), (256, 96, 64, 1984)])
+def test_int8_stages_match_one_call_and_oracle(torch, p, m, n, k):
+    # The two INT8 stage calls (centring transpose, product) give what qmm_gemm_mod_p
+    # gives; both 256 x 256 and 128 x 128 tiles; k past a 128-byte stage boundary.
+    note("int8 stages", p, m, n, k)
+    rng = np.random.default_rng(m + n + k)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    dA, dB = dev(torch, A), dev(torch, B)
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    one = qmm.gemm_mod_p(dA, dB, p, plan=plan)
+    Bt = qmm.pack_centred_cols(plan, dB)
+    for tile in (1, 2):
+        plan.tile = tile
+        assert torch.equal(qmm.gemm_centred(plan, dA, Bt, n), one)
+    if m * n * k <= 2 ** 28:
+        np.testing.assert_array_equal(host(one), ref.modmul(A, B, p))
+    else:
+        sampled_check(torch, A, B, p, host(one), nsamp=4000, rows=2)
+    plan.tile = 0
+    worst = torch.full((m, k), p - 1, dtype=torch.uint8, device="cuda")
+    worstB = torch.full((k, n), p - 1, dtype=torch.uint8, device="cuda")
+    assert (host(qmm.gemm_mod_p(worst, worstB, p, plan=plan)) == (k * (p - 1) ** 2) % p).all()
