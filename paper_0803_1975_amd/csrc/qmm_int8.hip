@@ -266,6 +266,16 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
 #pragma unroll
                 for (int ni = 0; ni < FN; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
+            // Interleave: one MFMA, then one of the next k-step's LDS reads, so the
+            // reads' latency hides behind the matrix core instead of stalling it.
+            if (ks + 1 < KT / 32) {
+#pragma unroll
+                for (int x = 0; x < FM + FN; ++x) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                if constexpr (FM * FN > FM + FN) __builtin_amdgcn_sched_group_barrier(0x008, FM * FN - (FM + FN), 0);
+            }
         }
         if constexpr (BLOCKED) {
             if ((kt + 1) % g.kb_tiles == 0 && kt + 1 < ntiles) {
@@ -342,8 +352,9 @@ qmm_status run_int8(const Int8Args &g, bool blocked, hipStream_t s) {
 }  // namespace
 
 int int8_tile_for(int64_t m, int64_t n) {
-    // 256 x 256 tiles once they (nearly) fill the 256 CUs, 128 x 128 below that.
-    return (ceil_div(m, 256) * ceil_div(n, 256) >= 192) ? 2 : 1;
+    // 256 x 256 tiles (16 wavefronts of 64 x 64) once they (nearly) fill the 256 CUs,
+    // 128 x 128 below that.
+    return (ceil_div(m, 256) * ceil_div(n, 256) >= 192) ? 3 : 1;
 }
 
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
@@ -370,6 +381,10 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
     if (tile == 2) {
         g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
         return run_int8<256, 256, 128, 2, 4>(g, blocked, s);
+    }
+    if (tile == 3) {
+        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
+        return run_int8<256, 256, 128, 4, 4>(g, blocked, s);
     }
     g.kb_tiles = blocked ? (int32_t)(pl.k_block / 64) : 0;
     return run_int8<128, 128, 64, 2, 2>(g, blocked, s);

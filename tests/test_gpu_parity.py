@@ -217,7 +217,13 @@ def test_int8_blocked_accumulation(torch):
     A = rng.integers(0, p, (20, k), dtype=np.uint8)
     B = rng.integers(0, p, (k, 9), dtype=np.uint8)
     got, _ = run_gemm(torch, A, B, p, qmm.PATH_INT8)
-    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+    want = ref.modmul(A, B, p)
+    np.testing.assert_array_equal(got, want)
+    dA, dB = dev(torch, A), dev(torch, B)
+    for tile in (1, 2, 3):
+        plan = qmm.choose_Qd(p, 20, 9, k, path=qmm.PATH_INT8)
+        plan.tile = tile
+        np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=plan)), want, err_msg=f"tile {tile}")
 
 
 def test_offset_regime_relies_on_one_rounding_per_product(torch):
@@ -336,7 +342,8 @@ def test_graph_workload_and_paley_closed_form(torch):
                                      (101, 33, 1024, 16), (256, 96, 64, 1984)])
 def test_int8_stages_match_one_call_and_oracle(torch, p, m, n, k):
     # The two INT8 stage calls (centring transpose, product) give what qmm_gemm_mod_p
-    # gives; both 256 x 256 and 128 x 128 tiles; k past a 128-byte stage boundary.
+    # gives; every tile variant (128 x 128, 256 x 256 with 8 or 16 wavefronts); k past
+    # a 128-byte stage boundary.
     note("int8 stages", p, m, n, k)
     rng = np.random.default_rng(m + n + k)
     A = rng.integers(0, p, (m, k), dtype=np.uint8)
@@ -345,7 +352,7 @@ def test_int8_stages_match_one_call_and_oracle(torch, p, m, n, k):
     plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
     one = qmm.gemm_mod_p(dA, dB, p, plan=plan)
     Bt = qmm.pack_centred_cols(plan, dB)
-    for tile in (1, 2):
+    for tile in (1, 2, 3):
         plan.tile = tile
         assert torch.equal(qmm.gemm_centred(plan, dA, Bt, n), one)
     if m * n * k <= 2 ** 28:
