@@ -196,9 +196,14 @@ typedef struct {
 typedef struct qmm_batched qmm_batched;
 
 /* Plans every product (path and tile per product), builds the device-side
- * descriptor table and tile list, and records one launch of the persistent kernel
- * in a HIP graph.  probs is a host array; the device buffers it names must stay
- * valid until qmm_batched_destroy.  The batch owns the device memory it allocates.
+ * descriptor table, tile list and operand-block list, and records the launches in
+ * one HIP graph: for INT8 products a pack kernel that centres every A_i and
+ * centres and transposes every B_i once into a workspace, then one persistent
+ * product kernel per tile shape.  probs is a host array; the device buffers it
+ * names must stay valid until qmm_batched_destroy.  The batch owns the device
+ * memory it allocates, including the workspace of sum_i (mp_i + np_i) kp_i bytes
+ * (kp_i = k_i rounded up to 64, mp_i and np_i = m_i and n_i rounded up to the
+ * product's tile).
  * flags: QMM_BATCH_FORCE_FP64 puts every product on the FP64 Q-adic tile path (the
  * paper's method, unblocked plans); QMM_BATCH_SHAPE_* fixes the INT8 output tile
  * instead of letting the autotuner pick it per product.  Products whose k would
@@ -214,12 +219,12 @@ qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t 
 /* Replays the recorded launch on `stream`: every product of the batch. */
 qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream);
 
-/* Autotuner calibration: times the persistent kernel on synthetic batches of each
- * INT8 tile shape (allocating and freeing its own device buffers, synchronising
- * `stream`) and fits per-tile cost = fixed + per_stage * (k / 64).  Later
- * qmm_batched_create calls use the fit.  costs (may be NULL) receives 6 doubles:
- * (fixed, per_stage) for 64x64, 32x128 and 128x32, in units of one 64-byte stage
- * of a 64x64 tile. */
+/* Autotuner calibration: times whole batches of each INT8 tile shape on
+ * synthetic products (allocating and freeing its own device buffers,
+ * synchronising `stream`) and fits per-tile cost = fixed + per_stage * (k / 128).
+ * Later qmm_batched_create calls use the fit.  costs (may be NULL) receives 6
+ * doubles: (fixed, per_stage) for 64x64, 32x128 and 128x32, in units of one
+ * 128-byte K stage of a 64x64 tile. */
 qmm_status qmm_batched_tune(void *stream, double *costs);
 
 /* Installs previously measured costs (6 doubles, as qmm_batched_tune returns). */

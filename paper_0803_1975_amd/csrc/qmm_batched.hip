@@ -1,21 +1,28 @@
-// Batches of independent products C_i = A_i x B_i mod p_i in ONE persistent launch.
+// Batches of independent products C_i = A_i x B_i mod p_i in one graph launch.
 //
 // Host side (qmm_batched_create):
 //   - plans every product: INT8 on centred residues whenever p_i <= 256 (the fast
 //     path on these matrix cores), or the FP64 Q-adic product when the batch is
 //     forced onto it (QMM_BATCH_FORCE_FP64, the paper's method as a baseline);
 //   - the autotuner picks the output tile shape per product (see tune_shape);
-//   - one descriptor per product and one entry per output tile go to device
-//     memory once; tiles are sorted longest first and dealt round-robin to the
-//     persistent workgroups (a static longest-processing-time schedule: no
-//     atomics, no counters to reset between replays);
-//   - the launch is recorded in a HIP graph; qmm_gemm_mod_p_batched replays it.
+//   - one descriptor per product, one entry per output tile and one per operand
+//     block to pack go to device memory once; tiles are sorted longest first and
+//     dealt round-robin to the persistent workgroups (a static longest-processing-
+//     time schedule: no atomics, no counters to reset between replays);
+//   - the launches are recorded in a HIP graph; qmm_gemm_mod_p_batched replays it.
 //
-// Device side: each workgroup (256 threads, 4 wavefronts) walks its tiles.  A
-// tile loads its A rows and B columns straight from the byte matrices (any
-// leading dimension, any alignment), converts them on the way into LDS
-// (centring for INT8; Q-adic packing of rows reversed / columns forward for
-// FP64) and runs the matching MFMA loop, then reduces and stores its outputs.
+// Device side, INT8 (two stages in the graph):
+//   pack    every operand byte is read once: A_i is centred into a workspace copy
+//           with rows of KP_i = k_i rounded up to 64 bytes, B_i is centred and
+//           transposed (k contiguous) into another, both zero padded to whole
+//           tiles and whole K stages, so the product needs no bounds checks and
+//           only aligned 16-byte loads;
+//   product one persistent kernel per tile shape, parallel graph branches; each
+//           tile runs 128-byte K stages through LDS into i32_32x32x32_i8 MFMAs
+//           (next stage's loads in flight during the MFMAs), then reduces mod p
+//           and stores its bytes.
+// Device side, FP64 Q-adic: one persistent kernel whose tiles pack rows of A
+// reversed and columns of B forward straight from the bytes on the way into LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,9 +40,14 @@ namespace {
 typedef int ix4 __attribute__((ext_vector_type(4)));
 typedef int ix16 __attribute__((ext_vector_type(16)));
 typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uint4v __attribute__((ext_vector_type(4)));
+
+// Global-address-space accesses: pointers read from a descriptor in memory are
+// otherwise generic, and a generic (flat) access also counts against the LDS
+// wait counter, so every LDS wait would wait for outstanding memory traffic too.
+#define QMM_GLOBAL __attribute__((address_space(1)))
 
 constexpr int NT = 256;
-constexpr int KB = 64;          // INT8 K stage (bytes)
 constexpr int KW = 16;          // FP64 K stage (packed words)
 
 // Tile shapes of the batched kernel (rows x columns of C per tile).
@@ -57,7 +69,19 @@ struct Desc {
     // FP64 Q-adic
     uint32_t t, d, offset_regime;
     double start, invp;
-    int32_t a_vec;    // A rows 16-byte aligned
+    // INT8: centred, zero-padded workspace copies (rows of kp bytes; mp and np rows)
+    int8_t *Ac;
+    int8_t *Bt;
+    int32_t kp, mp, np;
+};
+
+// One operand block for the pack kernel: kind 0 = rows r0 .. r0+63 of A at k bytes
+// c0 .. c0+255; kind 1 = k rows r0 .. r0+255 of B at columns c0 .. c0+63
+// (transposed into Bt).
+struct PackJob {
+    int32_t desc;
+    int32_t kind;
+    int32_t r0, c0;
 };
 
 struct TileRef {
@@ -81,8 +105,8 @@ __device__ __forceinline__ uint4 load16(const uint8_t *src, int valid, const uin
         const uintptr_t a = (uintptr_t)src;
         const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
         if (base >= lo && base + 20 <= hi) {
-            const u32x4a4 v = *(const u32x4a4 *)base;
-            const uint32_t w4 = *(const uint32_t *)(base + 16);
+            const u32x4a4 v = *(const QMM_GLOBAL u32x4a4 *)base;
+            const uint32_t w4 = *(const QMM_GLOBAL uint32_t *)(base + 16);
             const uint32_t sh = (uint32_t)(a & 3);
             if (sh == 0) return make_uint4(v.x, v.y, v.z, v.w);
             return make_uint4(__builtin_amdgcn_alignbyte(v.y, v.x, sh), __builtin_amdgcn_alignbyte(v.z, v.y, sh),
@@ -91,119 +115,165 @@ __device__ __forceinline__ uint4 load16(const uint8_t *src, int valid, const uin
     }
     uint32_t w[4] = {0, 0, 0, 0};
     for (int b = 0; b < 16; ++b)
-        if (b < valid) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+        if (b < valid) w[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)src)[b] << (8 * (b & 3));
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// One INT8 tile of BM x BN outputs: wavefronts laid out WGM x WGN, each owning
-// (BM/WGM) x (BN/WGN) outputs in 32 x 32 MFMA blocks (i32_32x32x32_i8).  k goes
-// through LDS in batches of KC bytes: all global loads of a batch are issued
-// together (one memory latency per batch, not per MFMA step), then centred and
-// stored, then multiplied.  B arrives as 4 (k) x 16 (column) byte blocks that are
-// transposed in registers into the k-contiguous LDS layout the MFMA reads.
-__device__ __forceinline__ uint32_t lane_word(const uint4 &v, int q) {
-    return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+// Pack one operand block (256 threads, four 16-byte segments each, all loads in
+// flight together).  A job: rows r0 .. r0+63 of A, k bytes c0 .. c0+255, centred,
+// zero past k and past m (rows up to mp, bytes up to kp).  B job: k rows
+// r0 .. r0+255, columns c0 .. c0+63 of B go through LDS; thread t then reads 16 k
+// rows of one 4-column word, transposes the 16 x 4 bytes in registers and writes
+// four 16-byte k-runs into rows of Bt (zero past k and past n, up to np and kp).
+constexpr int PACK_K = 256;
+__global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict__ descs,
+                                                          const PackJob *__restrict__ jobs) {
+    __shared__ uint32_t tile[PACK_K][17];  // k rows x 64 column bytes, padded by one word
+    const PackJob J = jobs[blockIdx.x];
+    const Desc &D = descs[J.desc];
+    const int t = threadIdx.x;
+    if (J.kind == 0) {
+        const int32_t row = J.r0 + (t >> 2);
+        if (row >= D.mp) return;
+        const uint8_t *hi = D.A + (int64_t)(D.m - 1) * D.lda + D.k;
+        uint4 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t kk = J.c0 + 16 * ((t & 3) + 4 * i);
+            v[i] = (row < D.m && kk < D.k) ? load16(D.A + (int64_t)row * D.lda + kk, D.k - kk, D.A, hi)
+                                           : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t kk = J.c0 + 16 * ((t & 3) + 4 * i);
+            if (kk < D.kp)
+                *(QMM_GLOBAL uint4v *)(D.Ac + (int64_t)row * D.kp + kk) =
+                    uint4v{centre4(v[i].x, D.add_h, D.neg_p), centre4(v[i].y, D.add_h, D.neg_p),
+                           centre4(v[i].z, D.add_h, D.neg_p), centre4(v[i].w, D.add_h, D.neg_p)};
+        }
+        return;
+    }
+    {
+        const uint8_t *hi = D.B + (int64_t)(D.k - 1) * D.ldb + D.n;
+        const int32_t col = J.c0 + 16 * (t & 3);
+        uint4 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t kk = J.r0 + (t >> 2) + 64 * i;
+            v[i] = (kk < D.k && col < D.n) ? load16(D.B + (int64_t)kk * D.ldb + col, D.n - col, D.B, hi)
+                                           : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t *dst = &tile[(t >> 2) + 64 * i][4 * (t & 3)];
+            dst[0] = centre4(v[i].x, D.add_h, D.neg_p);
+            dst[1] = centre4(v[i].y, D.add_h, D.neg_p);
+            dst[2] = centre4(v[i].z, D.add_h, D.neg_p);
+            dst[3] = centre4(v[i].w, D.add_h, D.neg_p);
+        }
+    }
+    __syncthreads();
+    const int cg = t & 15, kg = t >> 4;  // columns 4 cg .. 4 cg + 3, k rows 16 kg .. 16 kg + 15
+    uint32_t out[4][4];                  // [column q][k dword d]
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t r0 = tile[16 * kg + 4 * d + 0][cg], r1 = tile[16 * kg + 4 * d + 1][cg];
+        const uint32_t r2 = tile[16 * kg + 4 * d + 2][cg], r3 = tile[16 * kg + 4 * d + 3][cg];
+        const uint32_t lo01 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);  // r0b0 r1b0 r0b1 r1b1
+        const uint32_t lo23 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+        const uint32_t hi01 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);  // r0b2 r1b2 r0b3 r1b3
+        const uint32_t hi23 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+        out[0][d] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+        out[1][d] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+        out[2][d] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+        out[3][d] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+    }
+    const int32_t kk = J.r0 + 16 * kg;
+    if (kk >= D.kp) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t orow = J.c0 + 4 * cg + q;
+        if (orow < D.np)
+            *(QMM_GLOBAL uint4v *)(D.Bt + (int64_t)orow * D.kp + kk) = uint4v{out[q][0], out[q][1], out[q][2], out[q][3]};
+    }
 }
 
-constexpr int KC = 256;           // k-bytes per LDS batch
-constexpr int PC = KC + 16;       // LDS row pitch of a batch
+// One INT8 tile of BM x BN outputs from the packed operands: wavefronts laid out
+// WGM x WGN, each owning (BM/WGM) x (BN/WGN) outputs in 32 x 32 MFMA blocks
+// (i32_32x32x32_i8: lane l holds 16 k-bytes of row l % 32 for k-chunk l / 32 and
+// outputs D[8 (r/4) + 4 (l/32) + r % 4][l % 32] in register r).  K goes in
+// 128-byte stages through ONE LDS buffer per workgroup (so eight workgroups fit
+// a CU): a stage is published from registers, and the loads of the next stage
+// are issued before its MFMAs, so they are in flight during the MFMAs and the
+// barrier.  Loads are aligned 16-byte loads inside the padded workspace; the
+// segments of a last, 64-byte stage past kp are not loaded.
+__device__ __forceinline__ ix4 gload16(const int8_t *p) { return *(const QMM_GLOBAL ix4 *)p; }
+
+constexpr int KT = 128;            // K stage (bytes)
+constexpr int PT = KT + 16;        // LDS row pitch: 8 lanes reading 8 rows hit distinct banks
+constexpr int KP_ALIGN = 64;       // workspace rows: k rounded up to this
 template <int BM, int BN, int WGM, int WGN>
-__device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *sA, uint8_t *sB) {
+__device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
-    constexpr int A_SEGS = BM * (KC / 16);          // 16-byte A segments per batch
-    constexpr int B_ITEMS = (KC / 4) * (BN / 16);   // 4 x 16-byte B blocks per batch
-    constexpr int A_PER = (A_SEGS + NT - 1) / NT, B_PER = (B_ITEMS + NT - 1) / NT;
-    static_assert(WGM * WGN == 4, "four wavefronts");
+    constexpr int SEGS = KT / 16;
+    constexpr int A_SEGS = BM * SEGS, B_SEGS = BN * SEGS;
+    constexpr int A_LOADS = (A_SEGS + NT - 1) / NT, B_LOADS = (B_SEGS + NT - 1) / NT;
+    static_assert(WGM * WGN == NT / 64, "one wavefront per sub-tile");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
-    const uint8_t *a_lo = D.A, *a_hi = D.A + (D.m > 0 && D.k > 0 ? (int64_t)(D.m - 1) * D.lda + D.k : 0);
-    const uint8_t *b_lo = D.B, *b_hi = D.B + (D.k > 0 && D.n > 0 ? (int64_t)(D.k - 1) * D.ldb + D.n : 0);
+    const int kp = D.kp;
+    const int stages = (kp + KT - 1) / KT;
+
+    // Thread tid stages the 16-byte segment seg = tid % 8 of rows tid / 8 + 32 i: the
+    // same k offset in every row, so one predicate per stage covers all its loads.
+    static_assert(A_SEGS % NT == 0 && B_SEGS % NT == 0, "whole rows per load step");
+    constexpr int RSTEP = NT / SEGS;
+    const int seg = tid % SEGS, rfirst = tid / SEGS;
+    const int8_t *a_base = D.Ac + (row0 + rfirst) * kp + 16 * seg;
+    const int8_t *b_base = D.Bt + (col0 + rfirst) * kp + 16 * seg;
+    const int slot = rfirst * PT + 16 * seg;
+    const int64_t rstride = (int64_t)RSTEP * kp;
+    ix4 ra[A_LOADS], rb[B_LOADS];
+    auto fetch = [&](int st) __attribute__((always_inline)) {
+        const int k0 = st * KT;
+        const bool ok = k0 + 16 * seg < kp;
+#pragma unroll
+        for (int i = 0; i < A_LOADS; ++i) ra[i] = ok ? gload16(a_base + i * rstride + k0) : ix4{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < B_LOADS; ++i) rb[i] = ok ? gload16(b_base + i * rstride + k0) : ix4{0, 0, 0, 0};
+    };
+
     ix16 acc[FM][FN];
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
         for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
-
-    for (int k0 = 0; k0 < D.k; k0 += KC) {
-        uint4 ra[A_PER], rb[B_PER][4];
+    fetch(0);  // with kp = 0 nothing is loaded
+    for (int st = 0; st < stages; ++st) {
 #pragma unroll
-        for (int i = 0; i < A_PER; ++i) {
-            const int c = tid + NT * i;
-            const int r = c / (KC / 16), s = c % (KC / 16);
-            const int64_t row = row0 + r;
-            const int kk = k0 + 16 * s;
-            ra[i] = (c < A_SEGS && row < D.m && kk < D.k) ? load16(D.A + row * D.lda + kk, D.k - kk, a_lo, a_hi)
-                                                          : make_uint4(0, 0, 0, 0);
-        }
+        for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
 #pragma unroll
-        for (int i = 0; i < B_PER; ++i) {
-            const int c = tid + NT * i;
-            const int kq = c / (BN / 16), cg = c % (BN / 16);
-            const int64_t col = col0 + 16 * cg;
-            const int cvalid = (int)(D.n - col);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int kk = k0 + 4 * kq + j;
-                rb[i][j] = (c < B_ITEMS && kk < D.k && cvalid > 0)
-                               ? load16(D.B + (int64_t)kk * D.ldb + col, cvalid, b_lo, b_hi)
-                               : make_uint4(0, 0, 0, 0);
-            }
-        }
-        __syncthreads();  // the previous batch's MFMAs are done with LDS
-#pragma unroll
-        for (int i = 0; i < A_PER; ++i) {
-            const int c = tid + NT * i;
-            if (c >= A_SEGS) continue;
-            uint4 v = ra[i];
-            v.x = centre4(v.x, D.add_h, D.neg_p);
-            v.y = centre4(v.y, D.add_h, D.neg_p);
-            v.z = centre4(v.z, D.add_h, D.neg_p);
-            v.w = centre4(v.w, D.add_h, D.neg_p);
-            *(uint4 *)&sA[(c / (KC / 16)) * PC + 16 * (c % (KC / 16))] = v;
-        }
-#pragma unroll
-        for (int i = 0; i < B_PER; ++i) {
-            const int c = tid + NT * i;
-            if (c >= B_ITEMS) continue;
-            const int kq = c / (BN / 16), cg = c % (BN / 16);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // dword q of each of the 4 rows: columns 16 cg + 4 q .. + 3
-                const uint32_t r0 = lane_word(rb[i][0], q), r1 = lane_word(rb[i][1], q);
-                const uint32_t r2 = lane_word(rb[i][2], q), r3 = lane_word(rb[i][3], q);
-                const uint32_t lo01 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);  // r0b0 r1b0 r0b1 r1b1
-                const uint32_t lo23 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
-                const uint32_t hi01 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);  // r0b2 r1b2 r0b3 r1b3
-                const uint32_t hi23 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
-                uint32_t colw[4];
-                colw[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
-                colw[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
-                colw[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
-                colw[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    *(uint32_t *)&sB[(16 * cg + 4 * q + b) * PC + 4 * kq] = centre4(colw[b], D.add_h, D.neg_p);
-            }
-        }
+        for (int i = 0; i < B_LOADS; ++i) *(ix4 *)&lds[BM * PT + slot + i * RSTEP * PT] = rb[i];
         __syncthreads();
-        const int ksteps = (min(KC, D.k - k0) + 31) / 32;
+        if (st + 1 < stages) fetch(st + 1);
+        const uint8_t *sA = lds, *sB = lds + BM * PT;
+        const int ksteps = min(KT, kp - st * KT) / 32;
         for (int ks = 0; ks < ksteps; ++ks) {
             ix4 bf[FN];
 #pragma unroll
             for (int ni = 0; ni < FN; ++ni)
-                bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PC + ks * 32 + 16 * (lane >> 5)];
+                bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
 #pragma unroll
             for (int mi = 0; mi < FM; ++mi) {
-                const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PC + ks * 32 + 16 * (lane >> 5)];
+                const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
 #pragma unroll
                 for (int ni = 0; ni < FN; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
             }
         }
+        __syncthreads();  // the stage's LDS is read before the next one (or tile) overwrites it
     }
-    __syncthreads();  // LDS is free for the next tile
-    // lane l, register r holds D[8 (r/4) + 4 (l/32) + r % 4][l % 32]
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
@@ -213,7 +283,7 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
                 const int64_t row = row0 + wm * WTM + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int64_t col = col0 + wn * WTN + ni * 32 + (lane & 31);
                 if (row < D.m && col < D.n)
-                    D.C[row * D.ldc + col] = (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
+                    *(QMM_GLOBAL uint8_t *)(D.C + row * D.ldc + col) = (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
             }
 }
 
@@ -304,14 +374,13 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
 template <uint32_t SHAPE>
-__global__ __launch_bounds__(NT) void batched_int8_kernel(const Desc *__restrict__ descs,
+__global__ __launch_bounds__(NT, 8) void batched_int8_kernel(const Desc *__restrict__ descs,
                                                           const TileRef *__restrict__ tiles, int32_t ntiles) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PC];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PT];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
-        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_bm(SHAPE) / 32, shape_bn(SHAPE) / 32>(D, tr.tm, tr.tn, lds,
-                                                                                              lds + shape_bm(SHAPE) * PC);
+        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_bm(SHAPE) / 32, shape_bn(SHAPE) / 32>(D, tr.tm, tr.tn, lds);
     }
 }
 
@@ -326,8 +395,8 @@ __global__ __launch_bounds__(NT) void batched_fp64_kernel(const Desc *__restrict
 }
 
 // Autotuner cost model of one INT8 tile: a fixed part (tile set-up, epilogue) and a
-// part per 64-byte K stage, in units of one K stage of the 64 x 64 shape.  Every
-// shape does the same MFMA work per stage (four 16x16x64 blocks per wavefront);
+// part per 128-byte K stage, in units of one K stage of the 64 x 64 shape.  Every
+// shape does the same MFMA work per stage (four 32x32x32 blocks per wavefront);
 // the defaults are the analytic prior and qmm_batched_tune replaces them with a
 // fit to timed launches of each shape.
 struct ShapeCost {
@@ -337,7 +406,7 @@ ShapeCost g_costs[SHAPE_COUNT] = {{2.0, 1.0}, {2.0, 1.1}, {2.0, 1.1}};
 
 double tile_cost(uint32_t shape, int64_t m, int64_t n, int64_t k) {
     const int64_t tiles = ceil_div(m, shape_bm(shape)) * ceil_div(n, shape_bn(shape));
-    return (double)tiles * (g_costs[shape].fixed + g_costs[shape].per_stage * (double)ceil_div(k, KB));
+    return (double)tiles * (g_costs[shape].fixed + g_costs[shape].per_stage * (double)ceil_div(k, KT));
 }
 
 uint32_t tune_shape(int64_t m, int64_t n, int64_t k) {
@@ -371,6 +440,10 @@ struct qmm_batched {
     Desc *d_desc = nullptr;
     TileRef *d_tiles = nullptr;
     int32_t ntiles = 0;
+    PackJob *d_jobs = nullptr;
+    int32_t njobs = 0;
+    int8_t *d_ws = nullptr;   // centred, padded INT8 operands
+    size_t ws_bytes = 0;
     int32_t class_first[kClasses] = {0, 0, 0, 0}, class_count[kClasses] = {0, 0, 0, 0};
     hipStream_t streams[kClasses] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
@@ -391,6 +464,8 @@ void release(qmm_batched *b) {
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->d_ws) (void)hipFree(b->d_ws);
     delete b;
 }
 
@@ -399,6 +474,9 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     b->plans.resize((size_t)count);
     std::vector<Desc> descs((size_t)count);
     std::vector<std::pair<double, TileRef>> tiles[kClasses];
+    std::vector<PackJob> jobs;
+    std::vector<size_t> a_off((size_t)count, 0), b_off((size_t)count, 0);
+    size_t ws = 0;
     for (int64_t i = 0; i < count; ++i) {
         const qmm_problem &P = probs[i];
         if (P.p < 2 || P.p > 256) return fail(QMM_EINVAL, "problem " + std::to_string(i) + ": byte residues need 2 <= p <= 256");
@@ -433,7 +511,6 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         D.magic = mod_magic(P.p);
         D.off = P.p * ((1u << 31) / P.p);
         D.invp = 1.0 / (double)P.p;
-        D.a_vec = ((uintptr_t)P.A % 16 == 0) && (P.lda % 16 == 0);
         int bm = 64, bn = 64;
         if (pl.path == QMM_PATH_INT8) {
             const uint32_t h = (P.p - 1) / 2;
@@ -452,6 +529,20 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         }
         b->plans[(size_t)i] = pl;
         if (P.m == 0 || P.n == 0) continue;
+        if (pl.path == QMM_PATH_INT8) {
+            // workspace: Ac (mp x kp) then Bt (np x kp), each 256-byte aligned
+            D.kp = (int32_t)(ceil_div(P.k, KP_ALIGN) * KP_ALIGN);
+            D.mp = (int32_t)(ceil_div(P.m, bm) * bm);
+            D.np = (int32_t)(ceil_div(P.n, bn) * bn);
+            a_off[(size_t)i] = ws;
+            ws += (size_t)ceil_div((int64_t)D.mp * D.kp, 256) * 256;
+            b_off[(size_t)i] = ws;
+            ws += (size_t)ceil_div((int64_t)D.np * D.kp, 256) * 256;
+            for (int32_t r0 = 0; r0 < D.mp; r0 += 64)
+                for (int32_t c0 = 0; c0 < D.kp; c0 += PACK_K) jobs.push_back(PackJob{(int32_t)i, 0, r0, c0});
+            for (int32_t r0 = 0; r0 < D.kp; r0 += PACK_K)
+                for (int32_t c0 = 0; c0 < D.np; c0 += 64) jobs.push_back(PackJob{(int32_t)i, 1, r0, c0});
+        }
         const int32_t tmax = (int32_t)ceil_div(P.m, bm), nmax = (int32_t)ceil_div(P.n, bn);
         const double cost = pl.path == QMM_PATH_INT8 ? tile_cost(D.shape, bm, bn, P.k)
                                                      : (double)ceil_div(words_for(P.k < 1 ? 1 : P.k, pl.d), KW) * 4.0;
@@ -470,6 +561,23 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     b->ntiles = (int32_t)flat.size();
 
     hipError_t e;
+    if (jobs.size() > (size_t)INT32_MAX) return fail(QMM_EUNSUPPORTED, "batch too large");
+    b->njobs = (int32_t)jobs.size();
+    b->ws_bytes = ws;
+    if (ws > 0) {
+        if ((e = hipMalloc(&b->d_ws, ws)) != hipSuccess) return hip_fail(e, "hipMalloc (workspace)");
+        for (int64_t i = 0; i < count; ++i) {
+            Desc &D = descs[(size_t)i];
+            if (D.path != QMM_PATH_INT8 || D.m == 0 || D.n == 0) continue;
+            D.Ac = b->d_ws + a_off[(size_t)i];
+            D.Bt = b->d_ws + b_off[(size_t)i];
+        }
+    }
+    if (!jobs.empty()) {
+        if ((e = hipMalloc(&b->d_jobs, sizeof(PackJob) * jobs.size())) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMemcpy(b->d_jobs, jobs.data(), sizeof(PackJob) * jobs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy");
+    }
     if ((e = hipMalloc(&b->d_desc, sizeof(Desc) * std::max<size_t>(1, descs.size()))) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMalloc(&b->d_tiles, sizeof(TileRef) * std::max<size_t>(1, flat.size()))) != hipSuccess) return hip_fail(e, "hipMalloc");
     if (!descs.empty() && (e = hipMemcpy(b->d_desc, descs.data(), sizeof(Desc) * descs.size(), hipMemcpyHostToDevice)) != hipSuccess)
@@ -492,6 +600,10 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     hipStream_t s0 = b->streams[0];
     if ((e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e, "capture");
     hipError_t le = hipSuccess;
+    if (b->njobs > 0) {
+        batched_pack_kernel<<<b->njobs, NT, 0, s0>>>(b->d_desc, b->d_jobs);
+        le = hipGetLastError();
+    }
     (void)hipEventRecord(b->fork, s0);
     for (int c = 0; c < kClasses; ++c) {
         if (b->class_count[c] == 0) continue;
@@ -557,9 +669,9 @@ extern "C" qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream) {
 }
 
 extern "C" qmm_status qmm_batched_tune(void *stream, double *costs) {
-    // Times the persistent kernel on two synthetic batches per tile shape (a short
-    // and a long k) and fits cost = fixed + per_stage * stages per tile, in units of
-    // one 64-byte stage of the 64 x 64 shape.
+    // Times whole batches (pack and product) on two synthetic workloads per tile
+    // shape (a short and a long k) and fits cost = fixed + per_stage * stages per
+    // tile, in units of one 128-byte stage of the 64 x 64 shape.
     const int64_t mm = 256, nn = 256, reps = 10;
     const int64_t ks[2] = {128, 1024};
     const int count = 256;
@@ -602,7 +714,7 @@ extern "C" qmm_status qmm_batched_tune(void *stream, double *costs) {
     (void)hipFree(buf);
     if (st != QMM_OK) return st;
     // per-tile time = fixed + per_stage * stages; unit: one stage of the 64 x 64 shape
-    const double s0 = (double)ceil_div(ks[0], KB), s1 = (double)ceil_div(ks[1], KB);
+    const double s0 = (double)ceil_div(ks[0], KT), s1 = (double)ceil_div(ks[1], KT);
     const double unit = (ms[0][1] - ms[0][0]) / (s1 - s0);
     if (!(unit > 0)) return fail(QMM_EDEVICE, "tuning runs gave no usable timing");
     for (uint32_t sh = 0; sh < SHAPE_COUNT; ++sh) {
