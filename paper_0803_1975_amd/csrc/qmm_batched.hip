@@ -433,6 +433,7 @@ using namespace qmm;
 
 // Tile classes: the three INT8 shapes and the FP64 Q-adic tile.
 constexpr int kClasses = SHAPE_COUNT + 1;
+constexpr int kXcds = 8;  // accelerator complex dies, one L2 each
 
 struct qmm_batched {
     int64_t count = 0;
@@ -550,17 +551,45 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         for (int32_t tm = 0; tm < tmax; ++tm)
             for (int32_t tn = 0; tn < nmax; ++tn) tiles[cls].push_back({cost, TileRef{(int32_t)i, tm, tn, 0}});
     }
-    // per class, longest first (stable, so the order is deterministic)
+    hipError_t e;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return hip_fail(e, "attribute");
+    // persistent grid of each class: as many workgroups as fit the CUs at once
+    const void *kfun[kClasses] = {(const void *)batched_int8_kernel<SHAPE_64x64>,
+                                  (const void *)batched_int8_kernel<SHAPE_32x128>,
+                                  (const void *)batched_int8_kernel<SHAPE_128x32>, (const void *)batched_fp64_kernel};
+    int grid[kClasses];
+    for (int c = 0; c < kClasses; ++c) {
+        int per_cu = 1;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfun[c], NT, 0);
+        grid[c] = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)tiles[c].size(), (int64_t)cus * std::max(1, per_cu)));
+    }
+    // Per class, longest first (stable, so the tiles of a product stay together).
+    // Workgroup w takes list entries w, w + G, ...; the hardware hands workgroups
+    // to the XCDs round-robin (w mod 8), and each XCD has its own L2.  Within every
+    // full round of G entries the sorted tiles are placed XCD-major, so the tiles
+    // of one product run at the same time on one XCD and share its L2 copy of the
+    // product's operand panels.
     std::vector<TileRef> flat;
     for (int c = 0; c < kClasses; ++c) {
         std::stable_sort(tiles[c].begin(), tiles[c].end(), [](const auto &a, const auto &b) { return a.first > b.first; });
-        b->class_first[c] = (int32_t)flat.size();
-        b->class_count[c] = (int32_t)tiles[c].size();
-        for (const auto &t : tiles[c]) flat.push_back(t.second);
+        const int64_t first = (int64_t)flat.size(), nt = (int64_t)tiles[c].size(), G = grid[c];
+        b->class_first[c] = (int32_t)first;
+        b->class_count[c] = (int32_t)nt;
+        flat.resize((size_t)(first + nt));
+        for (int64_t i = 0; i < nt; ++i) {
+            const int64_t round = i / G, q = i % G;
+            int64_t slot = q;
+            if ((round + 1) * G <= nt && G % kXcds == 0) {
+                const int64_t per = G / kXcds;
+                slot = kXcds * (q % per) + q / per;
+            }
+            flat[(size_t)(first + round * G + slot)] = tiles[c][(size_t)i].second;
+        }
     }
     b->ntiles = (int32_t)flat.size();
 
-    hipError_t e;
     if (jobs.size() > (size_t)INT32_MAX) return fail(QMM_EUNSUPPORTED, "batch too large");
     b->njobs = (int32_t)jobs.size();
     b->ws_bytes = ws;
@@ -585,10 +614,6 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     if (!flat.empty() && (e = hipMemcpy(b->d_tiles, flat.data(), sizeof(TileRef) * flat.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "hipMemcpy");
 
-    int dev = 0, cus = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return hip_fail(e, "attribute");
-
     // Record the launches in one graph: the classes' persistent kernels are
     // parallel branches between a fork and a join.  The schedule is static, so
     // the graph holds only kernel nodes and nothing needs clearing between replays.
@@ -612,24 +637,11 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         const Desc *dd = b->d_desc;
         const TileRef *tt = b->d_tiles + b->class_first[c];
         const int32_t nt = b->class_count[c];
-        int per_cu = 1;
         switch (c) {
-        case SHAPE_64x64:
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_int8_kernel<SHAPE_64x64>, NT, 0);
-            batched_int8_kernel<SHAPE_64x64><<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
-            break;
-        case SHAPE_32x128:
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_int8_kernel<SHAPE_32x128>, NT, 0);
-            batched_int8_kernel<SHAPE_32x128><<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
-            break;
-        case SHAPE_128x32:
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_int8_kernel<SHAPE_128x32>, NT, 0);
-            batched_int8_kernel<SHAPE_128x32><<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
-            break;
-        default:
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_fp64_kernel, NT, 0);
-            batched_fp64_kernel<<<std::max(1, std::min(nt, cus * std::max(1, per_cu))), NT, 0, sc>>>(dd, tt, nt);
-            break;
+        case SHAPE_64x64: batched_int8_kernel<SHAPE_64x64><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case SHAPE_32x128: batched_int8_kernel<SHAPE_32x128><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case SHAPE_128x32: batched_int8_kernel<SHAPE_128x32><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        default: batched_fp64_kernel<<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
         }
         if (le == hipSuccess) le = hipGetLastError();
         if (c != 0) {
