@@ -224,7 +224,8 @@ def run_batched(args, torch, qmm):
 
     results = {}
     ref_out = None
-    for name, flags in (("chosen", 0), ("fp64_qadic_batched", qmm.BATCH_FORCE_FP64)):
+    # chosen: the autotuner's cost model, then its measuring stage on this batch
+    for name, flags in (("chosen", qmm.BATCH_MEASURE), ("fp64_qadic_batched", qmm.BATCH_FORCE_FP64)):
         batch = qmm.batched_create(dev, flags)
         batch.run()
         torch.cuda.synchronize()

@@ -209,10 +209,18 @@ typedef struct qmm_batched qmm_batched;
  * instead of letting the autotuner pick it per product.  Products whose k would
  * need blocked int32 accumulation are refused (QMM_EUNSUPPORTED). */
 #define QMM_BATCH_FORCE_FP64   1u
-#define QMM_BATCH_SHAPE_64x64  0x100u
-#define QMM_BATCH_SHAPE_32x128 0x200u
-#define QMM_BATCH_SHAPE_128x32 0x300u
-#define QMM_BATCH_SHAPE_MASK   0x300u
+#define QMM_BATCH_SHAPE_64x64   0x100u
+#define QMM_BATCH_SHAPE_32x128  0x200u
+#define QMM_BATCH_SHAPE_128x32  0x300u
+#define QMM_BATCH_SHAPE_128x128 0x400u
+#define QMM_BATCH_SHAPE_MASK    0x700u  /* other values under the mask are EINVAL */
+/* QMM_BATCH_MEASURE: the autotuner's second stage.  Builds the cost-model
+ * assignment and one batch per uniform INT8 tile shape, times each (three graph
+ * replays after a warm-up, on a private stream, synchronised) on the problems' own
+ * buffers, and keeps the fastest.  Every candidate computes the same C_i, so the
+ * outputs hold the products when the call returns.  Not combinable with
+ * QMM_BATCH_FORCE_FP64 or QMM_BATCH_SHAPE_* (EINVAL). */
+#define QMM_BATCH_MEASURE       0x1000u
 qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t flags,
                               qmm_batched **out);
 
@@ -222,16 +230,16 @@ qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream);
 /* Autotuner calibration: times whole batches of each INT8 tile shape on
  * synthetic products (allocating and freeing its own device buffers,
  * synchronising `stream`) and fits per-tile cost = fixed + per_stage * (k / 128).
- * Later qmm_batched_create calls use the fit.  costs (may be NULL) receives 6
- * doubles: (fixed, per_stage) for 64x64, 32x128 and 128x32, in units of one
- * 128-byte K stage of a 64x64 tile. */
+ * Later qmm_batched_create calls use the fit.  costs (may be NULL) receives 8
+ * doubles: (fixed, per_stage) for 64x64, 32x128, 128x32 and 128x128, in units of
+ * one 128-byte K stage of a 64x64 tile. */
 qmm_status qmm_batched_tune(void *stream, double *costs);
 
-/* Installs previously measured costs (6 doubles, as qmm_batched_tune returns). */
+/* Installs previously measured costs (8 doubles, as qmm_batched_tune returns). */
 qmm_status qmm_batched_set_costs(const double *costs);
 
 /* Plan chosen for product i of the batch (host copy); plan->tile holds the INT8
- * tile shape (0 = 64x64, 1 = 32x128, 2 = 128x32). */
+ * tile shape (0 = 64x64, 1 = 32x128, 2 = 128x32, 3 = 128x128). */
 qmm_status qmm_batched_plan(const qmm_batched *batch, int64_t i, qmm_plan *out);
 
 /* Frees the batch's device memory and graph.  NULL is accepted. */

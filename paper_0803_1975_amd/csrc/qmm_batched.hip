@@ -51,9 +51,11 @@ constexpr int NT = 256;
 constexpr int KW = 16;          // FP64 K stage (packed words)
 
 // Tile shapes of the batched kernel (rows x columns of C per tile).
-enum Shape : uint32_t { SHAPE_64x64 = 0, SHAPE_32x128 = 1, SHAPE_128x32 = 2, SHAPE_COUNT = 3 };
-constexpr int shape_bm(uint32_t s) { return s == SHAPE_32x128 ? 32 : (s == SHAPE_128x32 ? 128 : 64); }
-constexpr int shape_bn(uint32_t s) { return s == SHAPE_32x128 ? 128 : (s == SHAPE_128x32 ? 32 : 64); }
+enum Shape : uint32_t { SHAPE_64x64 = 0, SHAPE_32x128 = 1, SHAPE_128x32 = 2, SHAPE_128x128 = 3, SHAPE_COUNT = 4 };
+constexpr int shape_bm(uint32_t s) { return s == SHAPE_32x128 ? 32 : (s == SHAPE_64x64 ? 64 : 128); }
+constexpr int shape_bn(uint32_t s) { return s == SHAPE_128x32 ? 32 : (s == SHAPE_64x64 ? 64 : 128); }
+// wavefront grid of a shape: 2 x 2 for the square tiles, 1 x 4 / 4 x 1 for the thin ones
+constexpr int shape_wgm(uint32_t s) { return s == SHAPE_32x128 ? 1 : (s == SHAPE_128x32 ? 4 : 2); }
 
 struct Desc {
     const uint8_t *A;
@@ -274,17 +276,33 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
         }
         __syncthreads();  // the stage's LDS is read before the next one (or tile) overwrites it
     }
+    // Epilogue: every C offset of a product fits 32 bits (checked on the host), so a
+    // store is a uniform base plus one 32-bit lane offset; interior tiles skip the
+    // bounds checks.  Register r of a block holds row 8 (r/4) + 4 (l/32) + r % 4.
+    QMM_GLOBAL uint8_t *cbase = (QMM_GLOBAL uint8_t *)D.C;
+    const uint32_t ldc = (uint32_t)D.ldc;
+    const bool full = row0 + BM <= D.m && col0 + BN <= D.n;
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < FN; ++ni)
+        for (int ni = 0; ni < FN; ++ni) {
+            const uint32_t rl = (uint32_t)(row0 + wm * WTM + mi * 32 + 4 * (lane >> 5));
+            const uint32_t cl = (uint32_t)(col0 + wn * WTN + ni * 32 + (lane & 31));
+            const uint32_t off0 = rl * ldc + cl;
+            if (full) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = row0 + wm * WTM + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t col = col0 + wn * WTN + ni * 32 + (lane & 31);
-                if (row < D.m && col < D.n)
-                    *(QMM_GLOBAL uint8_t *)(D.C + row * D.ldc + col) = (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
+                for (int r = 0; r < 16; ++r)
+                    cbase[off0 + (uint32_t)(8 * (r >> 2) + (r & 3)) * ldc] =
+                        (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const uint32_t rr = (uint32_t)(8 * (r >> 2) + (r & 3));
+                    if (rl + rr < (uint32_t)D.m && cl < (uint32_t)D.n)
+                        cbase[off0 + rr * ldc] = (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
+                }
             }
+        }
 }
 
 // One FP64 Q-adic tile of 64 x 64 outputs: rows of A packed reversed and columns
@@ -374,13 +392,13 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
 template <uint32_t SHAPE>
-__global__ __launch_bounds__(NT, 8) void batched_int8_kernel(const Desc *__restrict__ descs,
+__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : 8) void batched_int8_kernel(const Desc *__restrict__ descs,
                                                           const TileRef *__restrict__ tiles, int32_t ntiles) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PT];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
-        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_bm(SHAPE) / 32, shape_bn(SHAPE) / 32>(D, tr.tm, tr.tn, lds);
+        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_wgm(SHAPE), 4 / shape_wgm(SHAPE)>(D, tr.tm, tr.tn, lds);
     }
 }
 
@@ -402,7 +420,7 @@ __global__ __launch_bounds__(NT) void batched_fp64_kernel(const Desc *__restrict
 struct ShapeCost {
     double fixed, per_stage;
 };
-ShapeCost g_costs[SHAPE_COUNT] = {{2.0, 1.0}, {2.0, 1.1}, {2.0, 1.1}};
+ShapeCost g_costs[SHAPE_COUNT] = {{2.0, 1.0}, {2.0, 1.1}, {2.0, 1.1}, {3.0, 3.0}};
 
 double tile_cost(uint32_t shape, int64_t m, int64_t n, int64_t k) {
     const int64_t tiles = ceil_div(m, shape_bm(shape)) * ceil_div(n, shape_bn(shape));
@@ -445,9 +463,9 @@ struct qmm_batched {
     int32_t njobs = 0;
     int8_t *d_ws = nullptr;   // centred, padded INT8 operands
     size_t ws_bytes = 0;
-    int32_t class_first[kClasses] = {0, 0, 0, 0}, class_count[kClasses] = {0, 0, 0, 0};
-    hipStream_t streams[kClasses] = {nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t class_first[kClasses] = {}, class_count[kClasses] = {};
+    hipStream_t streams[kClasses] = {};
+    hipEvent_t fork = nullptr, join[kClasses] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -496,6 +514,9 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         if (pl.path == QMM_PATH_INT8 && pl.k_block < P.k)
             return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": k needs blocked int32 accumulation, "
                                           "which the batched kernel does not do");
+        if (pl.path == QMM_PATH_INT8 && P.m > 0 && P.n > 0 && (P.m - 1) * P.ldc + P.n > (int64_t)UINT32_MAX)
+            return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": C spans more than 2^32 bytes, "
+                                          "past the batched kernel's 32-bit output offsets");
         Desc &D = descs[(size_t)i];
         std::memset(&D, 0, sizeof(D));
         D.A = P.A;
@@ -517,7 +538,7 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
             const uint32_t h = (P.p - 1) / 2;
             D.add_h = (127u - h) * 0x01010101u;
             D.neg_p = (256u - P.p) & 0xffu;
-            const uint32_t forced = (flags & QMM_BATCH_SHAPE_MASK) >> 8;
+            const uint32_t forced = (flags & QMM_BATCH_SHAPE_MASK) >> 8;  // 1 + shape, 0 = autotuned
             D.shape = forced ? forced - 1 : tune_shape(P.m, P.n, P.k);
             pl.tile = D.shape;
             bm = shape_bm(D.shape);
@@ -558,7 +579,8 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     // persistent grid of each class: as many workgroups as fit the CUs at once
     const void *kfun[kClasses] = {(const void *)batched_int8_kernel<SHAPE_64x64>,
                                   (const void *)batched_int8_kernel<SHAPE_32x128>,
-                                  (const void *)batched_int8_kernel<SHAPE_128x32>, (const void *)batched_fp64_kernel};
+                                  (const void *)batched_int8_kernel<SHAPE_128x32>,
+                                  (const void *)batched_int8_kernel<SHAPE_128x128>, (const void *)batched_fp64_kernel};
     int grid[kClasses];
     for (int c = 0; c < kClasses; ++c) {
         int per_cu = 1;
@@ -641,6 +663,7 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         case SHAPE_64x64: batched_int8_kernel<SHAPE_64x64><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
         case SHAPE_32x128: batched_int8_kernel<SHAPE_32x128><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
         case SHAPE_128x32: batched_int8_kernel<SHAPE_128x32><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case SHAPE_128x128: batched_int8_kernel<SHAPE_128x128><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
         default: batched_fp64_kernel<<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
         }
         if (le == hipSuccess) le = hipGetLastError();
@@ -657,11 +680,73 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
 
 }  // namespace
 
+namespace {
+
+// Mean time of `reps` replays of a batch's graph on `stream` (after one warm-up).
+qmm_status time_batch(qmm_batched *b, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, int reps, float *ms) {
+    hipError_t e;
+    if (b->ntiles == 0) {
+        *ms = 0.f;
+        return QMM_OK;
+    }
+    if ((e = hipGraphLaunch(b->exec, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if ((e = hipEventRecord(e0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int r = 0; r < reps; ++r)
+        if ((e = hipGraphLaunch(b->exec, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if ((e = hipEventRecord(e1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    if ((e = hipEventElapsedTime(ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    *ms /= (float)reps;
+    return QMM_OK;
+}
+
+// QMM_BATCH_MEASURE: build the cost-model assignment and one batch per uniform
+// tile shape, time each on the batch's own buffers (every candidate writes the
+// same, correct C_i), keep the fastest.
+qmm_status create_measured(int64_t count, const qmm_problem *probs, uint32_t flags, qmm_batched **out) {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    qmm_status st = QMM_OK;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) st = hip_fail(e, "event");
+    qmm_batched *best = nullptr;
+    float best_ms = 0.f;
+    for (uint32_t c = 0; c <= SHAPE_COUNT && st == QMM_OK; ++c) {
+        qmm_batched *b = new qmm_batched();
+        st = build_batch(count, probs, flags | (c << 8), b);  // c = 0: cost model; c >= 1: shape c - 1 everywhere
+        float ms = 0.f;
+        if (st == QMM_OK) st = time_batch(b, s, e0, e1, 3, &ms);
+        if (st == QMM_OK && (!best || ms < best_ms)) {
+            release(best);
+            best = b;
+            best_ms = ms;
+        } else {
+            release(b);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    if (st != QMM_OK) {
+        release(best);
+        return st;
+    }
+    *out = best;
+    return QMM_OK;
+}
+
+}  // namespace
+
 extern "C" qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t flags, qmm_batched **out) {
     if (!out) return fail(QMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 0 || (count > 0 && !probs)) return fail(QMM_EINVAL, "bad problem array");
-    if (flags & ~(QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK)) return fail(QMM_EINVAL, "unknown flags");
+    if (flags & ~(QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK | QMM_BATCH_MEASURE)) return fail(QMM_EINVAL, "unknown flags");
+    if (((flags & QMM_BATCH_SHAPE_MASK) >> 8) > SHAPE_COUNT) return fail(QMM_EINVAL, "unknown tile shape flag");
+    if ((flags & QMM_BATCH_MEASURE) && (flags & (QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK)))
+        return fail(QMM_EINVAL, "QMM_BATCH_MEASURE chooses the INT8 tile shapes itself");
+    if (flags & QMM_BATCH_MEASURE) return create_measured(count, probs, flags & ~QMM_BATCH_MEASURE, out);
     qmm_batched *b = new qmm_batched();
     const qmm_status st = build_batch(count, probs, flags, b);
     if (st != QMM_OK) {

@@ -25,7 +25,9 @@ REGIME_NAMES = {0: "exact", 1: "offset", 2: "paper", 3: "int"}
 # flags
 BOUND_PROVEN, BOUND_PAPER, PLAN_UNBLOCKED, BOUND_G4, BOUND_EQ4 = 0, 1, 2, 4, 8
 BATCH_FORCE_FP64 = 1
-BATCH_SHAPE_64x64, BATCH_SHAPE_32x128, BATCH_SHAPE_128x32 = 0x100, 0x200, 0x300
+BATCH_SHAPE_64x64, BATCH_SHAPE_32x128, BATCH_SHAPE_128x32, BATCH_SHAPE_128x128 = 0x100, 0x200, 0x300, 0x400
+BATCH_MEASURE = 0x1000
+N_BATCH_COSTS = 8  # (fixed, per_stage) for each of the four INT8 tile shapes
 # unpack selectors
 ROWS_REV, COLS_FWD, ROWS_FWD = 0, 1, 2
 
@@ -350,12 +352,14 @@ def batched_create(problems, flags=0) -> Batch:
 
 
 def batched_tune(stream=None):
-    """Calibrate the batched autotuner on this GPU; returns the 6 fitted costs."""
-    out = (ctypes.c_double * 6)()
+    """Calibrate the batched autotuner on this GPU; returns the 8 fitted costs."""
+    out = (ctypes.c_double * N_BATCH_COSTS)()
     _check(lib().qmm_batched_tune(_stream(stream), out), "qmm_batched_tune")
     return list(out)
 
 
 def batched_set_costs(costs):
-    arr = (ctypes.c_double * 6)(*costs)
+    if len(costs) != N_BATCH_COSTS:
+        raise ValueError(f"expected {N_BATCH_COSTS} costs, got {len(costs)}")
+    arr = (ctypes.c_double * N_BATCH_COSTS)(*costs)
     _check(lib().qmm_batched_set_costs(arr), "qmm_batched_set_costs")

@@ -84,3 +84,23 @@ def test_plans_that_break_the_bounds_are_refused():
         assert qmm.validate_plan(tiled, 4, 4, 200000) == want, tile
     with pytest.raises(qmm.QmmError):
         qmm.choose_Qd(300, 4, 4, 4, path=qmm.PATH_INT8)
+
+
+def test_batched_argument_checks():
+    # flags and cost vectors are checked on the host, before any device call
+    L = qmm.lib()
+    out = ctypes.c_void_p()
+    for bad in (0x500, 0x700, 0x800, 2):
+        assert L.qmm_batched_create(0, None, bad, ctypes.byref(out)) == qmm.EINVAL, hex(bad)
+        assert not out.value
+    for bad in (qmm.BATCH_MEASURE | qmm.BATCH_FORCE_FP64, qmm.BATCH_MEASURE | qmm.BATCH_SHAPE_128x128):
+        assert L.qmm_batched_create(0, None, bad, ctypes.byref(out)) == qmm.EINVAL, hex(bad)
+    assert L.qmm_batched_create(0, None, 0, None) == qmm.EINVAL
+    assert L.qmm_batched_create(-1, None, 0, ctypes.byref(out)) == qmm.EINVAL
+    with pytest.raises(qmm.QmmError):
+        qmm.batched_set_costs([1.0, 1.0, 1.0, 1.0, 1.0, -1.0, 1.0, 1.0])
+    with pytest.raises(qmm.QmmError):
+        qmm.batched_set_costs([1.0, 0.0] * 4)  # per-stage costs must be positive
+    with pytest.raises(ValueError):
+        qmm.batched_set_costs([1.0] * 6)
+    assert L.qmm_batched_destroy(None) == qmm.OK

@@ -49,7 +49,7 @@ EDGE_SHAPES = [(7, 1, 1, 1), (3, 16, 16, 16), (101, 17, 33, 5), (2, 513, 31, 70)
 
 
 @pytest.mark.parametrize("flags", [0, qmm.BATCH_SHAPE_64x64, qmm.BATCH_SHAPE_32x128, qmm.BATCH_SHAPE_128x32,
-                                   qmm.BATCH_FORCE_FP64])
+                                   qmm.BATCH_SHAPE_128x128, qmm.BATCH_FORCE_FP64])
 def test_batched_edge_shapes(torch, flags):
     note("edge", flags)
     host, dev = make_problems(torch, EDGE_SHAPES, 10 + flags)
@@ -107,14 +107,32 @@ def test_batched_workload_2000_products(torch):
 def test_autotuner_calibration_and_choices(torch):
     costs = qmm.batched_tune()
     note("costs", costs)
-    assert len(costs) == 6 and all(c >= 0 for c in costs) and all(costs[i] > 0 for i in (1, 3, 5))
+    assert len(costs) == qmm.N_BATCH_COSTS and all(c >= 0 for c in costs) and all(costs[i] > 0 for i in (1, 3, 5, 7))
     qmm.batched_set_costs(costs)
-    shapes = [(7, 32, 512, 256), (7, 512, 32, 256), (7, 256, 256, 256)]
+    shapes = [(7, 32, 512, 256), (7, 512, 32, 256), (7, 256, 256, 256), (7, 512, 512, 128)]
     host, dev = make_problems(torch, shapes, 3)
     batch = qmm.batched_create(dev)
     try:
-        tiles = [batch.plan(i).tile for i in range(3)]
+        tiles = [batch.plan(i).tile for i in range(len(shapes))]
         note("tiles", tiles)
+        batch.run()
+        torch.cuda.synchronize()
+        check_all(host, dev)
+    finally:
+        batch.destroy()
+
+
+def test_measuring_autotuner_keeps_a_correct_fastest_candidate(torch):
+    shapes = synth.batched_shapes(count=200, seed=11)
+    host, dev = make_problems(torch, shapes, 11)
+    batch = qmm.batched_create(dev, qmm.BATCH_MEASURE)
+    try:
+        check_all(host, dev)                    # candidates ran on the real buffers
+        tiles = {batch.plan(i).tile for i in range(len(shapes))}
+        note("measured tiles", tiles)
+        assert tiles <= {0, 1, 2, 3}
+        for _, _, dC, _ in dev:
+            dC.fill_(255)
         batch.run()
         torch.cuda.synchronize()
         check_all(host, dev)
