@@ -123,10 +123,12 @@ __device__ __forceinline__ uint4 load16(const uint8_t *src, int valid, const uin
 
 // Pack one operand block (256 threads, four 16-byte segments each, all loads in
 // flight together).  A job: rows r0 .. r0+63 of A, k bytes c0 .. c0+255, centred,
-// zero past k and past m (rows up to mp, bytes up to kp).  B job: k rows
-// r0 .. r0+255, columns c0 .. c0+63 of B go through LDS; thread t then reads 16 k
-// rows of one 4-column word, transposes the 16 x 4 bytes in registers and writes
-// four 16-byte k-runs into rows of Bt (zero past k and past n, up to np and kp).
+// zero past k (up to kp).  B job: k rows r0 .. r0+255, columns c0 .. c0+63 of B go
+// through LDS; thread t then reads 16 k rows of one 4-column word, transposes the
+// 16 x 4 bytes in registers and writes four 16-byte k-runs into rows of Bt (zero
+// past k, up to kp).  Rows of Ac past m and rows of Bt past n (the tile padding up
+// to mp and np) are never written: they only reach outputs past m or n, which the
+// product does not store, so any bytes there will do.
 constexpr int PACK_K = 256;
 __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict__ descs,
                                                           const PackJob *__restrict__ jobs) {
@@ -136,13 +138,13 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
     const int t = threadIdx.x;
     if (J.kind == 0) {
         const int32_t row = J.r0 + (t >> 2);
-        if (row >= D.mp) return;
+        if (row >= D.m) return;
         const uint8_t *hi = D.A + (int64_t)(D.m - 1) * D.lda + D.k;
         uint4 v[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int32_t kk = J.c0 + 16 * ((t & 3) + 4 * i);
-            v[i] = (row < D.m && kk < D.k) ? load16(D.A + (int64_t)row * D.lda + kk, D.k - kk, D.A, hi)
+            v[i] = kk < D.k ? load16(D.A + (int64_t)row * D.lda + kk, D.k - kk, D.A, hi)
                                            : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int32_t orow = J.c0 + 4 * cg + q;
-        if (orow < D.np)
+        if (orow < D.n)
             *(QMM_GLOBAL uint4v *)(D.Bt + (int64_t)orow * D.kp + kk) = uint4v{out[q][0], out[q][1], out[q][2], out[q][3]};
     }
 }
@@ -560,10 +562,10 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
             ws += (size_t)ceil_div((int64_t)D.mp * D.kp, 256) * 256;
             b_off[(size_t)i] = ws;
             ws += (size_t)ceil_div((int64_t)D.np * D.kp, 256) * 256;
-            for (int32_t r0 = 0; r0 < D.mp; r0 += 64)
+            for (int32_t r0 = 0; r0 < D.m; r0 += 64)
                 for (int32_t c0 = 0; c0 < D.kp; c0 += PACK_K) jobs.push_back(PackJob{(int32_t)i, 0, r0, c0});
             for (int32_t r0 = 0; r0 < D.kp; r0 += PACK_K)
-                for (int32_t c0 = 0; c0 < D.np; c0 += 64) jobs.push_back(PackJob{(int32_t)i, 1, r0, c0});
+                for (int32_t c0 = 0; c0 < D.n; c0 += 64) jobs.push_back(PackJob{(int32_t)i, 1, r0, c0});
         }
         const int32_t tmax = (int32_t)ceil_div(P.m, bm), nmax = (int32_t)ceil_div(P.n, bn);
         const double cost = pl.path == QMM_PATH_INT8 ? tile_cost(D.shape, bm, bn, P.k)
