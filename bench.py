@@ -284,12 +284,13 @@ def run_batched(args, torch, qmm):
         "warmup": args.warmup, "ms_per_step": chosen["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "i8", "data": "synthetic",
         "config": {"workload": "batched: 2000 products, p in {2,3,5,7,11,13,31,101}, m,n,k uniform in [16,512], "
-                               "seed 4; one persistent kernel replayed from a HIP graph",
+                               "seed 4; one HIP graph replay per step (pack kernel, then one persistent "
+                               "product kernel per tile shape)",
                    "macs": macs, "residue_bytes": io_bytes, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBps"], "unit": "GB/s",
                      "frac": ach / PEAK["hbm_GBps"], "traffic": None,
-                     "kernel": "batched persistent kernel (one launch per step)",
-                     "op": "residue bytes read and written (A, B, C of every product) per launch",
+                     "kernel": "batched graph replay (pack + persistent product kernels)",
+                     "op": "residue bytes read and written (A, B, C of every product) per replay",
                      "avg_launch_ms": chosen["ms_per_step"]},
         "paths": results,
         "speedup_vs_plain_fp64_qadic": chosen["gmacs"] / results["fp64_qadic_per_product"]["gmacs"],
