@@ -45,13 +45,15 @@ __device__ __forceinline__ uint32_t centre4(uint32_t w, uint32_t add_h, uint32_t
 // Bt[n0 + c][k0 + r] = centred(B[k0 + r][n0 + c]) for a 128 (k) x 128 (n) tile:
 // each thread reads 16 consecutive bytes of four B rows (vector loads when the
 // row segments are aligned and whole, all four in flight together) into an LDS
-// tile, then gathers 64 consecutive k of one column from LDS and writes them as
-// four 16-byte stores to Bt.
+// tile of 32-bit words.  Then thread t reads the word of columns 4 cg .. 4 cg + 3
+// (cg = t % 32) in 16 consecutive k rows (k group t / 32), transposes the 16 x 4
+// bytes in registers (4 x 4 blocks by byte permutes) and writes four 16-byte
+// k-runs, one per column, into Bt.
 constexpr int CT = 128;
 __global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
                                                                 int64_t ldb, int8_t *__restrict__ Bt, int64_t ldbt,
                                                                 uint32_t add_h, uint32_t neg_p, int b_vec) {
-    __shared__ __attribute__((aligned(16))) uint8_t tile[CT][CT + 4];
+    __shared__ uint32_t tile[CT][CT / 4 + 1];  // k rows x 128 column bytes, padded by one word
     const int64_t k0 = (int64_t)blockIdx.y * CT, n0 = (int64_t)blockIdx.x * CT;
     const int t = threadIdx.x;
     {
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            uint32_t *dst = (uint32_t *)&tile[r0 + 32 * i][16 * seg];
+            uint32_t *dst = &tile[r0 + 32 * i][4 * seg];
             dst[0] = centre4(v[i].x, add_h, neg_p);
             dst[1] = centre4(v[i].y, add_h, neg_p);
             dst[2] = centre4(v[i].z, add_h, neg_p);
@@ -84,23 +86,28 @@ __global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_
         }
     }
     __syncthreads();
-    {
-        const int c = t >> 1, half = t & 1;  // column c, k-bytes 64 half .. +63
-        const int64_t nn = n0 + c;
-        if (nn < n) {
+    const int cg = t & 31, kg = t >> 5;  // columns 4 cg .. 4 cg + 3; k rows 16 kg .. 16 kg + 15
+    uint32_t out[4][4];                  // [column q][k word d]
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int kb = 64 * half + 16 * q;
-                const int64_t kk = k0 + kb;
-                if (kk < ldbt) {
-                    uint32_t w[4] = {0, 0, 0, 0};
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t r0 = tile[16 * kg + 4 * d + 0][cg], r1 = tile[16 * kg + 4 * d + 1][cg];
+        const uint32_t r2 = tile[16 * kg + 4 * d + 2][cg], r3 = tile[16 * kg + 4 * d + 3][cg];
+        const uint32_t lo01 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);  // r0b0 r1b0 r0b1 r1b1
+        const uint32_t lo23 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+        const uint32_t hi01 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);  // r0b2 r1b2 r0b3 r1b3
+        const uint32_t hi23 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+        out[0][d] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+        out[1][d] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+        out[2][d] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+        out[3][d] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+    }
+    // rows past k were loaded as zero (and centre4(0) = 0), so Bt's padding is zero
+    const int64_t kk = k0 + 16 * kg;
+    if (kk >= ldbt) return;
 #pragma unroll
-                    for (int b = 0; b < 16; ++b) w[b >> 2] |= (uint32_t)tile[kb + b][c] << (8 * (b & 3));
-                    // rows past k were loaded as zero (and centre4(0) = 0), so Bt's padding is zero
-                    *(uint4 *)(Bt + nn * ldbt + kk) = make_uint4(w[0], w[1], w[2], w[3]);
-                }
-            }
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int64_t nn = n0 + 4 * cg + q;
+        if (nn < n) *(uint4 *)(Bt + nn * ldbt + kk) = make_uint4(out[q][0], out[q][1], out[q][2], out[q][3]);
     }
 }
 

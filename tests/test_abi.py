@@ -104,3 +104,18 @@ def test_batched_argument_checks():
     with pytest.raises(ValueError):
         qmm.batched_set_costs([1.0] * 6)
     assert L.qmm_batched_destroy(None) == qmm.OK
+
+
+def test_batched_refuses_outputs_past_32_bit_offsets_before_device_work():
+    # the batched INT8 epilogue addresses C with 32-bit offsets; the host check
+    # runs in the planning loop, before any allocation or launch
+    L = qmm.lib()
+    fake = 1 << 20
+    out = ctypes.c_void_p()
+    big = qmm.Problem(m=2, n=16, k=16, p=7, A=fake, lda=16, B=fake, ldb=16, C=fake, ldc=1 << 32)
+    assert L.qmm_batched_create(1, ctypes.byref(big), 0, ctypes.byref(out)) == qmm.EUNSUPPORTED
+    assert "2^32" in qmm.last_error() and not out.value
+    bad_p = qmm.Problem(m=2, n=16, k=16, p=300, A=fake, lda=16, B=fake, ldb=16, C=fake, ldc=16)
+    assert L.qmm_batched_create(1, ctypes.byref(bad_p), 0, ctypes.byref(out)) == qmm.EINVAL
+    bad_ld = qmm.Problem(m=2, n=16, k=16, p=7, A=fake, lda=8, B=fake, ldb=16, C=fake, ldc=16)
+    assert L.qmm_batched_create(1, ctypes.byref(bad_ld), 0, ctypes.byref(out)) == qmm.EINVAL
