@@ -328,7 +328,13 @@ void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
 
 }  // namespace
 
-int64_t int8_bt_ld(int64_t k) { return ceil_div(k < 1 ? 1 : k, kBtAlign) * kBtAlign; }
+// k rounded up to the stage alignment; strides that are multiples of 2 KiB get one
+// more 128-byte line (rows of Bt at such strides crowd fewer HBM channels: the
+// conversion writes at n = k = 16384 run 1.2x faster with the extra line).
+int64_t int8_bt_ld(int64_t k) {
+    const int64_t r = ceil_div(k < 1 ? 1 : k, kBtAlign) * kBtAlign;
+    return r % 2048 == 0 ? r + kBtAlign : r;
+}
 
 qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
                                    int8_t *Bt, int64_t ldbt, void *stream) {

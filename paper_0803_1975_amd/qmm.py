@@ -291,8 +291,10 @@ def gemm_right_packed(plan, A, CBr, n, C=None, stream=None):
 
 
 def centred_ld(k) -> int:
-    """Leading dimension of the centred, transposed right operand: k rounded up to 128."""
-    return max(1, -(-k // 128)) * 128
+    """Leading dimension of the centred, transposed right operand: k rounded up to 128,
+    plus one 128-byte line when that is a multiple of 2048 (the library's own choice)."""
+    r = max(1, -(-k // 128)) * 128
+    return r + 128 if r % 2048 == 0 else r
 
 
 def pack_centred_cols(plan, B, Bt=None, stream=None):
