@@ -38,7 +38,8 @@ typedef enum {
     QMM_OK = 0,
     QMM_EINVAL = 1,       /* bad argument: null pointer, negative size, short leading dimension */
     QMM_EBOUND = 2,       /* no (Q, d, block) meets the bounds, or a given plan violates them */
-    QMM_EVALUE = 3,       /* p out of range for the path (INT8 needs p <= 256) */
+    QMM_EVALUE = 3,       /* p out of range for the path (INT8 needs p <= 256), or input
+                             entries that are not residues (validation) */
     QMM_ENOSPACE = 4,     /* workspace smaller than qmm_gemm_workspace_size() */
     QMM_EDEVICE = 5,      /* a HIP runtime call failed (message in qmm_last_error) */
     QMM_EUNSUPPORTED = 6  /* combination not implemented (named in qmm_last_error) */
@@ -127,6 +128,16 @@ qmm_status qmm_pack_rows_fwd(const qmm_plan *plan, int64_t k, int64_t n,
 qmm_status qmm_unpack(const qmm_plan *plan, int which, int64_t rows, int64_t cols,
                       const void *packed, int64_t ldp, uint8_t *out, int64_t ldo,
                       void *stream);
+
+/* Input validation (the products take residues in [0, p) and leave any other
+ * byte undefined).  Counts the entries x >= p of the rows x cols byte matrix X
+ * (device, row-major, leading dimension ldx >= cols) into *count (device, 4-byte
+ * aligned, caller-owned; the call sets it to zero first, with a kernel, then
+ * adds).  Asynchronous on `stream`.  The Python binding's validate=True runs it on
+ * A and B, synchronises and reports QMM_EVALUE when the count is not zero.
+ * Errors: QMM_EINVAL for p outside [2, 256], a bad size, pointer or ldx. */
+qmm_status qmm_count_nonresidues(uint32_t p, int64_t rows, int64_t cols, const uint8_t *X,
+                                 int64_t ldx, uint32_t *count, void *stream);
 
 /* REDC of Table 2 (the per-entry extraction of section 2.5): C[i][j] = digit d of
  * the accumulated word T[i][j], reduced mod p.  EXACT regime: T holds the exact

@@ -108,6 +108,14 @@ extern "C" qmm_status qmm_unpack(const qmm_plan *plan, int which, int64_t rows, 
     return launch_unpack(*plan, which, rows, cols, packed, ldp, out, ldo, stream);
 }
 
+extern "C" qmm_status qmm_count_nonresidues(uint32_t p, int64_t rows, int64_t cols, const uint8_t *X, int64_t ldx,
+                                            uint32_t *count, void *stream) {
+    if (p < 2 || p > 256) return fail(QMM_EINVAL, "p must be in [2, 256] for byte residues");
+    if (bad_matrix(rows, cols, X, ldx)) return fail(QMM_EINVAL, "X: bad size, pointer or ldx");
+    if (!count || (uintptr_t)count % 4 != 0) return fail(QMM_EINVAL, "count: needs a 4-byte aligned device pointer");
+    return launch_count_nonresidues(p, rows, cols, X, ldx, count, stream);
+}
+
 extern "C" qmm_status qmm_extract(const qmm_plan *plan, int64_t m, int64_t n, const void *T, int64_t ldt,
                                   uint8_t *C, int64_t ldc, void *stream) {
     qmm_status st = check_plan_for_words(plan);

@@ -394,7 +394,7 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
 template <uint32_t SHAPE>
-__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : 8) void batched_int8_kernel(const Desc *__restrict__ descs,
+__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 ? 8 : 6)) void batched_int8_kernel(const Desc *__restrict__ descs,
                                                           const TileRef *__restrict__ tiles, int32_t ntiles) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PT];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {

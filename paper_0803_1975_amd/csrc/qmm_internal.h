@@ -62,6 +62,8 @@ qmm_status launch_extract(const qmm_plan &pl, int64_t m, int64_t n, const void *
 qmm_status launch_redq(const qmm_plan &pl, int64_t m, int64_t n, const void *CC, int64_t ldcc,
                        uint8_t *C, int64_t ldc, void *stream);
 qmm_status launch_fill_u8(uint8_t *C, int64_t m, int64_t n, int64_t ldc, uint8_t v, void *stream);
+qmm_status launch_count_nonresidues(uint32_t p, int64_t rows, int64_t cols, const uint8_t *X, int64_t ldx,
+                                    uint32_t *count, void *stream);
 
 // Q-adic GEMM on packed words (procedure (1)): C = digit d of CA x CB mod p.
 qmm_status launch_gemm_qadic(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,

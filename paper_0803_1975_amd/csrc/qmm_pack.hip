@@ -6,11 +6,14 @@
 //   unpack          Uncompress (procedure (5))
 //   extract         REDC of Table 2: digit d of an accumulated word, mod p (section 2.5)
 //   redq            REDQ + EXTRACT of Table 2 (section 3)
+//   count_nonresidues  input validation: entries x >= p of a byte matrix
 //
 // All are HBM-bound elementwise passes: one thread per output word (or residue),
 // consecutive threads on consecutive outputs so both the byte reads and the word
 // writes of a wavefront are contiguous; grid-stride loops over 64-bit indices.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "qmm_device.h"
 #include "qmm_internal.h"
@@ -250,6 +253,31 @@ qmm_status launch_redq(const qmm_plan &pl, int64_t m, int64_t n, const void *CC,
     else
         redq_kernel<double><<<grid_for(m * nw), kThreads, 0, s>>>(m, n, nw, (const double *)CC, ldcc, C, ldc, pl.t, pl.d, pl.p, invp, qmodp);
     return check_launch("redq");
+}
+
+// Entries x >= p of a byte matrix (input validation): a grid-stride loop over rows
+// (y) and columns (x), then a wavefront sum and one atomic add per wavefront.
+__global__ __launch_bounds__(kThreads) void count_nonresidues_kernel(uint32_t p, int64_t rows, int64_t cols,
+                                                                     const uint8_t *__restrict__ X, int64_t ldx,
+                                                                     uint32_t *count) {
+    uint32_t bad = 0;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+        for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < cols; c += (int64_t)gridDim.x * kThreads)
+            bad += X[r * ldx + c] >= p ? 1u : 0u;
+    for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
+    if ((threadIdx.x & 63) == 0 && bad != 0) atomicAdd(count, bad);
+}
+
+__global__ void zero_u32_kernel(uint32_t *x) { *x = 0; }
+
+qmm_status launch_count_nonresidues(uint32_t p, int64_t rows, int64_t cols, const uint8_t *X, int64_t ldx,
+                                    uint32_t *count, void *stream) {
+    zero_u32_kernel<<<1, 1, 0, (hipStream_t)stream>>>(count);
+    if (rows == 0 || cols == 0) return check_launch("zero");
+    const dim3 grid((unsigned)std::min<int64_t>(ceil_div(cols, kThreads), 64),
+                    (unsigned)std::min<int64_t>(rows, 4096));
+    count_nonresidues_kernel<<<grid, kThreads, 0, (hipStream_t)stream>>>(p, rows, cols, X, ldx, count);
+    return check_launch("count_nonresidues");
 }
 
 qmm_status launch_fill_u8(uint8_t *C, int64_t m, int64_t n, int64_t ldc, uint8_t v, void *stream) {

@@ -36,7 +36,7 @@ EXPORTS = [
     "qmm_unpack", "qmm_extract", "qmm_redq", "qmm_gemm_workspace_size", "qmm_gemm_mod_p", "qmm_gemm_packed",
     "qmm_batched_create", "qmm_gemm_mod_p_batched", "qmm_batched_plan", "qmm_batched_destroy",
     "qmm_last_error", "qmm_version", "qmm_pack_centred_cols", "qmm_gemm_centred",
-    "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs",
+    "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs", "qmm_count_nonresidues",
 ]
 
 
@@ -61,9 +61,9 @@ class Problem(ctypes.Structure):
 
 
 class QmmError(RuntimeError):
-    def __init__(self, status, where):
+    def __init__(self, status, where, detail=None):
         self.status = status
-        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {last_error()}")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {detail if detail else last_error()}")
 
 
 _lib = None
@@ -99,6 +99,7 @@ def lib():
             "qmm_batched_destroy": [vp],
             "qmm_batched_tune": [vp, ctypes.POINTER(ctypes.c_double)],
             "qmm_batched_set_costs": [ctypes.POINTER(ctypes.c_double)],
+            "qmm_count_nonresidues": [u32, i64, i64, vp, i64, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -247,8 +248,23 @@ def workspace(plan, m, n, k, device="cuda"):
     return torch.empty(max(gemm_workspace_size(plan, m, n, k), 1), dtype=torch.uint8, device=device)
 
 
-def gemm_mod_p(A, B, p, plan=None, C=None, ws=None, stream=None):
-    """C = A x B mod p (uint8 device tensors)."""
+def count_nonresidues(p, X, count=None, stream=None):
+    """Device int32 tensor of one entry: the number of entries x >= p of the uint8
+    matrix X (asynchronous; read it after the stream's work is done)."""
+    import torch
+    _u8(X, "X")
+    if count is None:
+        count = torch.empty(1, dtype=torch.int32, device=X.device)
+    rows, cols = X.shape
+    _check(lib().qmm_count_nonresidues(p, rows, cols, _ptr(X), _ld(X), _ptr(count), _stream(stream)),
+           "qmm_count_nonresidues")
+    return count
+
+
+def gemm_mod_p(A, B, p, plan=None, C=None, ws=None, stream=None, validate=False):
+    """C = A x B mod p (uint8 device tensors).  validate=True first counts the
+    entries of A and B that are not residues mod p, synchronises, and raises
+    QmmError(EVALUE) if there are any (the product itself leaves them undefined)."""
     import torch
     _u8(A, "A")
     _u8(B, "B")
@@ -256,6 +272,10 @@ def gemm_mod_p(A, B, p, plan=None, C=None, ws=None, stream=None):
     k2, n = B.shape
     if k2 != k:
         raise ValueError("inner dimensions differ")
+    if validate:
+        bad = [int(count_nonresidues(p, X, stream=stream).item()) for X in (A, B)]
+        if any(bad):
+            raise QmmError(EVALUE, "gemm_mod_p", f"{bad[0]} entries of A and {bad[1]} of B are not residues mod {p}")
     if plan is None:
         plan = choose_Qd(p, m, n, k)
     if C is None:

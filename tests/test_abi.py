@@ -119,3 +119,15 @@ def test_batched_refuses_outputs_past_32_bit_offsets_before_device_work():
     assert L.qmm_batched_create(1, ctypes.byref(bad_p), 0, ctypes.byref(out)) == qmm.EINVAL
     bad_ld = qmm.Problem(m=2, n=16, k=16, p=7, A=fake, lda=8, B=fake, ldb=16, C=fake, ldc=16)
     assert L.qmm_batched_create(1, ctypes.byref(bad_ld), 0, ctypes.byref(out)) == qmm.EINVAL
+
+
+def test_count_nonresidues_checks_arguments_before_device_work():
+    L = qmm.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    cnt = ctypes.c_void_p(1 << 21)
+    assert L.qmm_count_nonresidues(1, 4, 4, fake, 4, cnt, None) == qmm.EINVAL
+    assert L.qmm_count_nonresidues(257, 4, 4, fake, 4, cnt, None) == qmm.EINVAL
+    assert L.qmm_count_nonresidues(7, 4, 4, None, 4, cnt, None) == qmm.EINVAL
+    assert L.qmm_count_nonresidues(7, 4, 8, fake, 4, cnt, None) == qmm.EINVAL      # ldx < cols
+    assert L.qmm_count_nonresidues(7, 4, 4, fake, 4, None, None) == qmm.EINVAL
+    assert L.qmm_count_nonresidues(7, 4, 4, fake, 4, ctypes.c_void_p((1 << 21) + 2), None) == qmm.EINVAL

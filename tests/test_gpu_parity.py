@@ -363,3 +363,34 @@ def test_int8_stages_match_one_call_and_oracle(torch, p, m, n, k):
     worst = torch.full((m, k), p - 1, dtype=torch.uint8, device="cuda")
     worstB = torch.full((k, n), p - 1, dtype=torch.uint8, device="cuda")
     assert (host(qmm.gemm_mod_p(worst, worstB, p, plan=plan)) == (k * (p - 1) ** 2) % p).all()
+
+
+def test_count_nonresidues_and_validated_product(torch):
+    # Residues must lie in [0, p); validation counts the other bytes exactly and
+    # gemm_mod_p(validate=True) refuses such input with EVALUE.
+    rng = np.random.default_rng(21)
+    for p, rows, cols, ld in ((7, 300, 257, 257), (101, 1, 1, 1), (2, 65, 4000, 4096), (256, 9, 9, 9)):
+        X = rng.integers(0, p, (rows, ld), dtype=np.uint16)
+        nbad = min(17, rows * cols)
+        ri = rng.integers(0, rows, nbad)
+        ci = rng.integers(0, cols, nbad)
+        if p < 256:
+            X[ri, ci] = rng.integers(p, 256, nbad)
+        X[:, cols:] = 255                               # bytes past cols are not looked at
+        X = X.astype(np.uint8)
+        want = int((X[:, :cols] >= p).sum())
+        dX = dev(torch, X)[:, :cols]
+        got = int(qmm.count_nonresidues(p, dX).item())
+        note("count", p, rows, cols, want, got)
+        assert got == want
+    empty = torch.zeros((0, 5), dtype=torch.uint8, device="cuda")
+    assert int(qmm.count_nonresidues(3, empty).item()) == 0
+    p = 5
+    A = rng.integers(0, p, (64, 80), dtype=np.uint8)
+    B = rng.integers(0, p, (80, 48), dtype=np.uint8)
+    dA, dB = dev(torch, A), dev(torch, B)
+    np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, validate=True)), ref.modmul(A, B, p))
+    dB[3, 7] = 9
+    with pytest.raises(qmm.QmmError) as ei:
+        qmm.gemm_mod_p(dA, dB, p, validate=True)
+    assert ei.value.status == qmm.EVALUE and "1 of B" in str(ei.value)
