@@ -308,12 +308,84 @@ def run_batched(args, torch, qmm):
     print(json.dumps(out), flush=True)
 
 
+def run_passes(args, torch, qmm):
+    """HBM bandwidth of every standalone conversion and reduction pass at the square
+    workload's size (inputs resident, events at the ends of each timed loop)."""
+    import synth
+    p, A, B = synth.workload("square")
+    m, k = A.shape
+    n = B.shape[1]
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    paper = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
+    blocked = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP64_QADIC)
+    redq = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP64_REDQ)
+    f32 = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP32_QADIC)
+    int8 = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+
+    def words(pl, cnt):
+        return -(-cnt // (pl.d + 1))
+
+    def wbytes(pl):
+        return 4 if pl.beta == 24 else 8
+
+    passes = []
+    for name, pl in (("paper", paper), ("planner", blocked), ("fp32", f32)):
+        nw, w = words(pl, k), wbytes(pl)
+        CA = qmm.pack_rows_rev(pl, dA)
+        CB = qmm.pack_cols_fwd(pl, dB)
+        passes.append((f"pack_rows_rev ({name}, t={pl.t}, d={pl.d})", lambda pl=pl, CA=CA: qmm.pack_rows_rev(pl, dA, CA),
+                       m * k + m * nw * w))
+        passes.append((f"pack_cols_fwd ({name}, t={pl.t}, d={pl.d})", lambda pl=pl, CB=CB: qmm.pack_cols_fwd(pl, dB, CB),
+                       k * n + nw * n * w))
+        out = torch.empty((m, k), dtype=torch.uint8, device="cuda")
+        passes.append((f"unpack rows ({name})", lambda pl=pl, CA=CA, out=out: qmm.unpack(pl, qmm.ROWS_REV, m, k, CA, out),
+                       m * nw * w + m * k))
+        T = torch.randint(0, 1 << 40, (m, n), dtype=torch.int64, device="cuda").to(qmm.word_dtype(pl))
+        C = torch.empty((m, n), dtype=torch.uint8, device="cuda")
+        if pl.regime in (qmm.REGIME_EXACT, qmm.REGIME_OFFSET):
+            passes.append((f"extract ({name}, {qmm.REGIME_NAMES[pl.regime]})",
+                           lambda pl=pl, T=T, C=C: qmm.extract(pl, T, C), m * n * w + m * n))
+    nwr = words(redq, n)
+    CBr = qmm.pack_rows_fwd(redq, dB)
+    passes.append((f"pack_rows_fwd (REDQ, t={redq.t}, d={redq.d})", lambda: qmm.pack_rows_fwd(redq, dB, CBr),
+                   k * n + k * nwr * 8))
+    CC = torch.randint(0, 1 << 36, (m, nwr), dtype=torch.int64, device="cuda").to(torch.float64)
+    Cr = torch.empty((m, n), dtype=torch.uint8, device="cuda")
+    passes.append(("redq (REDQ + EXTRACT)", lambda: qmm.redq(redq, CC, n, Cr), m * nwr * 8 + m * n))
+    Bt = qmm.pack_centred_cols(int8, dB)
+    passes.append(("pack_centred_cols (INT8 centring transpose)", lambda: qmm.pack_centred_cols(int8, dB, Bt),
+                   k * n + n * Bt.stride(0)))
+    cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+    passes.append(("count_nonresidues (validation)", lambda: qmm.count_nonresidues(p, dA, cnt), m * k))
+
+    rows = []
+    for name, fn, nbytes in passes:
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(5, args.steps)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        gbps = nbytes / us / 1e3
+        rows.append({"pass": name, "bytes": nbytes, "us": us, "GBps": gbps, "frac": gbps / PEAK["hbm_GBps"]})
+        log(f"[bench] {name}: {us:.1f} us  {gbps:.0f} GB/s  ({100 * gbps / PEAK['hbm_GBps']:.1f}% of HBM)")
+    print(json.dumps({"passes": rows, "workload": f"square: GF({p}) {m}x{k} times {k}x{n}",
+                      "peak_GBps": PEAK["hbm_GBps"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="square")
+    ap.add_argument("--workload", default="square",
+                    help="square, large, graph, small, batched; or passes (HBM rate of each standalone pass)")
     ap.add_argument("--paths", default="all", help="'all' or 'chosen'")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -345,6 +417,9 @@ def main():
     qmm.lib()
     if args.workload == "batched":
         run_batched(args, torch, qmm)
+        return
+    if args.workload == "passes":
+        run_passes(args, torch, qmm)
         return
     p, A, B = synth.workload(args.workload)
     m, k = A.shape

@@ -10,7 +10,10 @@
 //
 // All are HBM-bound elementwise passes: one thread per output word (or residue),
 // consecutive threads on consecutive outputs so both the byte reads and the word
-// writes of a wavefront are contiguous; grid-stride loops over 64-bit indices.
+// writes of a wavefront are contiguous.  Two-dimensional grid-stride loops: rows
+// on the grid's y, positions in a row on x, so no thread divides a flat 64-bit
+// index (rows longer than 2^31 entries are refused, and the in-row divisions of
+// unpack are 32-bit).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,12 +26,17 @@ namespace {
 
 constexpr int kThreads = 256;
 
-inline dim3 grid_for(int64_t total) {
-    int64_t b = ceil_div(total, kThreads);
-    if (b > (int64_t)1 << 20) b = (int64_t)1 << 20;
-    if (b < 1) b = 1;
-    return dim3((unsigned)b);
+// Grid for a rows x cols pass: enough x blocks to cover a row (at most 4096), and
+// as many rows per launch as keep the grid near 2^18 workgroups.
+inline dim3 grid2(int64_t rows, int64_t cols) {
+    const int64_t x = std::max<int64_t>(1, std::min<int64_t>(ceil_div(cols, kThreads), 4096));
+    const int64_t y = std::max<int64_t>(1, std::min<int64_t>({rows, (int64_t)65535, std::max<int64_t>(1, 262144 / x)}));
+    return dim3((unsigned)x, (unsigned)y);
 }
+
+#define QMM_FOR_ROWS(r, rows) for (int64_t r = blockIdx.y; r < (rows); r += gridDim.y)
+#define QMM_FOR_COLS(c, cols) \
+    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < (cols); c += (int64_t)gridDim.x * kThreads)
 
 // CA[i][l] = sum_s A[i][l(d+1)+s] Q^(d-s): Horner from the first residue of the chunk,
 // which ends with the top power (the paper's init3 order).
@@ -37,18 +45,17 @@ __global__ __launch_bounds__(kThreads) void pack_rows_rev_kernel(int64_t m, int6
                                                                   const uint8_t *__restrict__ A, int64_t lda,
                                                                   W *__restrict__ CA, int64_t ldca,
                                                                   uint32_t t, uint32_t d) {
-    const int64_t total = m * nw;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t i = idx / nw, l = idx - i * nw;
+    QMM_FOR_ROWS(i, m) {
         const uint8_t *a = A + i * lda;
-        const int64_t base = l * (d + 1);
-        uint64_t w = 0;
-        for (uint32_t s = 0; s <= d; ++s) {
-            const int64_t c = base + s;
-            w = (w << t) | (c < k ? (uint64_t)a[c] : 0ull);
+        QMM_FOR_COLS(l, nw) {
+            const int64_t base = (int64_t)l * (d + 1);
+            uint64_t w = 0;
+            for (uint32_t s = 0; s <= d; ++s) {
+                const int64_t c = base + s;
+                w = (w << t) | (c < k ? (uint64_t)a[c] : 0ull);
+            }
+            CA[i * ldca + l] = word_from_u64<W>(w);
         }
-        CA[i * ldca + l] = word_from_u64<W>(w);
     }
 }
 
@@ -58,17 +65,16 @@ __global__ __launch_bounds__(kThreads) void pack_cols_fwd_kernel(int64_t k, int6
                                                                   const uint8_t *__restrict__ B, int64_t ldb,
                                                                   W *__restrict__ CB, int64_t ldcb,
                                                                   uint32_t t, uint32_t d) {
-    const int64_t total = nw * n;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t l = idx / n, j = idx - l * n;
+    QMM_FOR_ROWS(l, nw) {
         const int64_t base = l * (d + 1);
-        uint64_t w = 0;
-        for (int32_t s = (int32_t)d; s >= 0; --s) {
-            const int64_t r = base + s;
-            w = (w << t) | (r < k ? (uint64_t)B[r * ldb + j] : 0ull);
+        QMM_FOR_COLS(j, n) {
+            uint64_t w = 0;
+            for (int32_t s = (int32_t)d; s >= 0; --s) {
+                const int64_t r = base + s;
+                w = (w << t) | (r < k ? (uint64_t)B[r * ldb + j] : 0ull);
+            }
+            CB[l * ldcb + j] = word_from_u64<W>(w);
         }
-        CB[l * ldcb + j] = word_from_u64<W>(w);
     }
 }
 
@@ -78,18 +84,17 @@ __global__ __launch_bounds__(kThreads) void pack_rows_fwd_kernel(int64_t k, int6
                                                                   const uint8_t *__restrict__ B, int64_t ldb,
                                                                   W *__restrict__ CBr, int64_t ldcbr,
                                                                   uint32_t t, uint32_t d) {
-    const int64_t total = k * nw;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t i = idx / nw, J = idx - i * nw;
+    QMM_FOR_ROWS(i, k) {
         const uint8_t *b = B + i * ldb;
-        const int64_t base = J * (d + 1);
-        uint64_t w = 0;
-        for (int32_t j = (int32_t)d; j >= 0; --j) {
-            const int64_t c = base + j;
-            w = (w << t) | (c < n ? (uint64_t)b[c] : 0ull);
+        QMM_FOR_COLS(J, nw) {
+            const int64_t base = (int64_t)J * (d + 1);
+            uint64_t w = 0;
+            for (int32_t j = (int32_t)d; j >= 0; --j) {
+                const int64_t c = base + j;
+                w = (w << t) | (c < n ? (uint64_t)b[c] : 0ull);
+            }
+            CBr[i * ldcbr + J] = word_from_u64<W>(w);
         }
-        CBr[i * ldcbr + J] = word_from_u64<W>(w);
     }
 }
 
@@ -99,24 +104,24 @@ __global__ __launch_bounds__(kThreads) void unpack_kernel(int which, int64_t row
                                                            const W *__restrict__ P, int64_t ldp,
                                                            uint8_t *__restrict__ out, int64_t ldo,
                                                            uint32_t t, uint32_t d) {
-    const int64_t total = rows * cols;
     const uint64_t qmask = (t >= 64) ? ~0ull : ((1ull << t) - 1);
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t r = idx / cols, c = idx - r * cols;
-        uint64_t w;
-        uint32_t pos;
-        if (which == 0) {  // residue (r, c) is digit d - s of word (r, c / (d+1))
-            w = u64_from_word(P[r * ldp + c / (d + 1)]);
-            pos = d - (uint32_t)(c % (d + 1));
-        } else if (which == 1) {  // residue (r, c) is digit s of word (r / (d+1), c)
-            w = u64_from_word(P[(r / (d + 1)) * ldp + c]);
-            pos = (uint32_t)(r % (d + 1));
-        } else {  // residue (r, c) is digit j of word (r, c / (d+1))
-            w = u64_from_word(P[r * ldp + c / (d + 1)]);
-            pos = (uint32_t)(c % (d + 1));
+    const uint32_t e = d + 1;
+    QMM_FOR_ROWS(r, rows) {
+        QMM_FOR_COLS(c, cols) {
+            uint64_t w;
+            uint32_t pos;
+            if (which == 0) {  // residue (r, c) is digit d - s of word (r, c / (d+1))
+                w = u64_from_word(P[r * ldp + (uint32_t)c / e]);
+                pos = d - (uint32_t)c % e;
+            } else if (which == 1) {  // residue (r, c) is digit s of word (r / (d+1), c)
+                w = u64_from_word(P[(r / e) * ldp + c]);
+                pos = (uint32_t)(r % e);
+            } else {  // residue (r, c) is digit j of word (r, c / (d+1))
+                w = u64_from_word(P[r * ldp + (uint32_t)c / e]);
+                pos = (uint32_t)c % e;
+            }
+            out[r * ldo + c] = (uint8_t)((w >> (t * pos)) & qmask);
         }
-        out[r * ldo + c] = (uint8_t)((w >> (t * pos)) & qmask);
     }
 }
 
@@ -125,12 +130,11 @@ __global__ __launch_bounds__(kThreads) void extract_kernel(int64_t m, int64_t n,
                                                             int64_t ldt, uint8_t *__restrict__ C, int64_t ldc,
                                                             uint32_t td, uint64_t qmask, bool offset, uint32_t p,
                                                             double invp) {
-    const int64_t total = m * n;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t i = idx / n, j = idx - i * n;
-        const uint32_t c = qadic_digit<W>(T[i * ldt + j], offset, td, qmask);
-        C[i * ldc + j] = (uint8_t)mod_u64(c, p, invp);
+    QMM_FOR_ROWS(i, m) {
+        QMM_FOR_COLS(j, n) {
+            const uint32_t c = qadic_digit<W>(T[i * ldt + j], offset, td, qmask);
+            C[i * ldc + j] = (uint8_t)mod_u64(c, p, invp);
+        }
     }
 }
 
@@ -143,10 +147,7 @@ __global__ __launch_bounds__(kThreads) void redq_kernel(int64_t m, int64_t n, in
                                                          uint8_t *__restrict__ C, int64_t ldc,
                                                          uint32_t t, uint32_t d, uint32_t p, double invp,
                                                          uint32_t qmodp) {
-    const int64_t total = m * nw;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t i = idx / nw, J = idx - i * nw;
+    QMM_FOR_ROWS(i, m) QMM_FOR_COLS(J, nw) {
         const uint64_t r = u64_from_word(CC[i * ldcc + J]);
         const uint64_t s = div_u64(r, p, invp);  // floor(r / p), the one division
         uint32_t mu_next = 0;  // mu_{d+1} = 0
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void redq_kernel(int64_t m, int64_t n, in
             const uint32_t sh = t * (uint32_t)j;
             const uint32_t mu = (uint32_t)((r >> sh) - (uint64_t)p * (s >> sh));
             const uint64_t v = (uint64_t)mu + (uint64_t)qmodp * p - (uint64_t)qmodp * mu_next;
-            const int64_t col = J * (d + 1) + j;
+            const int64_t col = (int64_t)J * (d + 1) + j;
             if (col < n) C[i * ldc + col] = (uint8_t)mod_u64(v, p, invp);
             mu_next = mu;
         }
@@ -164,12 +165,11 @@ __global__ __launch_bounds__(kThreads) void redq_kernel(int64_t m, int64_t n, in
 
 __global__ __launch_bounds__(kThreads) void fill_u8_kernel(uint8_t *C, int64_t m, int64_t n, int64_t ldc,
                                                             uint8_t v) {
-    const int64_t total = m * n;
-    for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kThreads) {
-        const int64_t i = idx / n, j = idx - i * n;
-        C[i * ldc + j] = v;
-    }
+    QMM_FOR_ROWS(i, m) QMM_FOR_COLS(j, n) C[i * ldc + j] = v;
+}
+
+qmm_status row_too_long(int64_t cols) {
+    return cols > INT32_MAX ? fail(QMM_EUNSUPPORTED, "rows longer than 2^31 entries are not supported") : QMM_OK;
 }
 
 qmm_status check_launch(const char *what) {
@@ -184,11 +184,12 @@ qmm_status launch_pack_rows_rev(const qmm_plan &pl, int64_t m, int64_t k, const 
                                 void *CA, int64_t ldca, void *stream) {
     const int64_t nw = words_for(k, pl.d);
     if (m * nw == 0) return QMM_OK;
+    if (row_too_long(nw) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (pl.beta == 24)
-        pack_rows_rev_kernel<float><<<grid_for(m * nw), kThreads, 0, s>>>(m, k, nw, A, lda, (float *)CA, ldca, pl.t, pl.d);
+        pack_rows_rev_kernel<float><<<grid2(m, nw), kThreads, 0, s>>>(m, k, nw, A, lda, (float *)CA, ldca, pl.t, pl.d);
     else
-        pack_rows_rev_kernel<double><<<grid_for(m * nw), kThreads, 0, s>>>(m, k, nw, A, lda, (double *)CA, ldca, pl.t, pl.d);
+        pack_rows_rev_kernel<double><<<grid2(m, nw), kThreads, 0, s>>>(m, k, nw, A, lda, (double *)CA, ldca, pl.t, pl.d);
     return check_launch("pack_rows_rev");
 }
 
@@ -196,11 +197,12 @@ qmm_status launch_pack_cols_fwd(const qmm_plan &pl, int64_t k, int64_t n, const 
                                 void *CB, int64_t ldcb, void *stream) {
     const int64_t nw = words_for(k, pl.d);
     if (nw * n == 0) return QMM_OK;
+    if (row_too_long(n) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (pl.beta == 24)
-        pack_cols_fwd_kernel<float><<<grid_for(nw * n), kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CB, ldcb, pl.t, pl.d);
+        pack_cols_fwd_kernel<float><<<grid2(nw, n), kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CB, ldcb, pl.t, pl.d);
     else
-        pack_cols_fwd_kernel<double><<<grid_for(nw * n), kThreads, 0, s>>>(k, n, nw, B, ldb, (double *)CB, ldcb, pl.t, pl.d);
+        pack_cols_fwd_kernel<double><<<grid2(nw, n), kThreads, 0, s>>>(k, n, nw, B, ldb, (double *)CB, ldcb, pl.t, pl.d);
     return check_launch("pack_cols_fwd");
 }
 
@@ -208,36 +210,39 @@ qmm_status launch_pack_rows_fwd(const qmm_plan &pl, int64_t k, int64_t n, const 
                                 void *CBr, int64_t ldcbr, void *stream) {
     const int64_t nw = words_for(n, pl.d);
     if (k * nw == 0) return QMM_OK;
+    if (row_too_long(nw) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (pl.beta == 24)
-        pack_rows_fwd_kernel<float><<<grid_for(k * nw), kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CBr, ldcbr, pl.t, pl.d);
+        pack_rows_fwd_kernel<float><<<grid2(k, nw), kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CBr, ldcbr, pl.t, pl.d);
     else
-        pack_rows_fwd_kernel<double><<<grid_for(k * nw), kThreads, 0, s>>>(k, n, nw, B, ldb, (double *)CBr, ldcbr, pl.t, pl.d);
+        pack_rows_fwd_kernel<double><<<grid2(k, nw), kThreads, 0, s>>>(k, n, nw, B, ldb, (double *)CBr, ldcbr, pl.t, pl.d);
     return check_launch("pack_rows_fwd");
 }
 
 qmm_status launch_unpack(const qmm_plan &pl, int which, int64_t rows, int64_t cols, const void *packed,
                          int64_t ldp, uint8_t *out, int64_t ldo, void *stream) {
     if (rows * cols == 0) return QMM_OK;
+    if (row_too_long(cols) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (pl.beta == 24)
-        unpack_kernel<float><<<grid_for(rows * cols), kThreads, 0, s>>>(which, rows, cols, (const float *)packed, ldp, out, ldo, pl.t, pl.d);
+        unpack_kernel<float><<<grid2(rows, cols), kThreads, 0, s>>>(which, rows, cols, (const float *)packed, ldp, out, ldo, pl.t, pl.d);
     else
-        unpack_kernel<double><<<grid_for(rows * cols), kThreads, 0, s>>>(which, rows, cols, (const double *)packed, ldp, out, ldo, pl.t, pl.d);
+        unpack_kernel<double><<<grid2(rows, cols), kThreads, 0, s>>>(which, rows, cols, (const double *)packed, ldp, out, ldo, pl.t, pl.d);
     return check_launch("unpack");
 }
 
 qmm_status launch_extract(const qmm_plan &pl, int64_t m, int64_t n, const void *T, int64_t ldt, uint8_t *C,
                           int64_t ldc, void *stream) {
     if (m * n == 0) return QMM_OK;
+    if (row_too_long(n) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const uint64_t qmask = (1ull << pl.t) - 1;
     const bool offset = pl.regime == QMM_REGIME_OFFSET;
     const double invp = 1.0 / (double)pl.p;
     if (pl.beta == 24)
-        extract_kernel<float><<<grid_for(m * n), kThreads, 0, s>>>(m, n, (const float *)T, ldt, C, ldc, pl.t * pl.d, qmask, offset, pl.p, invp);
+        extract_kernel<float><<<grid2(m, n), kThreads, 0, s>>>(m, n, (const float *)T, ldt, C, ldc, pl.t * pl.d, qmask, offset, pl.p, invp);
     else
-        extract_kernel<double><<<grid_for(m * n), kThreads, 0, s>>>(m, n, (const double *)T, ldt, C, ldc, pl.t * pl.d, qmask, offset, pl.p, invp);
+        extract_kernel<double><<<grid2(m, n), kThreads, 0, s>>>(m, n, (const double *)T, ldt, C, ldc, pl.t * pl.d, qmask, offset, pl.p, invp);
     return check_launch("extract");
 }
 
@@ -245,25 +250,47 @@ qmm_status launch_redq(const qmm_plan &pl, int64_t m, int64_t n, const void *CC,
                        int64_t ldc, void *stream) {
     const int64_t nw = words_for(n, pl.d);
     if (m * nw == 0) return QMM_OK;
+    if (row_too_long(nw) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const double invp = 1.0 / (double)pl.p;
     const uint32_t qmodp = (uint32_t)((1ull << pl.t) % pl.p);
     if (pl.beta == 24)
-        redq_kernel<float><<<grid_for(m * nw), kThreads, 0, s>>>(m, n, nw, (const float *)CC, ldcc, C, ldc, pl.t, pl.d, pl.p, invp, qmodp);
+        redq_kernel<float><<<grid2(m, nw), kThreads, 0, s>>>(m, n, nw, (const float *)CC, ldcc, C, ldc, pl.t, pl.d, pl.p, invp, qmodp);
     else
-        redq_kernel<double><<<grid_for(m * nw), kThreads, 0, s>>>(m, n, nw, (const double *)CC, ldcc, C, ldc, pl.t, pl.d, pl.p, invp, qmodp);
+        redq_kernel<double><<<grid2(m, nw), kThreads, 0, s>>>(m, n, nw, (const double *)CC, ldcc, C, ldc, pl.t, pl.d, pl.p, invp, qmodp);
     return check_launch("redq");
 }
 
 // Entries x >= p of a byte matrix (input validation): a grid-stride loop over rows
-// (y) and columns (x), then a wavefront sum and one atomic add per wavefront.
+// (y) and 16-byte column segments (x); a segment is one vector load when the row
+// is 16-byte aligned and the segment lies inside it, else byte loads.  Each byte
+// of the loaded words is compared with p; then a wavefront sum and one atomic add
+// per wavefront.
+__device__ __forceinline__ uint32_t count_ge(uint32_t w, uint32_t p) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c += ((w >> (8 * b)) & 0xffu) >= p ? 1u : 0u;
+    return c;
+}
+
 __global__ __launch_bounds__(kThreads) void count_nonresidues_kernel(uint32_t p, int64_t rows, int64_t cols,
                                                                      const uint8_t *__restrict__ X, int64_t ldx,
                                                                      uint32_t *count) {
     uint32_t bad = 0;
-    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
-        for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < cols; c += (int64_t)gridDim.x * kThreads)
-            bad += X[r * ldx + c] >= p ? 1u : 0u;
+    const int64_t segs = ceil_div(cols, 16);
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const uint8_t *row = X + r * ldx;
+        const bool aligned = ((uintptr_t)row & 15) == 0;
+        for (int64_t sg = (int64_t)blockIdx.x * kThreads + threadIdx.x; sg < segs; sg += (int64_t)gridDim.x * kThreads) {
+            const int64_t c0 = 16 * sg;
+            if (aligned && c0 + 16 <= cols) {
+                const uint4 v = *(const uint4 *)(row + c0);
+                bad += count_ge(v.x, p) + count_ge(v.y, p) + count_ge(v.z, p) + count_ge(v.w, p);
+            } else {
+                for (int64_t c = c0; c < cols && c < c0 + 16; ++c) bad += row[c] >= p ? 1u : 0u;
+            }
+        }
+    }
     for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
     if ((threadIdx.x & 63) == 0 && bad != 0) atomicAdd(count, bad);
 }
@@ -274,7 +301,7 @@ qmm_status launch_count_nonresidues(uint32_t p, int64_t rows, int64_t cols, cons
                                     uint32_t *count, void *stream) {
     zero_u32_kernel<<<1, 1, 0, (hipStream_t)stream>>>(count);
     if (rows == 0 || cols == 0) return check_launch("zero");
-    const dim3 grid((unsigned)std::min<int64_t>(ceil_div(cols, kThreads), 64),
+    const dim3 grid((unsigned)std::min<int64_t>(ceil_div(ceil_div(cols, 16), kThreads), 64),
                     (unsigned)std::min<int64_t>(rows, 4096));
     count_nonresidues_kernel<<<grid, kThreads, 0, (hipStream_t)stream>>>(p, rows, cols, X, ldx, count);
     return check_launch("count_nonresidues");
@@ -282,7 +309,8 @@ qmm_status launch_count_nonresidues(uint32_t p, int64_t rows, int64_t cols, cons
 
 qmm_status launch_fill_u8(uint8_t *C, int64_t m, int64_t n, int64_t ldc, uint8_t v, void *stream) {
     if (m * n == 0) return QMM_OK;
-    fill_u8_kernel<<<grid_for(m * n), kThreads, 0, (hipStream_t)stream>>>(C, m, n, ldc, v);
+    if (row_too_long(n) != QMM_OK) return QMM_EUNSUPPORTED;
+    fill_u8_kernel<<<grid2(m, n), kThreads, 0, (hipStream_t)stream>>>(C, m, n, ldc, v);
     return check_launch("fill");
 }
 
