@@ -7,12 +7,13 @@ reduction, exactly the kernels qmm_gemm_mod_p runs, issued through the stage
 entry points of the C ABI so that HIP events on the launch stream can time the
 dominant kernel on its own.
 
-The headline line uses the plan the library chooses (QMM_PATH_AUTO) on the square
-workload (GF(7), 4096^3, uniform residues, seed 2).  The same line carries every
-other path on the same inputs (the paper's FP64 Q-adic product, the
-right-compressed REDQ product, the FP32 forms), each checked bit for bit against
-the chosen path's result, a roofline object for the dominant kernel, and the CPU
-oracle timed on a bounded sample of rows on this host.
+The headline line uses the plan the library chooses (QMM_PATH_AUTO: FP4 matrix
+cores for p <= 8, INT8 for other byte residues) on the square workload (GF(7),
+4096^3, uniform residues, seed 2).  The same line carries every other path on the
+same inputs (INT8, the paper's FP64 Q-adic product, the right-compressed REDQ
+product, the FP32 forms), each checked bit for bit against the others, a roofline
+object for the dominant kernel, and the CPU oracle timed on a bounded sample of
+rows on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload square]
 """
@@ -31,9 +32,11 @@ PEAK = {  # MI355X published dense peaks
     "fp64_TFLOPs": 78.6,
     "fp32_TFLOPs": 157.3,
     "int8_TOPs": 5000.0,
+    "fp4_TFLOPs": 10100.0,
 }
 KERNEL_SOURCES = {
     "int8": "paper_0803_1975_amd/csrc/qmm_int8.hip",
+    "fp4": "paper_0803_1975_amd/csrc/qmm_int8.hip",
     "fp64_qadic": "paper_0803_1975_amd/csrc/qmm_gemm.hip",
     "fp64_redq": "paper_0803_1975_amd/csrc/qmm_gemm.hip",
 }
@@ -74,6 +77,9 @@ class Stepper:
         self.C = torch.empty((m, n), dtype=torch.uint8, device=dev)
         if plan.path == qmm.PATH_INT8:
             self.Bt = torch.empty((n, qmm.centred_ld(k)), dtype=torch.int8, device=dev)
+        elif plan.path == qmm.PATH_FP4:
+            self.A4 = torch.empty((m, qmm.fp4_ld(k)), dtype=torch.uint8, device=dev)
+            self.Bt4 = torch.empty((n, qmm.fp4_ld(k)), dtype=torch.uint8, device=dev)
         elif plan.path in (qmm.PATH_FP64_QADIC, qmm.PATH_FP32_QADIC):
             wd = qmm.word_dtype(plan)
             nw = -(-k // (plan.d + 1))
@@ -101,6 +107,14 @@ class Stepper:
                                                           q._ld(Bt), st))]
             self.prod_calls = [(L.qmm_gemm_centred, (P, m, n, k, vp(A.data_ptr()), q._ld(A), vp(Bt.data_ptr()),
                                                      q._ld(Bt), vp(C.data_ptr()), q._ld(C), st))]
+        elif pl.path == q.PATH_FP4:
+            A4, Bt4 = self.A4, self.Bt4
+            self.conv_calls = [(L.qmm_pack_fp4_rows, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(A4.data_ptr()),
+                                                      q._ld(A4), st)),
+                               (L.qmm_pack_fp4_cols, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(Bt4.data_ptr()),
+                                                      q._ld(Bt4), st))]
+            self.prod_calls = [(L.qmm_gemm_fp4, (P, m, n, k, vp(A4.data_ptr()), q._ld(A4), vp(Bt4.data_ptr()),
+                                                 q._ld(Bt4), vp(C.data_ptr()), q._ld(C), st))]
         elif pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):
             CA, CB = self.CA, self.CB
             self.conv_calls = [(L.qmm_pack_rows_rev, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CA.data_ptr()), q._ld(CA), st)),
@@ -132,6 +146,8 @@ class Stepper:
         m, n, k = self.m, self.n, self.k
         if pl.path == q.PATH_INT8:
             return 2.0 * m * n * k, PEAK["int8_TOPs"], "TFLOP/s", "int8 MFMA ops (2 per MAC)"
+        if pl.path == q.PATH_FP4:
+            return 2.0 * m * n * k, PEAK["fp4_TFLOPs"], "TFLOP/s", "fp4 (e2m1) MFMA flops (2 per MAC)"
         fp64 = pl.beta == 53
         peak = PEAK["fp64_TFLOPs"] if fp64 else PEAK["fp32_TFLOPs"]
         if pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):
@@ -432,7 +448,8 @@ def main():
     # to its working clocks before the chosen path is timed.
     variants = []
     if args.paths == "all":
-        variants += [("fp64_qadic", qmm.PATH_FP64_QADIC, 0),
+        variants += [("int8", qmm.PATH_INT8, 0),
+                     ("fp64_qadic", qmm.PATH_FP64_QADIC, 0),
                      ("fp64_qadic_paper", qmm.PATH_FP64_QADIC, qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4),
                      ("fp64_redq", qmm.PATH_FP64_REDQ, 0),
                      ("fp32_qadic", qmm.PATH_FP32_QADIC, 0),
@@ -492,7 +509,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8" if cname == "int8" else ("f64" if "fp64" in cname else "f32"),
+        "dtype": {"int8": "i8", "fp4": "fp4 (e2m1)"}.get(cname, "f64" if "fp64" in cname else "f32"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: GF({p}) {m}x{k} times {k}x{n}, uniform residues, "
                                f"seed {synth.WORKLOADS[args.workload]['seed']}",

@@ -51,7 +51,9 @@ typedef enum {
     QMM_PATH_FP64_REDQ = 2,   /* n-compressed words times residues + REDQ (procedure (5)) */
     QMM_PATH_FP32_QADIC = 3,  /* as FP64_QADIC with a 24-bit mantissa */
     QMM_PATH_FP32_REDQ = 4,   /* as FP64_REDQ with a 24-bit mantissa */
-    QMM_PATH_INT8 = 5         /* centred residues, int8 matrix cores, int32 accumulation */
+    QMM_PATH_INT8 = 5,        /* centred residues, int8 matrix cores, int32 accumulation */
+    QMM_PATH_FP4 = 6          /* centred residues as FP4 (e2m1) codes, FP4 matrix cores with
+                                 FP32 accumulation that stays exact (p <= 8) */
 } qmm_path;
 
 typedef enum {
@@ -187,6 +189,28 @@ qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int64_t n, int
  * (The int8 matrix cores take both operands contiguous along k.) */
 qmm_status qmm_pack_centred_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B,
                                  int64_t ldb, int8_t *Bt, int64_t ldbt, void *stream);
+
+/* FP4 path (p <= 8).  Every centred residue of such a p (|x| <= 4) is an exact
+ * e2m1 value (0, +-1, +-2, +-3, +-4), so the FP4 matrix cores of gfx950 multiply
+ * them exactly and the FP32 accumulator stays an exact integer while
+ * k_block floor(p/2)^2 + p - 1 <= 2^24; longer k is cut into blocks reduced mod p.
+ * Packed operand layout: row-major rows of e2m1 codes (sign bit 8, magnitude code
+ * 0 = 0, 2 = 1, 4 = 2, 5 = 3, 6 = 4), two per byte, the even k in the low nibble;
+ * row stride ld4 bytes, a multiple of 128 with 2 ld4 >= k; codes past k are zero.
+ * Both packed operands must be 16-byte aligned.
+ * Conversion steps: A4 (m x ld4) from A (m x k residues, row-major) and Bt4
+ * (n x ld4) from B (k x n residues) transposed, so both are contiguous along k. */
+qmm_status qmm_pack_fp4_rows(const qmm_plan *plan, int64_t m, int64_t k, const uint8_t *A,
+                             int64_t lda, uint8_t *A4, int64_t lda4, void *stream);
+qmm_status qmm_pack_fp4_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B,
+                             int64_t ldb, uint8_t *Bt4, int64_t ldbt4, void *stream);
+
+/* FP4 path, product step: C = (A4 x Bt4^T) mod p (values decoded from the codes),
+ * FP32 accumulation, k cut into plan->k_block blocks reduced mod p.  plan->tile
+ * picks the kernel tile as for INT8. */
+qmm_status qmm_gemm_fp4(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                        const uint8_t *A4, int64_t lda4, const uint8_t *Bt4, int64_t ldbt4,
+                        uint8_t *C, int64_t ldc, void *stream);
 
 /* INT8 path, product step: C = (centred(A) x Bt^T) mod p with int32 accumulation,
  * k cut into plan->k_block blocks reduced mod p.  A: m x k bytes; Bt from

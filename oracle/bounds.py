@@ -141,3 +141,35 @@ def centred_max(p: int) -> int:
 def int32_ok(p: int, kb: int) -> bool:
     """kb products of centred residues never leave the int32 range."""
     return kb * centred_max(p) ** 2 <= (1 << 31) - 1
+
+
+# --- FP4 (e2m1) operands with FP32 accumulation --------------------------------------
+# The FP4 path multiplies centred residues on the FP4 matrix cores.  It is exact when
+# every centred residue is an e2m1 value and every partial sum is an integer of at
+# most 2^24 in magnitude (the range where FP32 holds every integer).
+
+def e2m1_value(code: int) -> Fraction:
+    """Value of a 4-bit e2m1 code: sign bit 3, exponent bits 2..1 with bias 1, mantissa
+    bit 0; exponent 0 is subnormal (0 or 1/2 before the sign)."""
+    sign = -1 if code & 8 else 1
+    e, mant = (code >> 1) & 3, code & 1
+    if e == 0:
+        return sign * Fraction(mant, 2)
+    return sign * Fraction(2 + mant, 2) * (2 ** (e - 1))
+
+
+def e2m1_values() -> set:
+    return {e2m1_value(c) for c in range(16)}
+
+
+def fp4_representable(p: int) -> bool:
+    """Every centred residue x - p [x > (p-1)//2], 0 <= x < p, is an e2m1 value."""
+    vals = e2m1_values()
+    return all(Fraction(x - p if x > (p - 1) // 2 else x) in vals for x in range(p))
+
+
+def fp4_block_ok(p: int, kb: int) -> bool:
+    """A block of kb products, started from the previous block's residue (< p), keeps
+    every partial sum an integer of magnitude at most 2^24."""
+    return kb * centred_max(p) ** 2 + (p - 1) <= 1 << 24
+

@@ -52,6 +52,10 @@ Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
     } else if (pl.path == QMM_PATH_INT8) {
         L.ld_b = int8_bt_ld(kk);
         L.bytes = align_up((size_t)n * L.ld_b);
+    } else if (pl.path == QMM_PATH_FP4) {
+        L.ld_a = L.ld_b = fp4_ld(kk);
+        L.off_b = align_up((size_t)m * L.ld_a);
+        L.bytes = L.off_b + align_up((size_t)n * L.ld_b);
     }
     return L;
 }
@@ -180,6 +184,12 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
         if ((st = launch_centre_transpose(pl, k, n, B, ldb, Bt, L.ld_b, stream)) != QMM_OK) return st;
         return launch_gemm_int8(pl, m, n, k, A, lda, Bt, L.ld_b, C, ldc, stream);
     }
+    if (pl.path == QMM_PATH_FP4) {
+        uint8_t *A4 = w, *Bt4 = w + L.off_b;
+        if ((st = launch_pack_fp4_rows(pl, m, k, A, lda, A4, L.ld_a, stream)) != QMM_OK) return st;
+        if ((st = launch_pack_fp4_cols(pl, k, n, B, ldb, Bt4, L.ld_b, stream)) != QMM_OK) return st;
+        return launch_gemm_fp4(pl, m, n, k, A4, L.ld_a, Bt4, L.ld_b, C, ldc, stream);
+    }
     return fail(QMM_EINVAL, "unknown path");
 }
 
@@ -222,6 +232,48 @@ extern "C" qmm_status qmm_gemm_centred(const qmm_plan *plan, int64_t m, int64_t 
     if (m == 0 || n == 0) return QMM_OK;
     if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
     return launch_gemm_int8(*plan, m, n, k, A, lda, Bt, ldbt, C, ldc, stream);
+}
+
+namespace {
+bool bad_fp4_operand(int64_t rows, int64_t k, const uint8_t *P, int64_t ld4) {
+    if (rows == 0 || k == 0) return false;
+    return P == nullptr || ld4 % 128 != 0 || 2 * ld4 < k || ((uintptr_t)P % 16) != 0;
+}
+}  // namespace
+
+extern "C" qmm_status qmm_pack_fp4_rows(const qmm_plan *plan, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
+                                        uint8_t *A4, int64_t lda4, void *stream) {
+    if (!plan || plan->path != QMM_PATH_FP4) return fail(QMM_EINVAL, "an FP4 plan is required");
+    if (plan->p < 2 || plan->p > 8) return fail(QMM_EINVAL, "FP4 needs 2 <= p <= 8");
+    if (bad_matrix(m, k, A, lda)) return fail(QMM_EINVAL, "A: bad size, pointer or lda");
+    if (bad_fp4_operand(m, k < 1 ? 1 : k, A4, lda4))
+        return fail(QMM_EINVAL, "A4: needs a 16-byte aligned pointer and lda4 a multiple of 128, >= k/2");
+    return launch_pack_fp4_rows(*plan, m, k, A, lda, A4, lda4, stream);
+}
+
+extern "C" qmm_status qmm_pack_fp4_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                        uint8_t *Bt4, int64_t ldbt4, void *stream) {
+    if (!plan || plan->path != QMM_PATH_FP4) return fail(QMM_EINVAL, "an FP4 plan is required");
+    if (plan->p < 2 || plan->p > 8) return fail(QMM_EINVAL, "FP4 needs 2 <= p <= 8");
+    if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad size, pointer or ldb");
+    if (bad_fp4_operand(n, k < 1 ? 1 : k, Bt4, ldbt4))
+        return fail(QMM_EINVAL, "Bt4: needs a 16-byte aligned pointer and ldbt4 a multiple of 128, >= k/2");
+    return launch_pack_fp4_cols(*plan, k, n, B, ldb, Bt4, ldbt4, stream);
+}
+
+extern "C" qmm_status qmm_gemm_fp4(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const uint8_t *A4,
+                                   int64_t lda4, const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc,
+                                   void *stream) {
+    if (!plan || plan->path != QMM_PATH_FP4) return fail(QMM_EINVAL, "an FP4 plan is required");
+    qmm_status st = qmm_validate_plan(plan, m, n, k);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(m, n, C, ldc)) return fail(QMM_EINVAL, "C: bad pointer or ldc");
+    if (bad_fp4_operand(m, k, A4, lda4) || bad_fp4_operand(n, k, Bt4, ldbt4))
+        return fail(QMM_EINVAL, "A4, Bt4: need 16-byte aligned pointers and leading dimensions that are "
+                                "multiples of 128, >= k/2");
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
+    return launch_gemm_fp4(*plan, m, n, k, A4, lda4, Bt4, ldbt4, C, ldc, stream);
 }
 
 extern "C" qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const uint8_t *A,

@@ -20,6 +20,9 @@
 //                     64-byte stages below that.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "qmm_device.h"
 #include "qmm_internal.h"
 
@@ -27,7 +30,11 @@ namespace qmm {
 namespace {
 
 typedef int ix4 __attribute__((ext_vector_type(4)));
+typedef int ix8 __attribute__((ext_vector_type(8)));
 typedef int ix16 __attribute__((ext_vector_type(16)));
+typedef float fx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int ux2 __attribute__((ext_vector_type(2)));
+typedef unsigned int ux4 __attribute__((ext_vector_type(4)));
 
 // Transposed operand rows are padded to a multiple of the largest K stage.
 constexpr int kBtAlign = 128;
@@ -111,6 +118,114 @@ __global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_
     }
 }
 
+// FP4 conversion.  Residue x (0 <= x < p <= 8) -> e2m1 code of centred(x), four
+// at a time: the codes of x = 0..7 sit in the bytes of (lut_hi:lut_lo) and one byte
+// permute looks all four up (selector bytes 0..7 pick those bytes).  Two words of
+// codes (each code < 16, one per byte) pack into one word of eight nibbles,
+// the lower k in the lower nibble.
+__device__ __forceinline__ uint32_t fp4_codes(uint32_t x4, uint32_t lut_lo, uint32_t lut_hi) {
+    return __builtin_amdgcn_perm(lut_hi, lut_lo, x4);
+}
+__device__ __forceinline__ uint32_t fp4_pack(uint32_t c_lo, uint32_t c_hi) {
+    const uint32_t a = c_lo | (c_lo >> 4), b = c_hi | (c_hi >> 4);  // bytes 0 and 2 hold nibble pairs
+    return __builtin_amdgcn_perm(b, a, 0x06040200u);
+}
+
+// A4 rows: thread (x, row) turns residues 32 s .. 32 s + 31 of the row (zero past k)
+// into 16 bytes of codes at byte 16 s of the packed row.
+__global__ __launch_bounds__(256) void pack_fp4_rows_kernel(int64_t m, int64_t k, const uint8_t *__restrict__ A,
+                                                            int64_t lda, uint8_t *__restrict__ A4, int64_t lda4,
+                                                            uint32_t lut_lo, uint32_t lut_hi, int a_vec) {
+    const int64_t segs = lda4 / 16;
+    for (int64_t r = blockIdx.y; r < m; r += gridDim.y) {
+        const uint8_t *row = A + r * lda;
+        for (int64_t sg = (int64_t)blockIdx.x * 256 + threadIdx.x; sg < segs; sg += (int64_t)gridDim.x * 256) {
+            const int64_t k0 = 32 * sg;
+            uint32_t w[8];
+            if (a_vec && k0 + 32 <= k) {
+                const uint4 v0 = *(const uint4 *)(row + k0), v1 = *(const uint4 *)(row + k0 + 16);
+                w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
+                w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) w[i] = 0;
+                for (int b = 0; b < 32; ++b)
+                    if (k0 + b < k) w[b >> 2] |= (uint32_t)row[k0 + b] << (8 * (b & 3));
+            }
+            uint32_t o[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                o[i] = fp4_pack(fp4_codes(w[2 * i], lut_lo, lut_hi), fp4_codes(w[2 * i + 1], lut_lo, lut_hi));
+            *(ux4 *)(A4 + r * lda4 + 16 * sg) = ux4{o[0], o[1], o[2], o[3]};
+        }
+    }
+}
+
+// Bt4[n0 + c][(k0 + r) / 2] = code(B[k0 + r][n0 + c]) for a 128 (k) x 128 (n) tile:
+// the loads, LDS tile and register transposes of centre_transpose_kernel, with the
+// codes looked up on the way into LDS and each column's 16 k packed into 8 bytes.
+__global__ __launch_bounds__(256) void pack_fp4_cols_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
+                                                            int64_t ldb, uint8_t *__restrict__ Bt4, int64_t ldbt4,
+                                                            uint32_t lut_lo, uint32_t lut_hi, int b_vec) {
+    __shared__ uint32_t tile[CT][CT / 4 + 1];
+    const int64_t k0 = (int64_t)blockIdx.y * CT, n0 = (int64_t)blockIdx.x * CT;
+    const int t = threadIdx.x;
+    {
+        const int seg = t & 7, r0 = t >> 3;
+        const int64_t nn = n0 + 16 * seg;
+        uint4 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t kk = k0 + r0 + 32 * i;
+            v[i] = make_uint4(0, 0, 0, 0);
+            if (kk < k) {
+                const uint8_t *src = B + kk * ldb + nn;
+                if (b_vec && nn + 16 <= n) {
+                    v[i] = *(const uint4 *)src;
+                } else {
+                    uint32_t w[4] = {0, 0, 0, 0};
+                    for (int b = 0; b < 16; ++b)
+                        if (nn + b < n) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+                    v[i] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t *dst = &tile[r0 + 32 * i][4 * seg];
+            dst[0] = fp4_codes(v[i].x, lut_lo, lut_hi);
+            dst[1] = fp4_codes(v[i].y, lut_lo, lut_hi);
+            dst[2] = fp4_codes(v[i].z, lut_lo, lut_hi);
+            dst[3] = fp4_codes(v[i].w, lut_lo, lut_hi);
+        }
+    }
+    __syncthreads();
+    const int cg = t & 31, kg = t >> 5;
+    uint32_t out[4][4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t r0 = tile[16 * kg + 4 * d + 0][cg], r1 = tile[16 * kg + 4 * d + 1][cg];
+        const uint32_t r2 = tile[16 * kg + 4 * d + 2][cg], r3 = tile[16 * kg + 4 * d + 3][cg];
+        const uint32_t lo01 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
+        const uint32_t lo23 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+        const uint32_t hi01 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+        const uint32_t hi23 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+        out[0][d] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+        out[1][d] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+        out[2][d] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+        out[3][d] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+    }
+    // rows past k were loaded as zero, whose code is 0, so Bt4's padding is zero
+    const int64_t kb = (k0 + 16 * kg) / 2;  // packed byte offset of this thread's 16 k
+    if (kb >= ldbt4) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t nn = n0 + 4 * cg + q;
+        if (nn < n)
+            *(ux2 *)(Bt4 + nn * ldbt4 + kb) = ux2{fp4_pack(out[q][0], out[q][1]), fp4_pack(out[q][2], out[q][3])};
+    }
+}
+
 template <int BM, int BN>
 __device__ __forceinline__ void tile_coords(int64_t m, int64_t n, int &tm, int &tn) {
     const int tiles_m = (int)ceil_div(m, BM), tiles_n = (int)ceil_div(n, BN);
@@ -152,8 +267,14 @@ struct Int8Args {
 // 16-byte segment below k is one vector load; segments past k or rows past m
 // load from a clamped, valid address and are zeroed by a select (no branches in
 // the loop).  Otherwise segments are assembled from byte loads.
-template <int BM, int BN, int KT, int WGM, int WGN, bool BLOCKED, bool AVEC>
+// FP4: both operands are packed e2m1 codes (two k per byte, A already converted,
+// g.k counts packed bytes), and each 16-byte fragment feeds the FP4 form of the
+// MFMA, v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales: 64 k per instruction
+// into FP32 accumulators (lane l holds 32 codes of row l % 32 for k-half l / 32,
+// in the same order for both operands; outputs as for the int8 form).
+template <int BM, int BN, int KT, int WGM, int WGN, bool BLOCKED, bool AVEC, bool FP4>
 __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * WGN) ? 1 : 2) void gemm_int8_kernel(Int8Args g) {
+    using AccT = typename std::conditional<FP4, fx16, ix16>::type;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int PITCH = KT + 16;
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
@@ -171,11 +292,11 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
     tile_coords<BM, BN>(g.m, g.n, tm, tn);
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
 
-    ix16 acc[FM][FN];
+    AccT acc[FM][FN];
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
+        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = AccT{};
 
     // Staging: segment c = tid + NT i covers row c / SEGS, bytes 16 (c % SEGS) .. +15.
     // Row pointers and validity are fixed for the whole k loop.
@@ -202,7 +323,11 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
 #pragma unroll
         for (int i = 0; i < A_LOADS; ++i) {
             const int64_t kk = k0 + ((tid + NT * i) % SEGS) * 16;
-            if constexpr (AVEC) {
+            if constexpr (FP4) {
+                // packed rows are zero padded to whole stages; rows past m are clamped
+                // to row 0 and only reach outputs that are not stored
+                ra[i] = *(const uint4 *)(a_ptr[i] + k0);
+            } else if constexpr (AVEC) {
                 // a segment past k (or a row past m) reads A's first 16 bytes instead
                 const bool ok = a_ok[i] && kk < g.k;
                 const uint4 v = *(const uint4 *)(ok ? a_ptr[i] + k0 : g.A);
@@ -223,7 +348,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
         for (int i = 0; i < B_LOADS; ++i) {
             // Bt rows are zero-padded to ldbt (a multiple of the stage), so whole stages are in bounds.
             const uint4 v = *(const uint4 *)(b_ptr[i] + k0);
-            rb[i] = b_ok[i] ? v : make_uint4(0, 0, 0, 0);
+            if constexpr (FP4)
+                rb[i] = v;  // rows past n (clamped to row 0) only reach outputs that are not stored
+            else
+                rb[i] = b_ok[i] ? v : make_uint4(0, 0, 0, 0);
         }
     };
     // The loads of a stage are only consumed here, after the MFMAs of the previous
@@ -233,10 +361,12 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
         for (int i = 0; i < A_LOADS; ++i) {
             const int c = tid + NT * i;
             uint4 v = ra[i];
-            v.x = centre4(v.x, g.add_h, g.neg_p);
-            v.y = centre4(v.y, g.add_h, g.neg_p);
-            v.z = centre4(v.z, g.add_h, g.neg_p);
-            v.w = centre4(v.w, g.add_h, g.neg_p);
+            if constexpr (!FP4) {
+                v.x = centre4(v.x, g.add_h, g.neg_p);
+                v.y = centre4(v.y, g.add_h, g.neg_p);
+                v.z = centre4(v.z, g.add_h, g.neg_p);
+                v.w = centre4(v.w, g.add_h, g.neg_p);
+            }
             *(uint4 *)&sA[buf][(c / SEGS) * PITCH + (c % SEGS) * 16] = v;
         }
 #pragma unroll
@@ -272,7 +402,14 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
             for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < FN; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
+                    if constexpr (FP4) {
+                        const ix4 a = af[cur][mi], b = bf[cur][ni];
+                        acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            ix8{a.x, a.y, a.z, a.w, 0, 0, 0, 0}, ix8{b.x, b.y, b.z, b.w, 0, 0, 0, 0}, acc[mi][ni],
+                            4, 4, 0, 127, 0, 127);  // e2m1 x e2m1, scales 2^(127-127) = 1
+                    } else {
+                        acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
+                    }
             // Interleave: one MFMA, then one of the next k-step's LDS reads, so the
             // reads' latency hides behind the matrix core instead of stalling it.
             if (ks + 1 < KT / 32) {
@@ -291,8 +428,12 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
 #pragma unroll
                     for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            acc[mi][ni][r] = (int)mod_i32_magic(acc[mi][ni][r], g.p, g.magic, g.off);
+                        for (int r = 0; r < 16; ++r) {
+                            if constexpr (FP4)  // an exact integer below 2^24 in magnitude
+                                acc[mi][ni][r] = (float)mod_i32_magic((int32_t)acc[mi][ni][r], g.p, g.magic, g.off);
+                            else
+                                acc[mi][ni][r] = (int)mod_i32_magic(acc[mi][ni][r], g.p, g.magic, g.off);
+                        }
             }
         }
         if (kt + 1 < ntiles) {
@@ -310,7 +451,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
                 const int64_t row = row0 + wm * WTM + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int64_t col = col0 + wn * WTN + ni * 32 + (lane & 31);
                 if (row < g.m && col < g.n)
-                    g.C[row * g.ldc + col] = (uint8_t)mod_i32_magic(acc[mi][ni][r], g.p, g.magic, g.off);
+                    g.C[row * g.ldc + col] = (uint8_t)mod_i32_magic((int32_t)acc[mi][ni][r], g.p, g.magic, g.off);
             }
 }
 
@@ -318,6 +459,21 @@ qmm_status check_launch(const char *what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(QMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     return QMM_OK;
+}
+
+// Codes of the residues 0..7 (centred, then e2m1: magnitudes 0, 1, 2, 3, 4 are the
+// codes 0, 2, 4, 5, 6, sign bit 8), bytes 0..3 in lo and 4..7 in hi; residues >= p
+// (not valid input) get code 0.
+void fp4_lut(uint32_t p, uint32_t &lo, uint32_t &hi) {
+    static const uint32_t mag_code[5] = {0, 2, 4, 5, 6};
+    uint64_t lut = 0;
+    for (uint32_t x = 0; x < 8 && x < p; ++x) {
+        const int32_t c = x > (p - 1) / 2 ? (int32_t)x - (int32_t)p : (int32_t)x;
+        const uint32_t code = mag_code[c < 0 ? -c : c] | (c < 0 ? 8u : 0u);
+        lut |= (uint64_t)code << (8 * x);
+    }
+    lo = (uint32_t)lut;
+    hi = (uint32_t)(lut >> 32);
 }
 
 void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
@@ -353,14 +509,27 @@ qmm_status run_int8(const Int8Args &g, bool blocked, hipStream_t s) {
     const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)));
     const bool avec = g.a_vec && g.k % 16 == 0;
     if (blocked && avec)
-        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, true, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
     else if (blocked)
-        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, false, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
     else if (avec)
-        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false, true, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
     else
-        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+        gemm_int8_kernel<BM, BN, KT, WGM, WGN, false, false, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
     return check_launch("gemm_int8");
+}
+
+// FP4: packed rows are 16-byte aligned with whole 16-byte segments (ld4 a multiple
+// of 128, g.k rounded up to 16 packed bytes), so A always takes the vector loads.
+// Only the blocked variant is built: an unblocked product runs it with one block
+// longer than k (the per-stage block test is one scalar step; the variant without
+// it is scheduled by the compiler into more registers than four wavefronts per
+// SIMD allow, and spills).
+template <int BM, int BN, int KT, int WGM, int WGN>
+qmm_status run_fp4(const Int8Args &g, hipStream_t s) {
+    const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)));
+    gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, true, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
+    return check_launch("gemm_fp4");
 }
 }  // namespace
 
@@ -368,6 +537,72 @@ int int8_tile_for(int64_t m, int64_t n) {
     // 256 x 256 tiles (16 wavefronts of 64 x 64) once they (nearly) fill the 256 CUs,
     // 128 x 128 below that.
     return (ceil_div(m, 256) * ceil_div(n, 256) >= 192) ? 3 : 1;
+}
+
+// Packed FP4 rows: ceil(k/2) bytes rounded up to 128, plus one 128-byte line at
+// multiples of 2 KiB (as for Bt).
+int64_t fp4_ld(int64_t k) {
+    const int64_t r = ceil_div(ceil_div(k < 1 ? 1 : k, 2), kBtAlign) * kBtAlign;
+    return r % 2048 == 0 ? r + kBtAlign : r;
+}
+
+qmm_status launch_pack_fp4_rows(const qmm_plan &pl, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
+                                uint8_t *A4, int64_t lda4, void *stream) {
+    if (m == 0) return QMM_OK;
+    uint32_t lo, hi;
+    fp4_lut(pl.p, lo, hi);
+    const int64_t segs = lda4 / 16;
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(ceil_div(segs, 256), 64));
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(m, 65535));
+    const int a_vec = ((uintptr_t)A % 16 == 0) && (lda % 16 == 0);
+    pack_fp4_rows_kernel<<<dim3((unsigned)gx, (unsigned)gy), 256, 0, (hipStream_t)stream>>>(m, k, A, lda, A4, lda4, lo,
+                                                                                             hi, a_vec);
+    return check_launch("pack_fp4_rows");
+}
+
+qmm_status launch_pack_fp4_cols(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                uint8_t *Bt4, int64_t ldbt4, void *stream) {
+    if (n == 0) return QMM_OK;
+    uint32_t lo, hi;
+    fp4_lut(pl.p, lo, hi);
+    const dim3 grid((unsigned)ceil_div(n, CT), (unsigned)ceil_div(2 * ldbt4, CT));
+    const int b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
+    pack_fp4_cols_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt4, ldbt4, lo, hi, b_vec);
+    return check_launch("pack_fp4_cols");
+}
+
+qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A4, int64_t lda4,
+                           const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc, void *stream) {
+    if (m == 0 || n == 0) return QMM_OK;
+    Int8Args g{};
+    g.m = m;
+    g.n = n;
+    g.k = ceil_div(ceil_div(k, 2), 16) * 16;  // packed bytes, whole 16-byte segments (zero padded)
+    g.A = A4;
+    g.lda = lda4;
+    g.Bt = (const int8_t *)Bt4;
+    g.ldbt = ldbt4;
+    g.C = C;
+    g.ldc = ldc;
+    const bool blocked = pl.k_block < k;
+    g.p = pl.p;
+    g.magic = mod_magic(pl.p);
+    g.off = pl.p * ((1u << 31) / pl.p);
+    g.a_vec = true;
+    hipStream_t s = (hipStream_t)stream;
+    const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n);
+    // one K stage of KT packed bytes holds 2 KT values of k
+    const int32_t never = INT32_MAX;
+    if (tile == 2) {
+        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 256) : never;
+        return run_fp4<256, 256, 128, 2, 4>(g, s);
+    }
+    if (tile == 3) {
+        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 256) : never;
+        return run_fp4<256, 256, 128, 4, 4>(g, s);
+    }
+    g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : never;
+    return run_fp4<128, 128, 64, 2, 2>(g, s);
 }
 
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,

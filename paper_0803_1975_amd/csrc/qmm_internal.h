@@ -14,6 +14,7 @@ constexpr int kQadicKT = 16;
 // Largest K stage of the INT8 kernels, in bytes.  Blocks of the INT8 path are
 // multiples of it (and so whole stages of every INT8 kernel).
 constexpr int kInt8KT = 128;
+constexpr int kFp4KB = 256;  // FP4 k-block granularity: one 128-byte K stage of packed codes
 // Cost of one block boundary (extraction + reduction of every output) in units of
 // one packed word of MFMA work per output; used to rank blocked plans.
 constexpr int kBlockCostWords = 8;
@@ -80,6 +81,13 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
                             uint8_t *C, int64_t ldc, void *stream);
 int64_t int8_bt_ld(int64_t k);
+int64_t fp4_ld(int64_t k);
+qmm_status launch_pack_fp4_rows(const qmm_plan &pl, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
+                                uint8_t *A4, int64_t lda4, void *stream);
+qmm_status launch_pack_fp4_cols(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                uint8_t *Bt4, int64_t ldbt4, void *stream);
+qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A4, int64_t lda4,
+                           const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc, void *stream);
 int int8_tile_for(int64_t m, int64_t n);
 
 }  // namespace qmm

@@ -181,6 +181,23 @@ qmm_status choose_int8(uint32_t p, int64_t k, qmm_plan *out) {
     return QMM_OK;
 }
 
+// FP4: centred residues are exact e2m1 values for p <= 8 (|x| <= 4); a block
+// starts from the previous block's residue (< p) and adds kb products of at most
+// floor(p/2)^2 each, and every partial sum must stay an integer the FP32
+// accumulator holds exactly (|s| <= 2^24).  Blocks are whole 256-value K stages.
+qmm_status choose_fp4(uint32_t p, int64_t k, qmm_plan *out) {
+    base_plan(out, p, QMM_PATH_FP4);
+    if (p > 8) return fail(QMM_EVALUE, "FP4 path needs p <= 8");
+    const int64_t h = p / 2;
+    const int64_t lim = (((int64_t)1 << 24) - (int64_t)(p - 1)) / (h * h);
+    int64_t kb = k;
+    if (k > lim) kb = (lim / kFp4KB) * kFp4KB;
+    out->beta = 24;
+    out->k_block = kb < 1 ? 1 : kb;
+    out->regime = QMM_REGIME_INT;
+    return QMM_OK;
+}
+
 }  // namespace
 
 void set_error(const std::string &msg) { g_last_error = msg; }
@@ -215,10 +232,12 @@ extern "C" qmm_status qmm_choose_Qd(uint32_t p, int64_t m, int64_t n, int64_t k,
     (void)m;
     const int64_t kk = k < 1 ? 1 : k;
     uint32_t pth = (uint32_t)path;
-    if (pth == QMM_PATH_AUTO) pth = (p <= 256) ? QMM_PATH_INT8 : QMM_PATH_FP64_QADIC;
-    if (pth > QMM_PATH_INT8) return fail(QMM_EINVAL, "unknown path");
+    // Automatic choice: FP4 matrix cores (twice the INT8 rate, half the operand bytes)
+    // when every centred residue is an e2m1 value, INT8 for other byte residues.
+    if (pth == QMM_PATH_AUTO) pth = p <= 8 ? QMM_PATH_FP4 : (p <= 256 ? QMM_PATH_INT8 : QMM_PATH_FP64_QADIC);
+    if (pth > QMM_PATH_FP4) return fail(QMM_EINVAL, "unknown path");
     if (beta == 0) beta = default_beta(pth);
-    if (pth != QMM_PATH_INT8 && ((path_is_fp64(pth) && beta != 53) || (path_is_fp32(pth) && beta != 24)) &&
+    if (pth != QMM_PATH_INT8 && pth != QMM_PATH_FP4 && ((path_is_fp64(pth) && beta != 53) || (path_is_fp32(pth) && beta != 24)) &&
         !(flags & QMM_BOUND_PAPER))
         return fail(QMM_EINVAL, "beta must match the path (53 for FP64, 24 for FP32)");
     if (flags & QMM_BOUND_PAPER) {
@@ -237,6 +256,7 @@ extern "C" qmm_status qmm_choose_Qd(uint32_t p, int64_t m, int64_t n, int64_t k,
         return (e >= 1) ? QMM_OK : fail(QMM_EBOUND, "no d >= 0 under the paper's rule");
     }
     if (pth == QMM_PATH_INT8) return choose_int8(p, kk, out);
+    if (pth == QMM_PATH_FP4) return choose_fp4(p, kk, out);
     if (path_is_redq(pth)) return choose_redq(p, n, kk, beta, pth, out);
     return choose_qadic(p, kk, beta, pth, flags, out);
 }
@@ -256,6 +276,17 @@ extern "C" qmm_status qmm_validate_plan(const qmm_plan *pl, int64_t m, int64_t n
         if (pl->tile > 3) return fail(QMM_EINVAL, "INT8 tile must be 0 (auto) or 1..3");
         if ((__int128)kb * h * h + (pl->p - 1) > (((__int128)1 << 31) - 1))
             return fail(QMM_EBOUND, "INT8 k_block overflows int32");
+        return QMM_OK;
+    }
+    case QMM_PATH_FP4: {
+        if (pl->p > 8) return fail(QMM_EVALUE, "FP4 path needs p <= 8");
+        const int64_t h = pl->p / 2;
+        const int64_t kb = pl->k_block;
+        if (kb < 1) return fail(QMM_EBOUND, "k_block < 1");
+        if (kb < kk && kb % kFp4KB) return fail(QMM_EBOUND, "FP4 k_block must be a multiple of 256");
+        if (pl->tile > 3) return fail(QMM_EINVAL, "FP4 tile must be 0 (auto) or 1..3");
+        if ((__int128)kb * h * h + (pl->p - 1) > ((__int128)1 << 24))
+            return fail(QMM_EBOUND, "FP4 k_block leaves the exact FP32 integers");
         return QMM_OK;
     }
     case QMM_PATH_FP64_QADIC:

@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(HERE, "libqmm.so")
 OK, EINVAL, EBOUND, EVALUE, ENOSPACE, EDEVICE, EUNSUPPORTED = range(7)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EBOUND", 3: "EVALUE", 4: "ENOSPACE", 5: "EDEVICE", 6: "EUNSUPPORTED"}
 # qmm_path
-PATH_AUTO, PATH_FP64_QADIC, PATH_FP64_REDQ, PATH_FP32_QADIC, PATH_FP32_REDQ, PATH_INT8 = range(6)
-PATH_NAMES = {0: "auto", 1: "fp64_qadic", 2: "fp64_redq", 3: "fp32_qadic", 4: "fp32_redq", 5: "int8"}
+PATH_AUTO, PATH_FP64_QADIC, PATH_FP64_REDQ, PATH_FP32_QADIC, PATH_FP32_REDQ, PATH_INT8, PATH_FP4 = range(7)
+PATH_NAMES = {0: "auto", 1: "fp64_qadic", 2: "fp64_redq", 3: "fp32_qadic", 4: "fp32_redq", 5: "int8", 6: "fp4"}
 # qmm_regime
 REGIME_EXACT, REGIME_OFFSET, REGIME_PAPER, REGIME_INT = range(4)
 REGIME_NAMES = {0: "exact", 1: "offset", 2: "paper", 3: "int"}
@@ -37,6 +37,7 @@ EXPORTS = [
     "qmm_batched_create", "qmm_gemm_mod_p_batched", "qmm_batched_plan", "qmm_batched_destroy",
     "qmm_last_error", "qmm_version", "qmm_pack_centred_cols", "qmm_gemm_centred",
     "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs", "qmm_count_nonresidues",
+    "qmm_pack_fp4_rows", "qmm_pack_fp4_cols", "qmm_gemm_fp4",
 ]
 
 
@@ -100,6 +101,9 @@ def lib():
             "qmm_batched_tune": [vp, ctypes.POINTER(ctypes.c_double)],
             "qmm_batched_set_costs": [ctypes.POINTER(ctypes.c_double)],
             "qmm_count_nonresidues": [u32, i64, i64, vp, i64, vp, vp],
+            "qmm_pack_fp4_rows": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_pack_fp4_cols": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_gemm_fp4": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -385,3 +389,45 @@ def batched_set_costs(costs):
         raise ValueError(f"expected {N_BATCH_COSTS} costs, got {len(costs)}")
     arr = (ctypes.c_double * N_BATCH_COSTS)(*costs)
     _check(lib().qmm_batched_set_costs(arr), "qmm_batched_set_costs")
+
+
+def fp4_ld(k) -> int:
+    """Row stride (bytes) of packed FP4 operands: ceil(k/2) rounded up to 128, plus one
+    128-byte line when that is a multiple of 2048 (the library's own choice)."""
+    r = max(1, -(-(-(-max(k, 1) // 2)) // 128)) * 128
+    return r + 128 if r % 2048 == 0 else r
+
+
+def pack_fp4_rows(plan, A, A4=None, stream=None):
+    """FP4 conversion of the left operand: A4 = codes of centred(A) (m x fp4_ld(k) bytes)."""
+    import torch
+    _u8(A, "A")
+    m, k = A.shape
+    if A4 is None:
+        A4 = torch.empty((m, fp4_ld(k)), dtype=torch.uint8, device=A.device)
+    _check(lib().qmm_pack_fp4_rows(ctypes.byref(plan), m, k, _ptr(A), _ld(A), _ptr(A4), _ld(A4), _stream(stream)),
+           "qmm_pack_fp4_rows")
+    return A4
+
+
+def pack_fp4_cols(plan, B, Bt4=None, stream=None):
+    """FP4 conversion of the right operand: Bt4 = codes of centred(B)^T (n x fp4_ld(k) bytes)."""
+    import torch
+    _u8(B, "B")
+    k, n = B.shape
+    if Bt4 is None:
+        Bt4 = torch.empty((n, fp4_ld(k)), dtype=torch.uint8, device=B.device)
+    _check(lib().qmm_pack_fp4_cols(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(Bt4), _ld(Bt4), _stream(stream)),
+           "qmm_pack_fp4_cols")
+    return Bt4
+
+
+def gemm_fp4(plan, A4, Bt4, k, C=None, stream=None):
+    """FP4 product step: C = (A4 x Bt4^T) mod p from the packed operands."""
+    import torch
+    m, n = A4.shape[0], Bt4.shape[0]
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=A4.device)
+    _check(lib().qmm_gemm_fp4(ctypes.byref(plan), m, n, k, _ptr(A4), _ld(A4), _ptr(Bt4), _ld(Bt4), _ptr(C), _ld(C),
+                              _stream(stream)), "qmm_gemm_fp4")
+    return C

@@ -131,3 +131,20 @@ def test_count_nonresidues_checks_arguments_before_device_work():
     assert L.qmm_count_nonresidues(7, 4, 8, fake, 4, cnt, None) == qmm.EINVAL      # ldx < cols
     assert L.qmm_count_nonresidues(7, 4, 4, fake, 4, None, None) == qmm.EINVAL
     assert L.qmm_count_nonresidues(7, 4, 4, fake, 4, ctypes.c_void_p((1 << 21) + 2), None) == qmm.EINVAL
+
+
+def test_fp4_entry_points_check_arguments_before_device_work():
+    L = qmm.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    pl = qmm.choose_Qd(7, 64, 64, 256, path=qmm.PATH_FP4)
+    i8 = qmm.choose_Qd(7, 64, 64, 256, path=qmm.PATH_INT8)
+    P = ctypes.byref(pl)
+    assert L.qmm_pack_fp4_rows(ctypes.byref(i8), 4, 256, fake, 256, fake, 128, None) == qmm.EINVAL  # wrong path
+    assert L.qmm_pack_fp4_rows(P, 4, 256, fake, 256, fake, 64, None) == qmm.EINVAL      # ld4 not a multiple of 128
+    assert L.qmm_pack_fp4_rows(P, 4, 512, fake, 512, fake, 128, None) == qmm.EINVAL     # 2 ld4 < k
+    assert L.qmm_pack_fp4_cols(P, 256, 4, fake, 4, ctypes.c_void_p((1 << 20) + 8), 128, None) == qmm.EINVAL
+    assert L.qmm_gemm_fp4(P, 4, 4, 256, fake, 128, None, 128, fake, 4, None) == qmm.EINVAL
+    bad = qmm.Plan.from_buffer_copy(pl)
+    bad.p = 11
+    assert L.qmm_gemm_fp4(ctypes.byref(bad), 4, 4, 256, fake, 128, fake, 128, fake, 4, None) == qmm.EVALUE
+    assert qmm.fp4_ld(4096) % 128 == 0 and 2 * qmm.fp4_ld(4096) >= 4096

@@ -132,3 +132,32 @@ def test_redq_one_division_identity():
         s = r // p
         for i in range(d + 1):
             assert (r >> (t * i)) - p * (s >> (t * i)) == (r >> (t * i)) % p
+
+
+def test_e2m1_table_and_which_primes_fit():
+    # the e2m1 format's sixteen codes decode to the published magnitudes
+    mags = sorted({abs(bounds.e2m1_value(c)) for c in range(16)})
+    assert [float(v) for v in mags] == [0, 0.5, 1, 1.5, 2, 3, 4, 6]
+    assert bounds.e2m1_value(0b0101) == 3 and bounds.e2m1_value(0b1110) == -4 and bounds.e2m1_value(0b1000) == 0
+    # centred residues are exact e2m1 values up to p = 9 (|x| <= 4); from p = 10 on
+    # some |x| = 5 appears, which e2m1 cannot hold
+    assert all(bounds.fp4_representable(p) for p in range(2, 10))
+    assert not any(bounds.fp4_representable(p) for p in range(10, 40))
+
+
+@pytest.mark.parametrize("p", (7, 8))
+def test_fp32_accumulation_bound_is_tight(p):
+    # Worst case: every product is h^2 (h = floor(p/2)) and the block starts from the
+    # residue p - 1.  Summed in 64-product groups (one MFMA) with one rounding to
+    # 24 significant bits per group: exact at the largest admissible block, wrong
+    # one product later, where the sum is an odd integer above 2^24.
+    h = bounds.centred_max(p)
+    kb = ((1 << 24) - (p - 1)) // (h * h)
+    assert bounds.fp4_block_ok(p, kb) and not bounds.fp4_block_ok(p, kb + 1)
+    inside = emulate.accumulate([h] * kb, [h] * kb, 24, start=p - 1, g=64)
+    assert inside == kb * h * h + (p - 1)
+    exact = (kb + 1) * h * h + (p - 1)
+    outside = emulate.accumulate([h] * (kb + 1), [h] * (kb + 1), 24, start=p - 1, g=64)
+    assert exact % 2 and exact > 1 << 24           # odd above 2^24: not a float32
+    assert outside != exact and outside % p != exact % p
+

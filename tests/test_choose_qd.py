@@ -115,10 +115,15 @@ def test_workload_plans():
     # graph: unblocked t = 17, d = 2
     pl = qmm.choose_Qd(3, 16384, 16384, 16384, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4)
     assert (pl.t, pl.d, pl.regime) == (17, 2, qmm.REGIME_OFFSET)
-    # INT8: no blocking needed at these sizes, and AUTO picks it for byte residues
+    # no blocking needed at these sizes; AUTO picks FP4 where every centred residue is
+    # an e2m1 value (p <= 8 on this path) and INT8 for other byte residues
     for p, k in ((7, 4096), (101, 8192), (3, 16384)):
         pl = qmm.choose_Qd(p, k, k, k)
-        assert pl.path == qmm.PATH_INT8 and pl.k_block == k
+        assert pl.path == (qmm.PATH_FP4 if p <= 8 else qmm.PATH_INT8) and pl.k_block == k
+    for p in range(2, 257):
+        want = qmm.PATH_FP4 if p <= 8 else qmm.PATH_INT8
+        assert qmm.choose_Qd(p, 64, 64, 64).path == want, p
+        assert p > 8 or bounds.fp4_representable(p)
 
 
 def test_redq_plans():
@@ -131,6 +136,24 @@ def test_redq_plans():
     assert bounds.redq_ok(3, 300, pl.t, pl.d, 24)
     pl = qmm.choose_Qd(3, 64, 2, 64, path=qmm.PATH_FP64_REDQ)
     assert pl.d == 1                           # never more residues per word than columns
+
+
+def test_fp4_blocks():
+    for p in (2, 3, 5, 7, 8):
+        k = 10 ** 8                                # past the bound for every p
+        pl = qmm.choose_Qd(p, 4, 4, k, path=qmm.PATH_FP4)
+        assert pl.k_block < k
+        assert pl.path == qmm.PATH_FP4 and pl.beta == 24 and pl.regime == qmm.REGIME_INT
+        assert bounds.fp4_block_ok(p, pl.k_block) and pl.k_block % 256 == 0
+        assert not bounds.fp4_block_ok(p, pl.k_block + 256)      # the largest whole-stage block
+        assert qmm.validate_plan(pl, 4, 4, k) == qmm.OK
+        big = qmm.Plan.from_buffer_copy(pl)
+        big.k_block += 256
+        assert qmm.validate_plan(big, 4, 4, k) == qmm.EBOUND
+    assert qmm.choose_Qd(7, 4, 4, 1000, path=qmm.PATH_FP4).k_block == 1000
+    for p in (9, 11, 101):
+        st, _ = qmm.try_choose_Qd(p, 4, 4, 16, path=qmm.PATH_FP4)
+        assert st == qmm.EVALUE
 
 
 def test_int8_blocks():

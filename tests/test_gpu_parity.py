@@ -17,7 +17,8 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-PATHS = (qmm.PATH_FP64_QADIC, qmm.PATH_FP64_REDQ, qmm.PATH_FP32_QADIC, qmm.PATH_FP32_REDQ, qmm.PATH_INT8)
+PATHS = (qmm.PATH_FP64_QADIC, qmm.PATH_FP64_REDQ, qmm.PATH_FP32_QADIC, qmm.PATH_FP32_REDQ, qmm.PATH_INT8,
+         qmm.PATH_FP4)
 
 
 @pytest.fixture(scope="module")
@@ -314,9 +315,9 @@ def test_graph_workload_and_paley_closed_form(torch):
     diff = (x[:, None] - x[None, :]) % q
     Ad = is_sq[diff].to(torch.uint8)
     del diff
-    for path in (qmm.PATH_INT8, qmm.PATH_FP64_QADIC):
+    for path in (qmm.PATH_FP4, qmm.PATH_INT8, qmm.PATH_FP64_QADIC):
         for flags in (0, qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4):
-            if path == qmm.PATH_INT8 and flags:
+            if path in (qmm.PATH_INT8, qmm.PATH_FP4) and flags:
                 continue
             plan = qmm.choose_Qd(3, q, q, q, path=path, flags=flags)
             note("paley", plan)
@@ -394,3 +395,67 @@ def test_count_nonresidues_and_validated_product(torch):
     with pytest.raises(qmm.QmmError) as ei:
         qmm.gemm_mod_p(dA, dB, p, validate=True)
     assert ei.value.status == qmm.EVALUE and "1 of B" in str(ei.value)
+
+
+@pytest.mark.parametrize("p,m,n,k", [(7, 300, 272, 1040), (2, 1, 16, 16), (3, 257, 512, 4096), (5, 640, 48, 12000),
+                                     (8, 33, 1024, 16), (7, 96, 64, 1984), (3, 130, 70, 257)])
+def test_fp4_stages_match_one_call_and_oracle(torch, p, m, n, k):
+    # The FP4 stage calls (both conversions, product) give what qmm_gemm_mod_p gives,
+    # on every tile variant; k across 256-value stage edges and ragged tiles.
+    note("fp4 stages", p, m, n, k)
+    rng = np.random.default_rng(m + n + k + p)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    dA, dB = dev(torch, A), dev(torch, B)
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP4)
+    one = qmm.gemm_mod_p(dA, dB, p, plan=plan)
+    A4 = qmm.pack_fp4_rows(plan, dA)
+    Bt4 = qmm.pack_fp4_cols(plan, dB)
+    for tile in (1, 2, 3):
+        plan.tile = tile
+        assert torch.equal(qmm.gemm_fp4(plan, A4, Bt4, k), one), tile
+    if m * n * k <= 2 ** 28:
+        np.testing.assert_array_equal(host(one), ref.modmul(A, B, p))
+    else:
+        sampled_check(torch, A, B, p, host(one), nsamp=4000, rows=2)
+
+
+def test_fp4_codes_match_the_oracle_encoding(torch):
+    # the packed operands decode (by the oracle's e2m1 table) to the centred residues
+    from oracle import bounds
+    for p in (2, 3, 5, 7, 8):
+        rng = np.random.default_rng(p)
+        A = rng.integers(0, p, (5, 77), dtype=np.uint8)
+        plan = qmm.choose_Qd(p, 5, 5, 77, path=qmm.PATH_FP4)
+        A4 = host(qmm.pack_fp4_rows(plan, dev(torch, A)))
+        codes = np.stack([A4 & 15, A4 >> 4], axis=-1).reshape(5, -1)     # even k in the low nibble
+        vals = np.vectorize(lambda c: float(bounds.e2m1_value(int(c))))(codes)
+        np.testing.assert_array_equal(vals[:, :77], ref.centre(A, p))
+        assert (codes[:, 77:] == 0).all()                                # zero past k
+        Bt4 = host(qmm.pack_fp4_cols(plan, dev(torch, A.T.copy())))
+        np.testing.assert_array_equal(Bt4[:, :A4.shape[1]], A4[:, :Bt4.shape[1]])
+
+
+def test_fp4_worst_case_and_blocked_accumulation(torch):
+    # all operands at the largest centred magnitude: sums of k h^2, blocked once k h^2
+    # leaves the exact FP32 integers (p = 7: past 1 864 134 products)
+    for p, v, k in ((7, 3, 70000), (7, 4, 2000000), (8, 4, 1100000), (3, 2, 40000)):
+        plan = qmm.choose_Qd(p, 16, 24, k, path=qmm.PATH_FP4)
+        note("fp4 worst", plan, v, k)
+        assert (plan.k_block < k) == (k * (p // 2) ** 2 + p - 1 > 2 ** 24)
+        A = torch.full((16, k), v, dtype=torch.uint8, device="cuda")
+        B = torch.full((k, 24), v, dtype=torch.uint8, device="cuda")
+        C = host(qmm.gemm_mod_p(A, B, p, plan=plan))
+        assert (C == (k * v * v) % p).all(), (plan, np.unique(C))
+        del A, B
+    # forced short blocks on random data, every tile
+    rng = np.random.default_rng(9)
+    p, k = 5, 3000
+    A = rng.integers(0, p, (50, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, 40), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    for tile in (1, 2, 3):
+        plan = qmm.choose_Qd(p, 50, 40, k, path=qmm.PATH_FP4)
+        plan.k_block, plan.tile = 512, tile
+        np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=plan)), want, err_msg=f"tile {tile}")
