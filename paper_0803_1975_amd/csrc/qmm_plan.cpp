@@ -229,12 +229,16 @@ extern "C" qmm_status qmm_choose_Qd(uint32_t p, int64_t m, int64_t n, int64_t k,
     if (!out) return fail(QMM_EINVAL, "out is NULL");
     if (p < 2) return fail(QMM_EINVAL, "p must be >= 2");
     if (m < 0 || n < 0 || k < 0) return fail(QMM_EINVAL, "negative size");
-    (void)m;
     const int64_t kk = k < 1 ? 1 : k;
     uint32_t pth = (uint32_t)path;
     // Automatic choice: FP4 matrix cores (twice the INT8 rate, half the operand bytes)
-    // when every centred residue is an e2m1 value, INT8 for other byte residues.
-    if (pth == QMM_PATH_AUTO) pth = p <= 8 ? QMM_PATH_FP4 : (p <= 256 ? QMM_PATH_INT8 : QMM_PATH_FP64_QADIC);
+    // when every centred residue is an e2m1 value and the product is large enough to
+    // repay FP4's extra conversion launch (measured crossover between 512^3 and 768^3
+    // multiply-adds), INT8 for other byte residues.
+    if (pth == QMM_PATH_AUTO) {
+        const bool fp4 = p <= 8 && (double)m * (double)n * (double)kk >= (double)(1ll << 28);
+        pth = fp4 ? QMM_PATH_FP4 : (p <= 256 ? QMM_PATH_INT8 : QMM_PATH_FP64_QADIC);
+    }
     if (pth > QMM_PATH_FP4) return fail(QMM_EINVAL, "unknown path");
     if (beta == 0) beta = default_beta(pth);
     if (pth != QMM_PATH_INT8 && pth != QMM_PATH_FP4 && ((path_is_fp64(pth) && beta != 53) || (path_is_fp32(pth) && beta != 24)) &&
