@@ -239,11 +239,15 @@ typedef struct qmm_batched qmm_batched;
  * memory it allocates, including the workspace of sum_i (mp_i + np_i) kp_i bytes
  * (kp_i = k_i rounded up to 64, mp_i and np_i = m_i and n_i rounded up to the
  * product's tile).
+ * INT8 products of p <= 8 whose k is one exact FP32 block (k floor(p/2)^2 + p - 1 <=
+ * 2^24) use FP4 codes instead (plan path QMM_PATH_FP4): half the workspace bytes
+ * and the FP4 form of the MFMA in the same tile kernels.
  * flags: QMM_BATCH_FORCE_FP64 puts every product on the FP64 Q-adic tile path (the
  * paper's method, unblocked plans); QMM_BATCH_SHAPE_* fixes the INT8 output tile
  * instead of letting the autotuner pick it per product.  Products whose k would
  * need blocked int32 accumulation are refused (QMM_EUNSUPPORTED). */
 #define QMM_BATCH_FORCE_FP64   1u
+#define QMM_BATCH_INT8_ONLY    2u  /* keep products of p <= 8 on INT8 instead of FP4 codes */
 #define QMM_BATCH_SHAPE_64x64   0x100u
 #define QMM_BATCH_SHAPE_32x128  0x200u
 #define QMM_BATCH_SHAPE_128x32  0x300u

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "qmm_device.h"
@@ -39,6 +40,9 @@ namespace {
 
 typedef int ix4 __attribute__((ext_vector_type(4)));
 typedef int ix16 __attribute__((ext_vector_type(16)));
+typedef int ix8 __attribute__((ext_vector_type(8)));
+typedef float fx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int ux2 __attribute__((ext_vector_type(2)));
 typedef double dx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int uint4v __attribute__((ext_vector_type(4)));
 
@@ -71,10 +75,13 @@ struct Desc {
     // FP64 Q-adic
     uint32_t t, d, offset_regime;
     double start, invp;
-    // INT8: centred, zero-padded workspace copies (rows of kp bytes; mp and np rows)
+    // INT8 / FP4: centred, zero-padded workspace copies (rows of kpb bytes; mp and np
+    // rows); kp = k rounded up to 64.  FP4 products hold e2m1 codes, two per byte
+    // (kpb = kp / 2), INT8 products centred bytes (kpb = kp).
     int8_t *Ac;
     int8_t *Bt;
-    int32_t kp, mp, np;
+    int32_t kp, mp, np, kpb;
+    uint32_t fp4, lut_lo, lut_hi;
 };
 
 // One operand block for the pack kernel: kind 0 = rows r0 .. r0+63 of A at k bytes
@@ -130,6 +137,21 @@ __device__ __forceinline__ uint4 load16(const uint8_t *src, int valid, const uin
 // to mp and np) are never written: they only reach outputs past m or n, which the
 // product does not store, so any bytes there will do.
 constexpr int PACK_K = 256;
+
+// FP4 codes: residue x < p <= 8 -> e2m1 code of centred(x), four at a time by one
+// byte permute over the codes of 0..7 held in (lut_hi:lut_lo); two words of codes
+// (one code per byte) pack into one word of eight nibbles, the lower k low.
+__device__ __forceinline__ uint32_t fp4_codes(uint32_t x4, uint32_t lut_lo, uint32_t lut_hi) {
+    return __builtin_amdgcn_perm(lut_hi, lut_lo, x4);
+}
+__device__ __forceinline__ uint32_t fp4_pack(uint32_t c_lo, uint32_t c_hi) {
+    const uint32_t a = c_lo | (c_lo >> 4), b = c_hi | (c_hi >> 4);
+    return __builtin_amdgcn_perm(b, a, 0x06040200u);
+}
+__device__ __forceinline__ uint32_t encode4(const Desc &D, uint32_t w) {
+    return D.fp4 ? fp4_codes(w, D.lut_lo, D.lut_hi) : centre4(w, D.add_h, D.neg_p);
+}
+
 __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict__ descs,
                                                           const PackJob *__restrict__ jobs) {
     __shared__ uint32_t tile[PACK_K][17];  // k rows x 64 column bytes, padded by one word
@@ -150,10 +172,12 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int32_t kk = J.c0 + 16 * ((t & 3) + 4 * i);
-            if (kk < D.kp)
-                *(QMM_GLOBAL uint4v *)(D.Ac + (int64_t)row * D.kp + kk) =
-                    uint4v{centre4(v[i].x, D.add_h, D.neg_p), centre4(v[i].y, D.add_h, D.neg_p),
-                           centre4(v[i].z, D.add_h, D.neg_p), centre4(v[i].w, D.add_h, D.neg_p)};
+            if (kk >= D.kp) continue;
+            const uint4v e{encode4(D, v[i].x), encode4(D, v[i].y), encode4(D, v[i].z), encode4(D, v[i].w)};
+            if (D.fp4)
+                *(QMM_GLOBAL ux2 *)(D.Ac + (int64_t)row * D.kpb + kk / 2) = ux2{fp4_pack(e.x, e.y), fp4_pack(e.z, e.w)};
+            else
+                *(QMM_GLOBAL uint4v *)(D.Ac + (int64_t)row * D.kpb + kk) = e;
         }
         return;
     }
@@ -170,10 +194,10 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             uint32_t *dst = &tile[(t >> 2) + 64 * i][4 * (t & 3)];
-            dst[0] = centre4(v[i].x, D.add_h, D.neg_p);
-            dst[1] = centre4(v[i].y, D.add_h, D.neg_p);
-            dst[2] = centre4(v[i].z, D.add_h, D.neg_p);
-            dst[3] = centre4(v[i].w, D.add_h, D.neg_p);
+            dst[0] = encode4(D, v[i].x);
+            dst[1] = encode4(D, v[i].y);
+            dst[2] = encode4(D, v[i].z);
+            dst[3] = encode4(D, v[i].w);
         }
     }
     __syncthreads();
@@ -197,8 +221,12 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int32_t orow = J.c0 + 4 * cg + q;
-        if (orow < D.n)
-            *(QMM_GLOBAL uint4v *)(D.Bt + (int64_t)orow * D.kp + kk) = uint4v{out[q][0], out[q][1], out[q][2], out[q][3]};
+        if (orow >= D.n) continue;
+        if (D.fp4)
+            *(QMM_GLOBAL ux2 *)(D.Bt + (int64_t)orow * D.kpb + kk / 2) =
+                ux2{fp4_pack(out[q][0], out[q][1]), fp4_pack(out[q][2], out[q][3])};
+        else
+            *(QMM_GLOBAL uint4v *)(D.Bt + (int64_t)orow * D.kpb + kk) = uint4v{out[q][0], out[q][1], out[q][2], out[q][3]};
     }
 }
 
@@ -213,10 +241,16 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 // segments of a last, 64-byte stage past kp are not loaded.
 __device__ __forceinline__ ix4 gload16(const int8_t *p) { return *(const QMM_GLOBAL ix4 *)p; }
 
+// An accumulator register as an integer: int32 for INT8 tiles, an FP32 exact
+// integer (|x| <= 2^24) for FP4 tiles.
+__device__ __forceinline__ int32_t acc_value(int32_t bits, bool fp4) {
+    return fp4 ? (int32_t)__builtin_bit_cast(float, bits) : bits;
+}
+
 constexpr int KT = 128;            // K stage (bytes)
 constexpr int PT = KT + 16;        // LDS row pitch: 8 lanes reading 8 rows hit distinct banks
 constexpr int KP_ALIGN = 64;       // workspace rows: k rounded up to this
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, bool FP4>
 __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
     constexpr int SEGS = KT / 16;
@@ -226,7 +260,8 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
-    const int kp = D.kp;
+    const int kp = D.kpb;  // bytes per packed row (k values for INT8, half of them for FP4)
+    constexpr bool fp4 = FP4;  // the tile list of an FP4 class holds only FP4 products
     const int stages = (kp + KT - 1) / KT;
 
     // Thread tid stages the 16-byte segment seg = tid % 8 of rows tid / 8 + 32 i: the
@@ -262,6 +297,8 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
         __syncthreads();
         if (st + 1 < stages) fetch(st + 1);
         const uint8_t *sA = lds, *sB = lds + BM * PT;
+        // 32 bytes of each row per MFMA step: 32 k of int8, or 64 k of e2m1 codes into
+        // the FP4 form (FP32 accumulators in the same registers, bit-cast)
         const int ksteps = min(KT, kp - st * KT) / 32;
         for (int ks = 0; ks < ksteps; ++ks) {
             ix4 bf[FN];
@@ -272,8 +309,17 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
             for (int mi = 0; mi < FM; ++mi) {
                 const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
 #pragma unroll
-                for (int ni = 0; ni < FN; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+                for (int ni = 0; ni < FN; ++ni) {
+                    if constexpr (fp4) {
+                        const ix4 b = bf[ni];
+                        const fx16 f = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            ix8{af.x, af.y, af.z, af.w, 0, 0, 0, 0}, ix8{b.x, b.y, b.z, b.w, 0, 0, 0, 0},
+                            __builtin_bit_cast(fx16, acc[mi][ni]), 4, 4, 0, 127, 0, 127);
+                        acc[mi][ni] = __builtin_bit_cast(ix16, f);
+                    } else {
+                        acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+                    }
+                }
             }
         }
         __syncthreads();  // the stage's LDS is read before the next one (or tile) overwrites it
@@ -295,13 +341,13 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
                     cbase[off0 + (uint32_t)(8 * (r >> 2) + (r & 3)) * ldc] =
-                        (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
+                        (uint8_t)mod_i32_magic(acc_value(acc[mi][ni][r], fp4), D.p, D.magic, D.off);
             } else {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const uint32_t rr = (uint32_t)(8 * (r >> 2) + (r & 3));
                     if (rl + rr < (uint32_t)D.m && cl < (uint32_t)D.n)
-                        cbase[off0 + rr * ldc] = (uint8_t)mod_i32_magic(acc[mi][ni][r], D.p, D.magic, D.off);
+                        cbase[off0 + rr * ldc] = (uint8_t)mod_i32_magic(acc_value(acc[mi][ni][r], fp4), D.p, D.magic, D.off);
                 }
             }
         }
@@ -393,14 +439,14 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // One persistent kernel per tile class (so each gets the registers and occupancy
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
-template <uint32_t SHAPE>
-__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 ? 8 : 6)) void batched_int8_kernel(const Desc *__restrict__ descs,
-                                                          const TileRef *__restrict__ tiles, int32_t ntiles) {
+template <uint32_t SHAPE, bool FP4>
+__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 ? 8 : 5))
+void batched_int8_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles, int32_t ntiles) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PT];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
-        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_wgm(SHAPE), 4 / shape_wgm(SHAPE)>(D, tr.tm, tr.tn, lds);
+        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_wgm(SHAPE), 4 / shape_wgm(SHAPE), FP4>(D, tr.tm, tr.tn, lds);
     }
 }
 
@@ -452,7 +498,10 @@ qmm_status hip_fail(hipError_t e, const char *what) {
 using namespace qmm;
 
 // Tile classes: the three INT8 shapes and the FP64 Q-adic tile.
-constexpr int kClasses = SHAPE_COUNT + 1;
+// Tile classes: the four INT8 shapes, the same four for FP4 products, and the FP64
+// Q-adic tile.
+constexpr int kFp4Class = SHAPE_COUNT, kFp64Class = 2 * SHAPE_COUNT;
+constexpr int kClasses = 2 * SHAPE_COUNT + 1;
 constexpr int kXcds = 8;  // accelerator complex dies, one L2 each
 
 struct qmm_batched {
@@ -508,15 +557,24 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
             return fail(QMM_EINVAL, "problem " + std::to_string(i) + ": bad pointer or leading dimension");
         qmm_plan pl;
         qmm_status st;
-        if (flags & QMM_BATCH_FORCE_FP64)
+        if (flags & QMM_BATCH_FORCE_FP64) {
             st = qmm_choose_Qd(P.p, P.m, P.n, P.k, 53, QMM_PATH_FP64_QADIC, QMM_PLAN_UNBLOCKED, &pl);
-        else
-            st = qmm_choose_Qd(P.p, P.m, P.n, P.k, 0, QMM_PATH_INT8, 0, &pl);
+        } else {
+            // FP4 codes when every centred residue is an e2m1 value (p <= 8) and the
+            // whole k is one exact FP32 block; INT8 otherwise
+            st = QMM_EINVAL;
+            if (!(flags & QMM_BATCH_INT8_ONLY) && P.p <= 8) {
+                st = qmm_choose_Qd(P.p, P.m, P.n, P.k, 0, QMM_PATH_FP4, 0, &pl);
+                if (st == QMM_OK && pl.k_block < P.k) st = QMM_EBOUND;
+            }
+            if (st != QMM_OK) st = qmm_choose_Qd(P.p, P.m, P.n, P.k, 0, QMM_PATH_INT8, 0, &pl);
+        }
         if (st != QMM_OK) return st;
+        const bool lowp = pl.path == QMM_PATH_INT8 || pl.path == QMM_PATH_FP4;
         if (pl.path == QMM_PATH_INT8 && pl.k_block < P.k)
             return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": k needs blocked int32 accumulation, "
                                           "which the batched kernel does not do");
-        if (pl.path == QMM_PATH_INT8 && P.m > 0 && P.n > 0 && (P.m - 1) * P.ldc + P.n > (int64_t)UINT32_MAX)
+        if (lowp && P.m > 0 && P.n > 0 && (P.m - 1) * P.ldc + P.n > (int64_t)UINT32_MAX)
             return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": C spans more than 2^32 bytes, "
                                           "past the batched kernel's 32-bit output offsets");
         Desc &D = descs[(size_t)i];
@@ -536,10 +594,12 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         D.off = P.p * ((1u << 31) / P.p);
         D.invp = 1.0 / (double)P.p;
         int bm = 64, bn = 64;
-        if (pl.path == QMM_PATH_INT8) {
+        if (lowp) {
             const uint32_t h = (P.p - 1) / 2;
             D.add_h = (127u - h) * 0x01010101u;
             D.neg_p = (256u - P.p) & 0xffu;
+            D.fp4 = pl.path == QMM_PATH_FP4;
+            if (D.fp4) fp4_lut(P.p, D.lut_lo, D.lut_hi);
             const uint32_t forced = (flags & QMM_BATCH_SHAPE_MASK) >> 8;  // 1 + shape, 0 = autotuned
             D.shape = forced ? forced - 1 : tune_shape(P.m, P.n, P.k);
             pl.tile = D.shape;
@@ -553,24 +613,26 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         }
         b->plans[(size_t)i] = pl;
         if (P.m == 0 || P.n == 0) continue;
-        if (pl.path == QMM_PATH_INT8) {
-            // workspace: Ac (mp x kp) then Bt (np x kp), each 256-byte aligned
+        if (lowp) {
+            // workspace: Ac (mp x kpb) then Bt (np x kpb), each 256-byte aligned
             D.kp = (int32_t)(ceil_div(P.k, KP_ALIGN) * KP_ALIGN);
+            D.kpb = D.fp4 ? D.kp / 2 : D.kp;
             D.mp = (int32_t)(ceil_div(P.m, bm) * bm);
             D.np = (int32_t)(ceil_div(P.n, bn) * bn);
             a_off[(size_t)i] = ws;
-            ws += (size_t)ceil_div((int64_t)D.mp * D.kp, 256) * 256;
+            ws += (size_t)ceil_div((int64_t)D.mp * D.kpb, 256) * 256;
             b_off[(size_t)i] = ws;
-            ws += (size_t)ceil_div((int64_t)D.np * D.kp, 256) * 256;
+            ws += (size_t)ceil_div((int64_t)D.np * D.kpb, 256) * 256;
             for (int32_t r0 = 0; r0 < D.m; r0 += 64)
                 for (int32_t c0 = 0; c0 < D.kp; c0 += PACK_K) jobs.push_back(PackJob{(int32_t)i, 0, r0, c0});
             for (int32_t r0 = 0; r0 < D.kp; r0 += PACK_K)
                 for (int32_t c0 = 0; c0 < D.n; c0 += 64) jobs.push_back(PackJob{(int32_t)i, 1, r0, c0});
         }
         const int32_t tmax = (int32_t)ceil_div(P.m, bm), nmax = (int32_t)ceil_div(P.n, bn);
-        const double cost = pl.path == QMM_PATH_INT8 ? tile_cost(D.shape, bm, bn, P.k)
-                                                     : (double)ceil_div(words_for(P.k < 1 ? 1 : P.k, pl.d), KW) * 4.0;
-        const int cls = pl.path == QMM_PATH_INT8 ? (int)D.shape : SHAPE_COUNT;
+        // cost in K-stage units: an FP4 tile streams half the bytes of an INT8 one
+        const double cost = lowp ? tile_cost(D.shape, bm, bn, D.fp4 ? ceil_div(P.k, 2) : P.k)
+                                 : (double)ceil_div(words_for(P.k < 1 ? 1 : P.k, pl.d), KW) * 4.0;
+        const int cls = lowp ? (int)D.shape + (D.fp4 ? kFp4Class : 0) : kFp64Class;
         for (int32_t tm = 0; tm < tmax; ++tm)
             for (int32_t tn = 0; tn < nmax; ++tn) tiles[cls].push_back({cost, TileRef{(int32_t)i, tm, tn, 0}});
     }
@@ -579,10 +641,12 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return hip_fail(e, "attribute");
     // persistent grid of each class: as many workgroups as fit the CUs at once
-    const void *kfun[kClasses] = {(const void *)batched_int8_kernel<SHAPE_64x64>,
-                                  (const void *)batched_int8_kernel<SHAPE_32x128>,
-                                  (const void *)batched_int8_kernel<SHAPE_128x32>,
-                                  (const void *)batched_int8_kernel<SHAPE_128x128>, (const void *)batched_fp64_kernel};
+    const void *kfun[kClasses] = {
+        (const void *)batched_int8_kernel<SHAPE_64x64, false>,  (const void *)batched_int8_kernel<SHAPE_32x128, false>,
+        (const void *)batched_int8_kernel<SHAPE_128x32, false>, (const void *)batched_int8_kernel<SHAPE_128x128, false>,
+        (const void *)batched_int8_kernel<SHAPE_64x64, true>,   (const void *)batched_int8_kernel<SHAPE_32x128, true>,
+        (const void *)batched_int8_kernel<SHAPE_128x32, true>,  (const void *)batched_int8_kernel<SHAPE_128x128, true>,
+        (const void *)batched_fp64_kernel};
     int grid[kClasses];
     for (int c = 0; c < kClasses; ++c) {
         int per_cu = 1;
@@ -621,7 +685,7 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         if ((e = hipMalloc(&b->d_ws, ws)) != hipSuccess) return hip_fail(e, "hipMalloc (workspace)");
         for (int64_t i = 0; i < count; ++i) {
             Desc &D = descs[(size_t)i];
-            if (D.path != QMM_PATH_INT8 || D.m == 0 || D.n == 0) continue;
+            if ((D.path != QMM_PATH_INT8 && D.path != QMM_PATH_FP4) || D.m == 0 || D.n == 0) continue;
             D.Ac = b->d_ws + a_off[(size_t)i];
             D.Bt = b->d_ws + b_off[(size_t)i];
         }
@@ -662,10 +726,14 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         const TileRef *tt = b->d_tiles + b->class_first[c];
         const int32_t nt = b->class_count[c];
         switch (c) {
-        case SHAPE_64x64: batched_int8_kernel<SHAPE_64x64><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case SHAPE_32x128: batched_int8_kernel<SHAPE_32x128><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case SHAPE_128x32: batched_int8_kernel<SHAPE_128x32><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case SHAPE_128x128: batched_int8_kernel<SHAPE_128x128><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 0: batched_int8_kernel<SHAPE_64x64, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 1: batched_int8_kernel<SHAPE_32x128, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 2: batched_int8_kernel<SHAPE_128x32, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 3: batched_int8_kernel<SHAPE_128x128, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 4: batched_int8_kernel<SHAPE_64x64, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 5: batched_int8_kernel<SHAPE_32x128, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 6: batched_int8_kernel<SHAPE_128x32, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 7: batched_int8_kernel<SHAPE_128x128, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
         default: batched_fp64_kernel<<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
         }
         if (le == hipSuccess) le = hipGetLastError();
@@ -744,7 +812,8 @@ extern "C" qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs
     if (!out) return fail(QMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 0 || (count > 0 && !probs)) return fail(QMM_EINVAL, "bad problem array");
-    if (flags & ~(QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK | QMM_BATCH_MEASURE)) return fail(QMM_EINVAL, "unknown flags");
+    if (flags & ~(QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK | QMM_BATCH_MEASURE | QMM_BATCH_INT8_ONLY))
+        return fail(QMM_EINVAL, "unknown flags");
     if (((flags & QMM_BATCH_SHAPE_MASK) >> 8) > SHAPE_COUNT) return fail(QMM_EINVAL, "unknown tile shape flag");
     if ((flags & QMM_BATCH_MEASURE) && (flags & (QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK)))
         return fail(QMM_EINVAL, "QMM_BATCH_MEASURE chooses the INT8 tile shapes itself");

@@ -461,6 +461,14 @@ qmm_status check_launch(const char *what) {
     return QMM_OK;
 }
 
+void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
+    const uint32_t h = (p - 1) / 2;
+    add_h = (127u - h) * 0x01010101u;
+    neg_p = (256u - p) & 0xffu;
+}
+
+}  // namespace
+
 // Codes of the residues 0..7 (centred, then e2m1: magnitudes 0, 1, 2, 3, 4 are the
 // codes 0, 2, 4, 5, 6, sign bit 8), bytes 0..3 in lo and 4..7 in hi; residues >= p
 // (not valid input) get code 0.
@@ -475,14 +483,6 @@ void fp4_lut(uint32_t p, uint32_t &lo, uint32_t &hi) {
     lo = (uint32_t)lut;
     hi = (uint32_t)(lut >> 32);
 }
-
-void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
-    const uint32_t h = (p - 1) / 2;
-    add_h = (127u - h) * 0x01010101u;
-    neg_p = (256u - p) & 0xffu;
-}
-
-}  // namespace
 
 // k rounded up to the stage alignment; strides that are multiples of 2 KiB get one
 // more 128-byte line (rows of Bt at such strides crowd fewer HBM channels: the

@@ -82,6 +82,7 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             uint8_t *C, int64_t ldc, void *stream);
 int64_t int8_bt_ld(int64_t k);
 int64_t fp4_ld(int64_t k);
+void fp4_lut(uint32_t p, uint32_t &lo, uint32_t &hi);  // e2m1 codes of the residues 0..7, as bytes
 qmm_status launch_pack_fp4_rows(const qmm_plan &pl, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
                                 uint8_t *A4, int64_t lda4, void *stream);
 qmm_status launch_pack_fp4_cols(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,

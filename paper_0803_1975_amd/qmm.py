@@ -25,6 +25,7 @@ REGIME_NAMES = {0: "exact", 1: "offset", 2: "paper", 3: "int"}
 # flags
 BOUND_PROVEN, BOUND_PAPER, PLAN_UNBLOCKED, BOUND_G4, BOUND_EQ4 = 0, 1, 2, 4, 8
 BATCH_FORCE_FP64 = 1
+BATCH_INT8_ONLY = 2
 BATCH_SHAPE_64x64, BATCH_SHAPE_32x128, BATCH_SHAPE_128x32, BATCH_SHAPE_128x128 = 0x100, 0x200, 0x300, 0x400
 BATCH_MEASURE = 0x1000
 N_BATCH_COSTS = 8  # (fixed, per_stage) for each of the four INT8 tile shapes

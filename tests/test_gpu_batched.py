@@ -49,7 +49,8 @@ EDGE_SHAPES = [(7, 1, 1, 1), (3, 16, 16, 16), (101, 17, 33, 5), (2, 513, 31, 70)
 
 
 @pytest.mark.parametrize("flags", [0, qmm.BATCH_SHAPE_64x64, qmm.BATCH_SHAPE_32x128, qmm.BATCH_SHAPE_128x32,
-                                   qmm.BATCH_SHAPE_128x128, qmm.BATCH_FORCE_FP64])
+                                   qmm.BATCH_SHAPE_128x128, qmm.BATCH_FORCE_FP64, qmm.BATCH_INT8_ONLY,
+                                   qmm.BATCH_INT8_ONLY | qmm.BATCH_SHAPE_128x128])
 def test_batched_edge_shapes(torch, flags):
     note("edge", flags)
     host, dev = make_problems(torch, EDGE_SHAPES, 10 + flags)
@@ -61,7 +62,13 @@ def test_batched_edge_shapes(torch, flags):
         for i, (p, m, n, k) in enumerate(EDGE_SHAPES):
             pl = batch.plan(i)
             assert pl.p == p
-            assert pl.path == (qmm.PATH_FP64_QADIC if flags & qmm.BATCH_FORCE_FP64 else qmm.PATH_INT8)
+            if flags & qmm.BATCH_FORCE_FP64:
+                want = qmm.PATH_FP64_QADIC
+            elif p <= 8 and not flags & qmm.BATCH_INT8_ONLY:
+                want = qmm.PATH_FP4                   # every edge k here is one exact FP32 block
+            else:
+                want = qmm.PATH_INT8
+            assert pl.path == want, (i, p, flags)
     finally:
         batch.destroy()
 
@@ -91,7 +98,7 @@ def test_batched_workload_2000_products(torch):
     for (p, m, n, k), (A, B) in zip(shapes, inputs):
         dev.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
                     torch.full((m, n), 255, dtype=torch.uint8, device="cuda"), p))
-    for flags in (0, qmm.BATCH_FORCE_FP64):
+    for flags in (0, qmm.BATCH_INT8_ONLY, qmm.BATCH_FORCE_FP64):
         note("workload", flags)
         batch = qmm.batched_create(dev, flags)
         try:
