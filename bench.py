@@ -109,10 +109,8 @@ class Stepper:
                                                      q._ld(Bt), vp(C.data_ptr()), q._ld(C), st))]
         elif pl.path == q.PATH_FP4:
             A4, Bt4 = self.A4, self.Bt4
-            self.conv_calls = [(L.qmm_pack_fp4_rows, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(A4.data_ptr()),
-                                                      q._ld(A4), st)),
-                               (L.qmm_pack_fp4_cols, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(Bt4.data_ptr()),
-                                                      q._ld(Bt4), st))]
+            self.conv_calls = [(L.qmm_pack_fp4, (P, m, n, k, vp(A.data_ptr()), q._ld(A), vp(B.data_ptr()), q._ld(B),
+                                                 vp(A4.data_ptr()), q._ld(A4), vp(Bt4.data_ptr()), q._ld(Bt4), st))]
             self.prod_calls = [(L.qmm_gemm_fp4, (P, m, n, k, vp(A4.data_ptr()), q._ld(A4), vp(Bt4.data_ptr()),
                                                  q._ld(Bt4), vp(C.data_ptr()), q._ld(C), st))]
         elif pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):

@@ -205,6 +205,12 @@ qmm_status qmm_pack_fp4_rows(const qmm_plan *plan, int64_t m, int64_t k, const u
 qmm_status qmm_pack_fp4_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B,
                              int64_t ldb, uint8_t *Bt4, int64_t ldbt4, void *stream);
 
+/* Both FP4 conversions in one launch: A4 from A as qmm_pack_fp4_rows and Bt4 from
+ * B as qmm_pack_fp4_cols (what qmm_gemm_mod_p runs on this path). */
+qmm_status qmm_pack_fp4(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                        int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *A4, int64_t lda4,
+                        uint8_t *Bt4, int64_t ldbt4, void *stream);
+
 /* FP4 path, product step: C = (A4 x Bt4^T) mod p (values decoded from the codes),
  * FP32 accumulation, k cut into plan->k_block blocks reduced mod p.  plan->tile
  * picks the kernel tile as for INT8. */

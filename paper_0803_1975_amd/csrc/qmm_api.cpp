@@ -186,8 +186,7 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
     }
     if (pl.path == QMM_PATH_FP4) {
         uint8_t *A4 = w, *Bt4 = w + L.off_b;
-        if ((st = launch_pack_fp4_rows(pl, m, k, A, lda, A4, L.ld_a, stream)) != QMM_OK) return st;
-        if ((st = launch_pack_fp4_cols(pl, k, n, B, ldb, Bt4, L.ld_b, stream)) != QMM_OK) return st;
+        if ((st = launch_pack_fp4_both(pl, m, n, k, A, lda, B, ldb, A4, L.ld_a, Bt4, L.ld_b, stream)) != QMM_OK) return st;
         return launch_gemm_fp4(pl, m, n, k, A4, L.ld_a, Bt4, L.ld_b, C, ldc, stream);
     }
     return fail(QMM_EINVAL, "unknown path");
@@ -259,6 +258,19 @@ extern "C" qmm_status qmm_pack_fp4_cols(const qmm_plan *plan, int64_t k, int64_t
     if (bad_fp4_operand(n, k < 1 ? 1 : k, Bt4, ldbt4))
         return fail(QMM_EINVAL, "Bt4: needs a 16-byte aligned pointer and ldbt4 a multiple of 128, >= k/2");
     return launch_pack_fp4_cols(*plan, k, n, B, ldb, Bt4, ldbt4, stream);
+}
+
+extern "C" qmm_status qmm_pack_fp4(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                                   int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *A4, int64_t lda4, uint8_t *Bt4,
+                                   int64_t ldbt4, void *stream) {
+    if (!plan || plan->path != QMM_PATH_FP4) return fail(QMM_EINVAL, "an FP4 plan is required");
+    if (plan->p < 2 || plan->p > 8) return fail(QMM_EINVAL, "FP4 needs 2 <= p <= 8");
+    if (bad_matrix(m, k, A, lda)) return fail(QMM_EINVAL, "A: bad size, pointer or lda");
+    if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad size, pointer or ldb");
+    if (bad_fp4_operand(m, k < 1 ? 1 : k, A4, lda4) || bad_fp4_operand(n, k < 1 ? 1 : k, Bt4, ldbt4))
+        return fail(QMM_EINVAL, "A4, Bt4: need 16-byte aligned pointers and leading dimensions that are "
+                                "multiples of 128, >= k/2");
+    return launch_pack_fp4_both(*plan, m, n, k, A, lda, B, ldb, A4, lda4, Bt4, ldbt4, stream);
 }
 
 extern "C" qmm_status qmm_gemm_fp4(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const uint8_t *A4,

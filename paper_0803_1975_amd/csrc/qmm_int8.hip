@@ -131,44 +131,48 @@ __device__ __forceinline__ uint32_t fp4_pack(uint32_t c_lo, uint32_t c_hi) {
     return __builtin_amdgcn_perm(b, a, 0x06040200u);
 }
 
-// A4 rows: thread (x, row) turns residues 32 s .. 32 s + 31 of the row (zero past k)
-// into 16 bytes of codes at byte 16 s of the packed row.
+// A4 rows: residues 32 sg .. 32 sg + 31 of row r (zero past k) become the 16 bytes of
+// codes at byte 16 sg of the packed row.
+__device__ __forceinline__ void fp4_row_segment(int64_t r, int64_t sg, int64_t k, const uint8_t *__restrict__ A,
+                                                int64_t lda, uint8_t *__restrict__ A4, int64_t lda4, uint32_t lut_lo,
+                                                uint32_t lut_hi, int a_vec) {
+    const uint8_t *row = A + r * lda;
+    const int64_t k0 = 32 * sg;
+    uint32_t w[8];
+    if (a_vec && k0 + 32 <= k) {
+        const uint4 v0 = *(const uint4 *)(row + k0), v1 = *(const uint4 *)(row + k0 + 16);
+        w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
+        w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = 0;
+        for (int b = 0; b < 32; ++b)
+            if (k0 + b < k) w[b >> 2] |= (uint32_t)row[k0 + b] << (8 * (b & 3));
+    }
+    uint32_t o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = fp4_pack(fp4_codes(w[2 * i], lut_lo, lut_hi), fp4_codes(w[2 * i + 1], lut_lo, lut_hi));
+    *(ux4 *)(A4 + r * lda4 + 16 * sg) = ux4{o[0], o[1], o[2], o[3]};
+}
+
 __global__ __launch_bounds__(256) void pack_fp4_rows_kernel(int64_t m, int64_t k, const uint8_t *__restrict__ A,
                                                             int64_t lda, uint8_t *__restrict__ A4, int64_t lda4,
                                                             uint32_t lut_lo, uint32_t lut_hi, int a_vec) {
     const int64_t segs = lda4 / 16;
-    for (int64_t r = blockIdx.y; r < m; r += gridDim.y) {
-        const uint8_t *row = A + r * lda;
-        for (int64_t sg = (int64_t)blockIdx.x * 256 + threadIdx.x; sg < segs; sg += (int64_t)gridDim.x * 256) {
-            const int64_t k0 = 32 * sg;
-            uint32_t w[8];
-            if (a_vec && k0 + 32 <= k) {
-                const uint4 v0 = *(const uint4 *)(row + k0), v1 = *(const uint4 *)(row + k0 + 16);
-                w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
-                w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
-            } else {
-#pragma unroll
-                for (int i = 0; i < 8; ++i) w[i] = 0;
-                for (int b = 0; b < 32; ++b)
-                    if (k0 + b < k) w[b >> 2] |= (uint32_t)row[k0 + b] << (8 * (b & 3));
-            }
-            uint32_t o[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                o[i] = fp4_pack(fp4_codes(w[2 * i], lut_lo, lut_hi), fp4_codes(w[2 * i + 1], lut_lo, lut_hi));
-            *(ux4 *)(A4 + r * lda4 + 16 * sg) = ux4{o[0], o[1], o[2], o[3]};
-        }
-    }
+    for (int64_t r = blockIdx.y; r < m; r += gridDim.y)
+        for (int64_t sg = (int64_t)blockIdx.x * 256 + threadIdx.x; sg < segs; sg += (int64_t)gridDim.x * 256)
+            fp4_row_segment(r, sg, k, A, lda, A4, lda4, lut_lo, lut_hi, a_vec);
 }
 
-// Bt4[n0 + c][(k0 + r) / 2] = code(B[k0 + r][n0 + c]) for a 128 (k) x 128 (n) tile:
-// the loads, LDS tile and register transposes of centre_transpose_kernel, with the
-// codes looked up on the way into LDS and each column's 16 k packed into 8 bytes.
-__global__ __launch_bounds__(256) void pack_fp4_cols_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
-                                                            int64_t ldb, uint8_t *__restrict__ Bt4, int64_t ldbt4,
-                                                            uint32_t lut_lo, uint32_t lut_hi, int b_vec) {
-    __shared__ uint32_t tile[CT][CT / 4 + 1];
-    const int64_t k0 = (int64_t)blockIdx.y * CT, n0 = (int64_t)blockIdx.x * CT;
+// Bt4[n0 + c][(k0 + r) / 2] = code(B[k0 + r][n0 + c]) for the 128 (k) x 128 (n) tile
+// (tx, ty): the loads, LDS tile and register transposes of centre_transpose_kernel,
+// with the codes looked up on the way into LDS and each column's 16 k packed into 8
+// bytes.  Every thread of the workgroup calls it (it holds a barrier).
+__device__ __forceinline__ void fp4_cols_tile(int64_t tx, int64_t ty, int64_t k, int64_t n,
+                                              const uint8_t *__restrict__ B, int64_t ldb, uint8_t *__restrict__ Bt4,
+                                              int64_t ldbt4, uint32_t lut_lo, uint32_t lut_hi, int b_vec,
+                                              uint32_t (*tile)[CT / 4 + 1]) {
+    const int64_t k0 = ty * CT, n0 = tx * CT;
     const int t = threadIdx.x;
     {
         const int seg = t & 7, r0 = t >> 3;
@@ -224,6 +228,47 @@ __global__ __launch_bounds__(256) void pack_fp4_cols_kernel(int64_t k, int64_t n
         if (nn < n)
             *(ux2 *)(Bt4 + nn * ldbt4 + kb) = ux2{fp4_pack(out[q][0], out[q][1]), fp4_pack(out[q][2], out[q][3])};
     }
+}
+
+__global__ __launch_bounds__(256) void pack_fp4_cols_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
+                                                            int64_t ldb, uint8_t *__restrict__ Bt4, int64_t ldbt4,
+                                                            uint32_t lut_lo, uint32_t lut_hi, int b_vec) {
+    __shared__ uint32_t tile[CT][CT / 4 + 1];
+    fp4_cols_tile(blockIdx.x, blockIdx.y, k, n, B, ldb, Bt4, ldbt4, lut_lo, lut_hi, b_vec, tile);
+}
+
+// Both conversions of an FP4 product in one launch (two kernels this size each
+// spend a good part of their time filling and draining the GPU): workgroups
+// 0 .. a_blocks-1 pack A, 256 row segments each; the rest transpose B tiles.
+struct Fp4PackArgs {
+    int64_t m, n, k;
+    const uint8_t *A;
+    int64_t lda;
+    uint8_t *A4;
+    int64_t lda4;
+    const uint8_t *B;
+    int64_t ldb;
+    uint8_t *Bt4;
+    int64_t ldbt4;
+    uint32_t lut_lo, lut_hi;
+    int a_vec, b_vec;
+    int64_t a_blocks, b_tiles_x;
+};
+__global__ __launch_bounds__(256) void pack_fp4_both_kernel(Fp4PackArgs g) {
+    __shared__ uint32_t tile[CT][CT / 4 + 1];
+    const int64_t blk = blockIdx.x;
+    if (blk < g.a_blocks) {
+        const int64_t segs = g.lda4 / 16;
+        const int64_t idx = blk * 256 + threadIdx.x;
+        if (idx < g.m * segs) {
+            const int64_t r = idx / segs;
+            fp4_row_segment(r, idx - r * segs, g.k, g.A, g.lda, g.A4, g.lda4, g.lut_lo, g.lut_hi, g.a_vec);
+        }
+        return;
+    }
+    const int64_t tb = blk - g.a_blocks;
+    fp4_cols_tile(tb % g.b_tiles_x, tb / g.b_tiles_x, g.k, g.n, g.B, g.ldb, g.Bt4, g.ldbt4, g.lut_lo, g.lut_hi,
+                  g.b_vec, tile);
 }
 
 template <int BM, int BN>
@@ -569,6 +614,33 @@ qmm_status launch_pack_fp4_cols(const qmm_plan &pl, int64_t k, int64_t n, const 
     const int b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
     pack_fp4_cols_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt4, ldbt4, lo, hi, b_vec);
     return check_launch("pack_fp4_cols");
+}
+
+qmm_status launch_pack_fp4_both(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
+                                const uint8_t *B, int64_t ldb, uint8_t *A4, int64_t lda4, uint8_t *Bt4, int64_t ldbt4,
+                                void *stream) {
+    if (m == 0 && n == 0) return QMM_OK;
+    Fp4PackArgs g{};
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.A = A;
+    g.lda = lda;
+    g.A4 = A4;
+    g.lda4 = lda4;
+    g.B = B;
+    g.ldb = ldb;
+    g.Bt4 = Bt4;
+    g.ldbt4 = ldbt4;
+    fp4_lut(pl.p, g.lut_lo, g.lut_hi);
+    g.a_vec = ((uintptr_t)A % 16 == 0) && (lda % 16 == 0);
+    g.b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
+    g.a_blocks = ceil_div(m * (lda4 / 16), 256);
+    g.b_tiles_x = ceil_div(n, CT);
+    const int64_t blocks = g.a_blocks + (n > 0 ? g.b_tiles_x * ceil_div(2 * ldbt4, CT) : 0);
+    if (blocks > INT32_MAX) return fail(QMM_EUNSUPPORTED, "FP4 conversion grid too large");
+    pack_fp4_both_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(g);
+    return check_launch("pack_fp4_both");
 }
 
 qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A4, int64_t lda4,

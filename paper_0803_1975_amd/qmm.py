@@ -38,7 +38,7 @@ EXPORTS = [
     "qmm_batched_create", "qmm_gemm_mod_p_batched", "qmm_batched_plan", "qmm_batched_destroy",
     "qmm_last_error", "qmm_version", "qmm_pack_centred_cols", "qmm_gemm_centred",
     "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs", "qmm_count_nonresidues",
-    "qmm_pack_fp4_rows", "qmm_pack_fp4_cols", "qmm_gemm_fp4",
+    "qmm_pack_fp4_rows", "qmm_pack_fp4_cols", "qmm_gemm_fp4", "qmm_pack_fp4",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
             "qmm_pack_fp4_rows": [P, i64, i64, vp, i64, vp, i64, vp],
             "qmm_pack_fp4_cols": [P, i64, i64, vp, i64, vp, i64, vp],
             "qmm_gemm_fp4": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_pack_fp4": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -432,3 +433,19 @@ def gemm_fp4(plan, A4, Bt4, k, C=None, stream=None):
     _check(lib().qmm_gemm_fp4(ctypes.byref(plan), m, n, k, _ptr(A4), _ld(A4), _ptr(Bt4), _ld(Bt4), _ptr(C), _ld(C),
                               _stream(stream)), "qmm_gemm_fp4")
     return C
+
+
+def pack_fp4(plan, A, B, A4=None, Bt4=None, stream=None):
+    """Both FP4 conversions in one launch: (A4, Bt4) as pack_fp4_rows / pack_fp4_cols."""
+    import torch
+    _u8(A, "A")
+    _u8(B, "B")
+    m, k = A.shape
+    n = B.shape[1]
+    if A4 is None:
+        A4 = torch.empty((m, fp4_ld(k)), dtype=torch.uint8, device=A.device)
+    if Bt4 is None:
+        Bt4 = torch.empty((n, fp4_ld(k)), dtype=torch.uint8, device=B.device)
+    _check(lib().qmm_pack_fp4(ctypes.byref(plan), m, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(A4), _ld(A4),
+                              _ptr(Bt4), _ld(Bt4), _stream(stream)), "qmm_pack_fp4")
+    return A4, Bt4

@@ -411,6 +411,8 @@ def test_fp4_stages_match_one_call_and_oracle(torch, p, m, n, k):
     one = qmm.gemm_mod_p(dA, dB, p, plan=plan)
     A4 = qmm.pack_fp4_rows(plan, dA)
     Bt4 = qmm.pack_fp4_cols(plan, dB)
+    A4b, Bt4b = qmm.pack_fp4(plan, dA, dB)          # both conversions in one launch
+    assert torch.equal(A4b, A4) and torch.equal(Bt4b, Bt4)
     for tile in (1, 2, 3):
         plan.tile = tile
         assert torch.equal(qmm.gemm_fp4(plan, A4, Bt4, k), one), tile
