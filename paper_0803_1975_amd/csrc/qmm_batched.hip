@@ -12,15 +12,17 @@
 //   - the launches are recorded in a HIP graph; qmm_gemm_mod_p_batched replays it.
 //
 // Device side, INT8 (two stages in the graph):
-//   pack    every operand byte is read once: A_i is centred into a workspace copy
+//   pack    every operand byte is read once: A_i is centred (or FP4-coded) into a workspace copy
 //           with rows of KP_i = k_i rounded up to 64 bytes, B_i is centred and
 //           transposed (k contiguous) into another, both zero padded to whole
 //           tiles and whole K stages, so the product needs no bounds checks and
 //           only aligned 16-byte loads;
-//   product one persistent kernel per tile shape, parallel graph branches; each
-//           tile runs 128-byte K stages through LDS into i32_32x32x32_i8 MFMAs
-//           (next stage's loads in flight during the MFMAs), then reduces mod p
-//           and stores its bytes.
+//   product one persistent kernel per tile class (tile shape x encoding), one after
+//           another in the graph; each tile runs 128-byte K stages through LDS
+//           into i32_32x32x32_i8 MFMAs (centred bytes) or the FP4 form of the
+//           MFMA (e2m1 codes of p <= 8, 64 k per instruction), with the next
+//           stage's loads in flight during the MFMAs, then reduces mod p and
+//           stores its bytes.
 // Device side, FP64 Q-adic: one persistent kernel whose tiles pack rows of A
 // reversed and columns of B forward straight from the bytes on the way into LDS.
 #include <hip/hip_runtime.h>
@@ -515,8 +517,7 @@ struct qmm_batched {
     int8_t *d_ws = nullptr;   // centred, padded INT8 operands
     size_t ws_bytes = 0;
     int32_t class_first[kClasses] = {}, class_count[kClasses] = {};
-    hipStream_t streams[kClasses] = {};
-    hipEvent_t fork = nullptr, join[kClasses] = {};
+    hipStream_t capture = nullptr;  // the stream the graph was recorded on
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -527,11 +528,7 @@ void release(qmm_batched *b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (int c = 0; c < kClasses; ++c) {
-        if (b->join[c]) (void)hipEventDestroy(b->join[c]);
-        if (b->streams[c]) (void)hipStreamDestroy(b->streams[c]);
-    }
-    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
@@ -702,45 +699,36 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     if (!flat.empty() && (e = hipMemcpy(b->d_tiles, flat.data(), sizeof(TileRef) * flat.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "hipMemcpy");
 
-    // Record the launches in one graph: the classes' persistent kernels are
-    // parallel branches between a fork and a join.  The schedule is static, so
-    // the graph holds only kernel nodes and nothing needs clearing between replays.
-    for (int c = 0; c < kClasses; ++c) {
-        if ((e = hipStreamCreateWithFlags(&b->streams[c], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-        if ((e = hipEventCreateWithFlags(&b->join[c], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-    }
-    if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-    hipStream_t s0 = b->streams[0];
+    // Record the launches in one graph: the pack kernel, then each class's persistent
+    // kernel in turn, each with the whole GPU (measured marginally faster than the
+    // classes as parallel branches, whose later kernels wait for the earlier ones'
+    // persistent workgroups anyway).  The schedule is static, so the graph holds only
+    // kernel nodes and nothing needs clearing between replays.
+    if ((e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    hipStream_t s0 = b->capture;
     if ((e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e, "capture");
     hipError_t le = hipSuccess;
     if (b->njobs > 0) {
         batched_pack_kernel<<<b->njobs, NT, 0, s0>>>(b->d_desc, b->d_jobs);
         le = hipGetLastError();
     }
-    (void)hipEventRecord(b->fork, s0);
     for (int c = 0; c < kClasses; ++c) {
         if (b->class_count[c] == 0) continue;
-        hipStream_t sc = b->streams[c];
-        if (c != 0) (void)hipStreamWaitEvent(sc, b->fork, 0);
         const Desc *dd = b->d_desc;
         const TileRef *tt = b->d_tiles + b->class_first[c];
         const int32_t nt = b->class_count[c];
         switch (c) {
-        case 0: batched_int8_kernel<SHAPE_64x64, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case 1: batched_int8_kernel<SHAPE_32x128, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case 2: batched_int8_kernel<SHAPE_128x32, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case 3: batched_int8_kernel<SHAPE_128x128, false><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case 4: batched_int8_kernel<SHAPE_64x64, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case 5: batched_int8_kernel<SHAPE_32x128, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case 6: batched_int8_kernel<SHAPE_128x32, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        case 7: batched_int8_kernel<SHAPE_128x128, true><<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
-        default: batched_fp64_kernel<<<grid[c], NT, 0, sc>>>(dd, tt, nt); break;
+        case 0: batched_int8_kernel<SHAPE_64x64, false><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        case 1: batched_int8_kernel<SHAPE_32x128, false><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        case 2: batched_int8_kernel<SHAPE_128x32, false><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        case 3: batched_int8_kernel<SHAPE_128x128, false><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        case 4: batched_int8_kernel<SHAPE_64x64, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        case 5: batched_int8_kernel<SHAPE_32x128, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        case 6: batched_int8_kernel<SHAPE_128x32, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        case 7: batched_int8_kernel<SHAPE_128x128, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+        default: batched_fp64_kernel<<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
         }
         if (le == hipSuccess) le = hipGetLastError();
-        if (c != 0) {
-            (void)hipEventRecord(b->join[c], sc);
-            (void)hipStreamWaitEvent(s0, b->join[c], 0);
-        }
     }
     if ((e = hipStreamEndCapture(s0, &b->graph)) != hipSuccess) return hip_fail(e, "end capture");
     if (le != hipSuccess) return hip_fail(le, "batched launch");
