@@ -106,36 +106,50 @@ __device__ __forceinline__ uint32_t centre4(uint32_t w, uint32_t add_h, uint32_t
     return w + flag * neg_p;
 }
 
-// 16 bytes of a byte matrix starting at src, any alignment, zero past `valid`
-// bytes.  When all 16 are valid and the dword-aligned 20-byte window around them
-// lies inside the matrix's data [lo, hi), the bytes come from five dword loads
-// and byte-aligning shifts; otherwise from single byte loads.
-typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
-__device__ __forceinline__ uint4 load16(const uint8_t *src, int valid, const uint8_t *lo, const uint8_t *hi) {
-    if (valid >= 16) {
-        const uintptr_t a = (uintptr_t)src;
-        const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
-        if (base >= lo && base + 20 <= hi) {
-            const u32x4a4 v = *(const QMM_GLOBAL u32x4a4 *)base;
-            const uint32_t w4 = *(const QMM_GLOBAL uint32_t *)(base + 16);
-            const uint32_t sh = (uint32_t)(a & 3);
-            if (sh == 0) return make_uint4(v.x, v.y, v.z, v.w);
-            return make_uint4(__builtin_amdgcn_alignbyte(v.y, v.x, sh), __builtin_amdgcn_alignbyte(v.z, v.y, sh),
-                              __builtin_amdgcn_alignbyte(v.w, v.z, sh), __builtin_amdgcn_alignbyte(w4, v.w, sh));
+typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
+
+// 64 bytes of a byte matrix starting at src (any alignment), bytes at positions
+// >= valid zero.  When the dword-aligned 68-byte window around them lies inside
+// the matrix's data [lo, hi) (it may run into the next row: those bytes are masked)
+// they come from four 16-byte and one 4-byte load and byte-aligning shifts;
+// otherwise from single byte loads.
+__device__ __forceinline__ void load64(const uint8_t *src, int valid, const uint8_t *lo, const uint8_t *hi,
+                                       uint32_t out[16]) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) out[j] = 0;
+    if (valid <= 0) return;
+    const uintptr_t a = (uintptr_t)src;
+    const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
+    if (base >= lo && base + 68 <= hi) {
+        uint32_t w[17];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const u32x4a4 v = *(const QMM_GLOBAL u32x4a4 *)(base + 16 * q);
+            w[4 * q] = v.x; w[4 * q + 1] = v.y; w[4 * q + 2] = v.z; w[4 * q + 3] = v.w;
         }
+        w[16] = *(const QMM_GLOBAL uint32_t *)(base + 64);
+        const uint32_t sh = (uint32_t)(a & 3);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) out[j] = sh ? __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh) : w[j];
+        if (valid < 64) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int left = valid - 4 * j;  // valid bytes in this dword
+                out[j] &= left >= 4 ? 0xffffffffu : (left <= 0 ? 0u : (1u << (8 * left)) - 1u);
+            }
+        }
+    } else {
+        const int nb = valid < 64 ? valid : 64;
+        for (int b = 0; b < nb; ++b) out[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)src)[b] << (8 * (b & 3));
     }
-    uint32_t w[4] = {0, 0, 0, 0};
-    for (int b = 0; b < 16; ++b)
-        if (b < valid) w[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)src)[b] << (8 * (b & 3));
-    return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// Pack one operand block (256 threads, four 16-byte segments each, all loads in
-// flight together).  A job: rows r0 .. r0+63 of A, k bytes c0 .. c0+255, centred,
-// zero past k (up to kp).  B job: k rows r0 .. r0+255, columns c0 .. c0+63 of B go
-// through LDS; thread t then reads 16 k rows of one 4-column word, transposes the
-// 16 x 4 bytes in registers and writes four 16-byte k-runs into rows of Bt (zero
-// past k, up to kp).  Rows of Ac past m and rows of Bt past n (the tile padding up
+// Pack one operand block (256 threads, one 64-byte run each, its loads in flight
+// together).  A job: rows r0 .. r0+63 of A, k bytes c0 .. c0+255, encoded (centred
+// bytes, or FP4 codes two per byte), zero past k (up to kp).  B job: k rows
+// r0 .. r0+255, columns c0 .. c0+63 of B go through LDS encoded; thread t then reads
+// 16 k rows of one 4-column word, transposes the 16 x 4 bytes in registers and
+// writes the four k-runs into rows of Bt (zero past k, up to kp).  Rows of Ac past m and rows of Bt past n (the tile padding up
 // to mp and np) are never written: they only reach outputs past m or n, which the
 // product does not store, so any bytes there will do.
 constexpr int PACK_K = 256;
@@ -161,46 +175,39 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
     const Desc &D = descs[J.desc];
     const int t = threadIdx.x;
     if (J.kind == 0) {
-        const int32_t row = J.r0 + (t >> 2);
-        if (row >= D.m) return;
-        const uint8_t *hi = D.A + (int64_t)(D.m - 1) * D.lda + D.k;
-        uint4 v[4];
+        // thread t: row r0 + t / 4, k bytes c0 + 64 (t % 4) .. + 63
+        const int32_t row = J.r0 + (t >> 2), kk = J.c0 + 64 * (t & 3);
+        if (row >= D.m || kk >= D.kp) return;
+        uint32_t w[16];
+        load64(D.A + (int64_t)row * D.lda + kk, D.k - kk, D.A, D.A + (int64_t)(D.m - 1) * D.lda + D.k, w);
+        if (D.fp4) {
+            uint32_t o[8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int32_t kk = J.c0 + 16 * ((t & 3) + 4 * i);
-            v[i] = kk < D.k ? load16(D.A + (int64_t)row * D.lda + kk, D.k - kk, D.A, hi)
-                                           : make_uint4(0, 0, 0, 0);
-        }
+            for (int i = 0; i < 8; ++i)
+                o[i] = fp4_pack(fp4_codes(w[2 * i], D.lut_lo, D.lut_hi), fp4_codes(w[2 * i + 1], D.lut_lo, D.lut_hi));
+            QMM_GLOBAL uint4v *dst = (QMM_GLOBAL uint4v *)(D.Ac + (int64_t)row * D.kpb + kk / 2);
+            dst[0] = uint4v{o[0], o[1], o[2], o[3]};
+            dst[1] = uint4v{o[4], o[5], o[6], o[7]};
+        } else {
+            QMM_GLOBAL uint4v *dst = (QMM_GLOBAL uint4v *)(D.Ac + (int64_t)row * D.kpb + kk);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int32_t kk = J.c0 + 16 * ((t & 3) + 4 * i);
-            if (kk >= D.kp) continue;
-            const uint4v e{encode4(D, v[i].x), encode4(D, v[i].y), encode4(D, v[i].z), encode4(D, v[i].w)};
-            if (D.fp4)
-                *(QMM_GLOBAL ux2 *)(D.Ac + (int64_t)row * D.kpb + kk / 2) = ux2{fp4_pack(e.x, e.y), fp4_pack(e.z, e.w)};
-            else
-                *(QMM_GLOBAL uint4v *)(D.Ac + (int64_t)row * D.kpb + kk) = e;
+            for (int q = 0; q < 4; ++q)
+                dst[q] = uint4v{centre4(w[4 * q], D.add_h, D.neg_p), centre4(w[4 * q + 1], D.add_h, D.neg_p),
+                                centre4(w[4 * q + 2], D.add_h, D.neg_p), centre4(w[4 * q + 3], D.add_h, D.neg_p)};
         }
         return;
     }
     {
-        const uint8_t *hi = D.B + (int64_t)(D.k - 1) * D.ldb + D.n;
-        const int32_t col = J.c0 + 16 * (t & 3);
-        uint4 v[4];
+        // thread t: k row r0 + t, columns c0 .. c0 + 63, encoded into LDS row t
+        const int32_t kk = J.r0 + t;
+        uint32_t w[16];
+        if (kk < D.k)
+            load64(D.B + (int64_t)kk * D.ldb + J.c0, D.n - J.c0, D.B, D.B + (int64_t)(D.k - 1) * D.ldb + D.n, w);
+        else
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int32_t kk = J.r0 + (t >> 2) + 64 * i;
-            v[i] = (kk < D.k && col < D.n) ? load16(D.B + (int64_t)kk * D.ldb + col, D.n - col, D.B, hi)
-                                           : make_uint4(0, 0, 0, 0);
-        }
+            for (int j = 0; j < 16; ++j) w[j] = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t *dst = &tile[(t >> 2) + 64 * i][4 * (t & 3)];
-            dst[0] = encode4(D, v[i].x);
-            dst[1] = encode4(D, v[i].y);
-            dst[2] = encode4(D, v[i].z);
-            dst[3] = encode4(D, v[i].w);
-        }
+        for (int j = 0; j < 16; ++j) tile[t][j] = encode4(D, w[j]);
     }
     __syncthreads();
     const int cg = t & 15, kg = t >> 4;  // columns 4 cg .. 4 cg + 3, k rows 16 kg .. 16 kg + 15
