@@ -190,7 +190,8 @@ qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int64_t n, int
 qmm_status qmm_pack_centred_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B,
                                  int64_t ldb, int8_t *Bt, int64_t ldbt, void *stream);
 
-/* FP4 path (p <= 8).  Every centred residue of such a p (|x| <= 4) is an exact
+/* FP4 path (p <= 8): the product C = A x B mod p of section 1's problem, on a
+ * number format the paper's hardware did not have.  Every centred residue of such a p (|x| <= 4) is an exact
  * e2m1 value (0, +-1, +-2, +-3, +-4), so the FP4 matrix cores of gfx950 multiply
  * them exactly and the FP32 accumulator stays an exact integer while
  * k_block floor(p/2)^2 + p - 1 <= 2^24; longer k is cut into blocks reduced mod p.
@@ -199,7 +200,12 @@ qmm_status qmm_pack_centred_cols(const qmm_plan *plan, int64_t k, int64_t n, con
  * row stride ld4 bytes, a multiple of 128 with 2 ld4 >= k; codes past k are zero.
  * Both packed operands must be 16-byte aligned.
  * Conversion steps: A4 (m x ld4) from A (m x k residues, row-major) and Bt4
- * (n x ld4) from B (k x n residues) transposed, so both are contiguous along k. */
+ * (n x ld4) from B (k x n residues) transposed, so both are contiguous along k.
+ * All buffers are the caller's; every call is asynchronous on `stream`.
+ * Errors: QMM_EINVAL for a plan that is not an FP4 plan, p outside [2, 8], a bad
+ * size, pointer, alignment or leading dimension; the product step also returns
+ * what qmm_validate_plan returns for the plan (QMM_EBOUND for a k_block past the
+ * exact FP32 range, QMM_EVALUE for p > 8). */
 qmm_status qmm_pack_fp4_rows(const qmm_plan *plan, int64_t m, int64_t k, const uint8_t *A,
                              int64_t lda, uint8_t *A4, int64_t lda4, void *stream);
 qmm_status qmm_pack_fp4_cols(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B,
