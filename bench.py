@@ -157,35 +157,32 @@ class Stepper:
     def time(self, steps, warmup):
         """(ms per step, ms of the conversion stage, ms of the product kernel).
 
-        The step time comes from a loop with events only at its two ends: an event
-        recorded between two kernels adds a gap of its own.  The per-stage times come
-        from a second loop over the same calls with events around each stage."""
+        Every figure comes from a loop of back-to-back launches with events only at its
+        two ends (an event recorded between two kernels adds a gap of its own): the
+        whole step, then the conversion stage alone, then the product kernel alone on
+        the operands the conversion left."""
         torch = self.torch
+
+        def loop(fn):
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            start.record()
+            for _ in range(steps):
+                fn()
+            end.record()
+            torch.cuda.synchronize()
+            return start.elapsed_time(end) / steps
+
         for _ in range(warmup):
             self.convert()
             self.product()
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        start.record()
-        for _ in range(steps):
+
+        def step():
             self.convert()
             self.product()
-        end.record()
-        torch.cuda.synchronize()
-        total_ms = start.elapsed_time(end)
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-        torch.cuda.synchronize()
-        for s in range(steps):
-            ev[s][0].record()
-            self.convert()
-            ev[s][1].record()
-            self.product()
-            ev[s][2].record()
-        torch.cuda.synchronize()
-        conv = [e[0].elapsed_time(e[1]) for e in ev]
-        prod = [e[1].elapsed_time(e[2]) for e in ev]
-        return total_ms / steps, sum(conv) / steps, sum(prod) / steps
+
+        return loop(step), loop(self.convert), loop(self.product)
 
 
 def plan_dict(qmm, pl):
@@ -370,6 +367,10 @@ def run_passes(args, torch, qmm):
     Bt = qmm.pack_centred_cols(int8, dB)
     passes.append(("pack_centred_cols (INT8 centring transpose)", lambda: qmm.pack_centred_cols(int8, dB, Bt),
                    k * n + n * Bt.stride(0)))
+    fp4 = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP4)
+    A4, Bt4 = qmm.pack_fp4(fp4, dA, dB)
+    passes.append(("pack_fp4 (FP4 codes of A and of B transposed, one launch)",
+                   lambda: qmm.pack_fp4(fp4, dA, dB, A4, Bt4), m * k + k * n + (m + n) * A4.stride(0)))
     cnt = torch.empty(1, dtype=torch.int32, device="cuda")
     passes.append(("count_nonresidues (validation)", lambda: qmm.count_nonresidues(p, dA, cnt), m * k))
 

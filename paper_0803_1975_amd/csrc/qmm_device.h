@@ -37,6 +37,15 @@ __device__ __forceinline__ uint32_t mod_u32(uint32_t u, uint32_t p, uint64_t mag
     return u - q * p;
 }
 
+// u mod p for any 32-bit u and 2 <= p < 2^31, with m32 = floor(2^32 / p): then
+// u/p - 1 < u m32 / 2^32 <= u/p, so the high word q is floor(u/p) or one less, the
+// remainder u - q p lies in [0, 2p), and min(r, r - p) (unsigned, r - p wraps when
+// r < p) is the residue.  Five 32-bit operations in place of mod_u32's 64-bit ones.
+__device__ __forceinline__ uint32_t mod_u32_m32(uint32_t u, uint32_t p, uint32_t m32) {
+    const uint32_t r = u - __umulhi(u, m32) * p;
+    return min(r, r - p);
+}
+
 // x mod p for a signed 32-bit x with |x| <= 2^31 - p: off = p floor(2^31 / p) is a
 // multiple of p that makes x + off land in [1, 2^32).
 __device__ __forceinline__ uint32_t mod_i32_magic(int32_t x, uint32_t p, uint64_t magic, uint32_t off) {

@@ -299,8 +299,24 @@ struct Int8Args {
     uint32_t p, add_h, neg_p;
     uint64_t magic;    // floor(2^64 / p) + 1
     uint32_t off;      // p floor(2^31 / p)
+    uint32_t magic32;  // floor(2^32 / p)
     bool a_vec;        // A rows 16-byte aligned: vector loads allowed
+    bool c_vec;        // C and ldc 4-byte aligned: whole tiles are stored as dwords
 };
+
+// 4 x 4 byte transpose across the 4 lanes of a quad: lane j holds bytes
+// M[j][0..3] (byte i in bits 8i..8i+7) and gets M[0..3][j].  Two DPP exchanges:
+// 16-bit halves with lane j ^ 2, then bytes with lane j ^ 1.
+__device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t w, int j) {
+    // quad_perm [2,3,0,1]: lane j reads lane j ^ 2
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
+    // j < 2 keeps [w0 w1 o0 o1], j >= 2 keeps [o2 o3 w2 w3]
+    const uint32_t t = __builtin_amdgcn_perm(o, w, (j & 2) ? 0x03020706u : 0x05040100u);
+    // quad_perm [1,0,3,2]: lane j reads lane j ^ 1
+    const uint32_t u = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0xB1, 0xF, 0xF, false);
+    // even j: [t0 u0 t2 u2], odd j: [u1 t1 u3 t3]
+    return __builtin_amdgcn_perm(u, t, (j & 1) ? 0x03070105u : 0x06020400u);
+}
 
 // BM x BN output tile, WGM x WGN wavefronts, K stage of KT bytes.  Each wavefront
 // owns a (BM/WGM) x (BN/WGN) sub-tile of 32 x 32 MFMA blocks (i32_32x32x32_i8:
@@ -487,6 +503,27 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
         }
     }
 
+    if (g.c_vec && row0 + BM <= g.m && col0 + BN <= g.n) {
+        // Whole tile: registers 4q .. 4q+3 of lane l are rows R .. R+3 of column l % 32
+        // (R = 8q + 4 (l / 32)); packed into a dword and transposed across the lane's
+        // quad, they become 4 consecutive bytes of row R + (l % 4), one dword store.
+        const int j = lane & 3;
+        uint8_t *cbase = g.C + (row0 + wm * WTM + 4 * (lane >> 5) + j) * g.ldc + col0 + wn * WTN + (lane & 31) - j;
+#pragma unroll
+        for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < FN; ++ni)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        w |= mod_u32_m32((uint32_t)(int32_t)acc[mi][ni][4 * q + i] + g.off, g.p, g.magic32) << (8 * i);
+                    w = quad_transpose_bytes(w, j);
+                    *(uint32_t *)(cbase + (int64_t)(mi * 32 + 8 * q) * g.ldc + ni * 32) = w;
+                }
+        return;
+    }
 #pragma unroll
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
@@ -660,6 +697,8 @@ qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, 
     g.p = pl.p;
     g.magic = mod_magic(pl.p);
     g.off = pl.p * ((1u << 31) / pl.p);
+    g.magic32 = (uint32_t)((1ull << 32) / pl.p);
+    g.c_vec = ((uintptr_t)C % 4 == 0) && (ldc % 4 == 0);
     g.a_vec = true;
     hipStream_t s = (hipStream_t)stream;
     const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n);
@@ -695,6 +734,8 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
     centre_consts(pl.p, g.add_h, g.neg_p);
     g.magic = mod_magic(pl.p);
     g.off = pl.p * ((1u << 31) / pl.p);
+    g.magic32 = (uint32_t)((1ull << 32) / pl.p);
+    g.c_vec = ((uintptr_t)C % 4 == 0) && (ldc % 4 == 0);
     g.a_vec = ((uintptr_t)A % 16 == 0) && (lda % 16 == 0);
     hipStream_t s = (hipStream_t)stream;
     const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n);
