@@ -84,6 +84,8 @@ struct Desc {
     int8_t *Bt;
     int32_t kp, mp, np, kpb;
     uint32_t fp4, lut_lo, lut_hi;
+    uint32_t magic32;  // floor(2^32 / p)
+    uint32_t c_vec;    // C and ldc 4-byte aligned: whole tiles are stored as dwords
 };
 
 // One operand block for the pack kernel: kind 0 = rows r0 .. r0+63 of A at k bytes
@@ -334,32 +336,54 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
         __syncthreads();  // the stage's LDS is read before the next one (or tile) overwrites it
     }
     // Epilogue: every C offset of a product fits 32 bits (checked on the host), so a
-    // store is a uniform base plus one 32-bit lane offset; interior tiles skip the
-    // bounds checks.  Register r of a block holds row 8 (r/4) + 4 (l/32) + r % 4.
+    // store is a uniform base plus one 32-bit lane offset.  Register r of a block
+    // holds row 8 (r/4) + 4 (l/32) + r % 4 of column l % 32.
     QMM_GLOBAL uint8_t *cbase = (QMM_GLOBAL uint8_t *)D.C;
     const uint32_t ldc = (uint32_t)D.ldc;
     const bool full = row0 + BM <= D.m && col0 + BN <= D.n;
+    auto residue = [&](int32_t bits) __attribute__((always_inline)) {
+        return mod_u32_m32((uint32_t)acc_value(bits, fp4) + D.off, D.p, D.magic32);
+    };
+    if (full && D.c_vec) {
+        // Interior tile, aligned C: registers 4q .. 4q+3 (rows R .. R+3 of one column)
+        // packed into a dword and transposed across the lane's quad become 4
+        // consecutive bytes of row R + l % 4: one dword store each.
+        const int j = lane & 3;
+        const uint32_t b0 = (uint32_t)(row0 + wm * WTM + 4 * (lane >> 5) + j) * ldc +
+                            (uint32_t)(col0 + wn * WTN + (lane & 31) - j);
 #pragma unroll
-    for (int mi = 0; mi < FM; ++mi)
+        for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < FN; ++ni) {
-            const uint32_t rl = (uint32_t)(row0 + wm * WTM + mi * 32 + 4 * (lane >> 5));
-            const uint32_t cl = (uint32_t)(col0 + wn * WTN + ni * 32 + (lane & 31));
-            const uint32_t off0 = rl * ldc + cl;
-            if (full) {
+            for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    cbase[off0 + (uint32_t)(8 * (r >> 2) + (r & 3)) * ldc] =
-                        (uint8_t)mod_i32_magic(acc_value(acc[mi][ni][r], fp4), D.p, D.magic, D.off);
-            } else {
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t w = 0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const uint32_t rr = (uint32_t)(8 * (r >> 2) + (r & 3));
-                    if (rl + rr < (uint32_t)D.m && cl < (uint32_t)D.n)
-                        cbase[off0 + rr * ldc] = (uint8_t)mod_i32_magic(acc_value(acc[mi][ni][r], fp4), D.p, D.magic, D.off);
+                    for (int i = 0; i < 4; ++i) w |= residue(acc[mi][ni][4 * q + i]) << (8 * i);
+                    w = quad_transpose_bytes(w, j);
+                    *(QMM_GLOBAL uint32_t *)(cbase + b0 + (uint32_t)(mi * 32 + 8 * q) * ldc + ni * 32) = w;
+                }
+    } else {
+#pragma unroll
+        for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < FN; ++ni) {
+                const uint32_t rl = (uint32_t)(row0 + wm * WTM + mi * 32 + 4 * (lane >> 5));
+                const uint32_t cl = (uint32_t)(col0 + wn * WTN + ni * 32 + (lane & 31));
+                const uint32_t off0 = rl * ldc + cl;
+                if (full) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        cbase[off0 + (uint32_t)(8 * (r >> 2) + (r & 3)) * ldc] = (uint8_t)residue(acc[mi][ni][r]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const uint32_t rr = (uint32_t)(8 * (r >> 2) + (r & 3));
+                        if (rl + rr < (uint32_t)D.m && cl < (uint32_t)D.n) cbase[off0 + rr * ldc] = (uint8_t)residue(acc[mi][ni][r]);
+                    }
                 }
             }
-        }
+    }
 }
 
 // One FP64 Q-adic tile of 64 x 64 outputs: rows of A packed reversed and columns
@@ -596,6 +620,8 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         D.path = pl.path;
         D.magic = mod_magic(P.p);
         D.off = P.p * ((1u << 31) / P.p);
+        D.magic32 = (uint32_t)((1ull << 32) / P.p);
+        D.c_vec = ((uintptr_t)P.C % 4 == 0) && (P.ldc % 4 == 0);
         D.invp = 1.0 / (double)P.p;
         int bm = 64, bn = 64;
         if (lowp) {

@@ -304,20 +304,6 @@ struct Int8Args {
     bool c_vec;        // C and ldc 4-byte aligned: whole tiles are stored as dwords
 };
 
-// 4 x 4 byte transpose across the 4 lanes of a quad: lane j holds bytes
-// M[j][0..3] (byte i in bits 8i..8i+7) and gets M[0..3][j].  Two DPP exchanges:
-// 16-bit halves with lane j ^ 2, then bytes with lane j ^ 1.
-__device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t w, int j) {
-    // quad_perm [2,3,0,1]: lane j reads lane j ^ 2
-    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
-    // j < 2 keeps [w0 w1 o0 o1], j >= 2 keeps [o2 o3 w2 w3]
-    const uint32_t t = __builtin_amdgcn_perm(o, w, (j & 2) ? 0x03020706u : 0x05040100u);
-    // quad_perm [1,0,3,2]: lane j reads lane j ^ 1
-    const uint32_t u = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0xB1, 0xF, 0xF, false);
-    // even j: [t0 u0 t2 u2], odd j: [u1 t1 u3 t3]
-    return __builtin_amdgcn_perm(u, t, (j & 1) ? 0x03070105u : 0x06020400u);
-}
-
 // BM x BN output tile, WGM x WGN wavefronts, K stage of KT bytes.  Each wavefront
 // owns a (BM/WGM) x (BN/WGN) sub-tile of 32 x 32 MFMA blocks (i32_32x32x32_i8:
 // lane l holds 16 k-bytes of row l % 32 for k-chunk l / 32, and outputs
