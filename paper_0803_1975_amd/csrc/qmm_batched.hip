@@ -90,7 +90,7 @@ struct Desc {
 
 // One operand block for the pack kernel: kind 0 = rows r0 .. r0+63 of A at k bytes
 // c0 .. c0+255; kind 1 = k rows r0 .. r0+255 of B at columns c0 .. c0+63
-// (transposed into Bt).
+// (transposed into Bt); kind 2 = nothing (pads the list to a multiple of 8).
 struct PackJob {
     int32_t desc;
     int32_t kind;
@@ -173,7 +173,12 @@ __device__ __forceinline__ uint32_t encode4(const Desc &D, uint32_t w) {
 __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict__ descs,
                                                           const PackJob *__restrict__ jobs) {
     __shared__ uint32_t tile[PACK_K][17];  // k rows x 64 column bytes, padded by one word
-    const PackJob J = jobs[blockIdx.x];
+    // Workgroups go to the 8 XCDs round-robin; the job list (padded to a multiple
+    // of 8) is split into 8 contiguous ranges, one per XCD, so neighbouring jobs,
+    // which share the cache lines at their edges, share one L2.
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const PackJob J = jobs[(b & 7) * (nb >> 3) + (b >> 3)];
+    if (J.kind > 1) return;  // padding
     const Desc &D = descs[J.desc];
     const int t = threadIdx.x;
     if (J.kind == 0) {
@@ -708,7 +713,8 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     }
     b->ntiles = (int32_t)flat.size();
 
-    if (jobs.size() > (size_t)INT32_MAX) return fail(QMM_EUNSUPPORTED, "batch too large");
+    if (jobs.size() > (size_t)INT32_MAX - kXcds) return fail(QMM_EUNSUPPORTED, "batch too large");
+    while (jobs.size() % kXcds) jobs.push_back(PackJob{0, 2, 0, 0});  // padding jobs do nothing
     b->njobs = (int32_t)jobs.size();
     b->ws_bytes = ws;
     if (ws > 0) {
