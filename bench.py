@@ -34,11 +34,14 @@ PEAK = {  # MI355X published dense peaks
     "int8_TOPs": 5000.0,
     "fp4_TFLOPs": 10100.0,
 }
+# Sources a product kernel is compiled from: stored traffic counters count only
+# while all of them are unchanged.
+_CSRC = "paper_0803_1975_amd/csrc/"
 KERNEL_SOURCES = {
-    "int8": "paper_0803_1975_amd/csrc/qmm_int8.hip",
-    "fp4": "paper_0803_1975_amd/csrc/qmm_int8.hip",
-    "fp64_qadic": "paper_0803_1975_amd/csrc/qmm_gemm.hip",
-    "fp64_redq": "paper_0803_1975_amd/csrc/qmm_gemm.hip",
+    "int8": (_CSRC + "qmm_int8.hip", _CSRC + "qmm_device.h"),
+    "fp4": (_CSRC + "qmm_int8.hip", _CSRC + "qmm_device.h"),
+    "fp64_qadic": (_CSRC + "qmm_gemm.hip", _CSRC + "qmm_device.h"),
+    "fp64_redq": (_CSRC + "qmm_gemm.hip", _CSRC + "qmm_device.h"),
 }
 
 
@@ -46,9 +49,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_digest(path):
-    with open(os.path.join(ROOT, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_digest(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(kernel_key, workload):
