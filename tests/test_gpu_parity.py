@@ -271,6 +271,31 @@ def test_strided_operands(torch):
         assert int(Cbig[:, :10].max()) == 0 and int(Cbig[:, 170:].max()) == 0
 
 
+@pytest.mark.parametrize("path", (qmm.PATH_INT8, qmm.PATH_FP4))
+@pytest.mark.parametrize("tile", (1, 2, 3))
+@pytest.mark.parametrize("col0", (4, 3))
+def test_output_views_for_every_tile(torch, path, tile, col0):
+    # C is a view into a larger zeroed buffer: at a 4-byte aligned column offset with
+    # ldc a multiple of 4, whole tiles are stored as dwords; at an odd offset they are
+    # stored as bytes.  Either way exactly the view's bytes change.
+    p, m, n, k = 7, 520, 530, 700
+    note("views", qmm.PATH_NAMES[path], "tile", tile, "col0", col0)
+    rng = np.random.default_rng(100 * tile + col0)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    plan = qmm.choose_Qd(p, m, n, k, path=path)
+    plan.tile = tile
+    Cbig = torch.full((m + 3, 600), 0xEE, dtype=torch.uint8, device="cuda")
+    C = Cbig[1:m + 1, col0:col0 + n]
+    qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan, C=C)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(C), ref.modmul(A, B, p))
+    big = host(Cbig)
+    outside = np.ones(big.shape, dtype=bool)
+    outside[1:m + 1, col0:col0 + n] = False
+    assert (big[outside] == 0xEE).all()
+
+
 # --- workload sizes -------------------------------------------------------------------
 def sampled_check(torch, A, B, p, C, nsamp=20000, rows=4, seed=0):
     rng = np.random.default_rng(seed)
