@@ -477,9 +477,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
                             if constexpr (FP4)  // an exact integer below 2^24 in magnitude
-                                acc[mi][ni][r] = (float)mod_i32_magic((int32_t)acc[mi][ni][r], g.p, g.magic, g.off);
+                                acc[mi][ni][r] = (float)mod_u32_m32((uint32_t)(int32_t)acc[mi][ni][r] + g.off, g.p, g.magic32);
                             else
-                                acc[mi][ni][r] = (int)mod_i32_magic(acc[mi][ni][r], g.p, g.magic, g.off);
+                                acc[mi][ni][r] = (int)mod_u32_m32((uint32_t)acc[mi][ni][r] + g.off, g.p, g.magic32);
                         }
             }
         }
