@@ -250,7 +250,7 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 // WGM x WGN, each owning (BM/WGM) x (BN/WGN) outputs in 32 x 32 MFMA blocks
 // (i32_32x32x32_i8: lane l holds 16 k-bytes of row l % 32 for k-chunk l / 32 and
 // outputs D[8 (r/4) + 4 (l/32) + r % 4][l % 32] in register r).  K goes in
-// 128-byte stages through ONE LDS buffer per workgroup (so eight workgroups fit
+// 128-byte stages through ONE LDS buffer per workgroup (so seven workgroups fit
 // a CU): a stage is published from registers, and the loads of the next stage
 // are issued before its MFMAs, so they are in flight during the MFMAs and the
 // barrier.  Loads are aligned 16-byte loads inside the padded workspace; the
@@ -304,14 +304,14 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
         for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
-    fetch(0);  // with kp = 0 nothing is loaded
-    for (int st = 0; st < stages; ++st) {
+    auto publish = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
 #pragma unroll
         for (int i = 0; i < B_LOADS; ++i) *(ix4 *)&lds[BM * PT + slot + i * RSTEP * PT] = rb[i];
         __syncthreads();
-        if (st + 1 < stages) fetch(st + 1);
+    };
+    auto compute = [&](int st) __attribute__((always_inline)) {
         const uint8_t *sA = lds, *sB = lds + BM * PT;
         // 32 bytes of each row per MFMA step: 32 k of int8, or 64 k of e2m1 codes into
         // the FP4 form (FP32 accumulators in the same registers, bit-cast)
@@ -339,6 +339,20 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
             }
         }
         __syncthreads();  // the stage's LDS is read before the next one (or tile) overwrites it
+    };
+    // The last stage is peeled off: it loads nothing, so no load is in flight when
+    // the epilogue's stores go out, and the next tile's first loads need not wait
+    // for those stores (a load that might still be pending would make them wait).
+    // A product with k = 0 (no stages) loads nothing at all.
+    if (stages > 0) {
+        fetch(0);
+        for (int st = 0; st + 1 < stages; ++st) {
+            publish();
+            fetch(st + 1);
+            compute(st);
+        }
+        publish();
+        compute(stages - 1);
     }
     // Epilogue: every C offset of a product fits 32 bits (checked on the host), so a
     // store is a uniform base plus one 32-bit lane offset.  Register r of a block
@@ -478,7 +492,7 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
 template <uint32_t SHAPE, bool FP4>
-__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 ? 8 : 5))
+__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 ? 7 : 5))
 void batched_int8_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles, int32_t ntiles) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PT];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
