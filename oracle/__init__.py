@@ -7,7 +7,9 @@ or tables); the two only meet on the seeded inputs that the tests hand to both.
 
 Contents
   reference  the plain definitions: the modular product (C library + a pure
-             Python brute force), the Q-adic packings, digit extraction, REDQ.
+             Python brute force), the Q-adic packings, digit extraction, REDQ,
+             left and full compression (sections 4, 5) and ReduceAndCompress
+             (procedure (1)).
   bounds     the paper's bounds relating p, k, Q = 2^t, d and the mantissa
              width, and the regime tests under which the floating-point
              accumulation is exact.

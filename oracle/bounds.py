@@ -173,3 +173,40 @@ def fp4_block_ok(p: int, kb: int) -> bool:
     every partial sum an integer of magnitude at most 2^24."""
     return kb * centred_max(p) ** 2 + (p - 1) <= 1 << 24
 
+
+
+# -- left and full compression (sections 4 and 5) ---------------------------
+def left_ok(p: int, k: int, t: int, d: int, beta: int) -> bool:
+    """Left compression (Table 2): the same words as section 3 along m instead of n,
+    so the same bounds, eqs. (3) and (4)."""
+    return redq_ok(p, k, t, d, beta)
+
+
+def full_ok(p: int, k: int, t: int, dq: int, dth: int, beta: int) -> bool:
+    """Full compression (section 4): eq. (3) for every coefficient, Theta = Q^(d_q+1)
+    (eq. (6) with equality) and eq. (7), Q^((d_q+1)(d_theta+1)) < 2^beta, so every
+    product word and every partial sum is an integer below 2^beta."""
+    return (dq >= 0 and dth >= 0 and eq3_lower_ok(p, k, t)
+            and t * (dq + 1) * (dth + 1) < beta)
+
+
+def full_word_max(p: int, k: int, t: int, dq: int, dth: int) -> int:
+    """Largest product word: every coefficient of Q^i Theta^j at its largest, k (p-1)^2."""
+    D = (dq + 1) * (dth + 1)
+    return sum(k * (p - 1) ** 2 << (t * q) for q in range(D))
+
+
+def table2_word_products(algorithm: str, m: int, n: int, k: int, d: int, d2: int = 0) -> int:
+    """Multiply-adds of packed words of each algorithm of Table 2 with classical
+    matrix multiplication (omega = 3), for degree d (and d_theta = d2 for 'full'):
+      'qadic' procedure (2): m n ceil(k/(d+1));  'right' procedure (5): m ceil(n/(d+1)) k;
+      'left': ceil(m/(d+1)) n k;  'full' (section 4): ceil(m/(d+1)) ceil(n/(d2+1)) k."""
+    if algorithm == "qadic":
+        return m * n * ceil_div(k, d + 1)
+    if algorithm == "right":
+        return m * ceil_div(n, d + 1) * k
+    if algorithm == "left":
+        return ceil_div(m, d + 1) * n * k
+    if algorithm == "full":
+        return ceil_div(m, d + 1) * ceil_div(n, d2 + 1) * k
+    raise ValueError(algorithm)

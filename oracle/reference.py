@@ -274,3 +274,132 @@ def centre(x: np.ndarray, p: int) -> np.ndarray:
     """Centred representative: x - p if x > (p-1)//2, as int64 (the INT8 path's operands)."""
     x = np.asarray(x, dtype=np.int64)
     return np.where(x > (p - 1) // 2, x - p, x)
+
+
+# --------------------------------------------------------------------------
+# Left compression (section 5, Table 2): the transpose of section 3's form.
+# A is packed along m, d+1 consecutive rows per word, forward in Q; B stays as
+# residues; every word of CC = CAl x B holds d+1 entries of one column of C.
+# --------------------------------------------------------------------------
+def compress_left(A: np.ndarray, t: int, d: int) -> np.ndarray:
+    """CAl[I, l] = sum_{i=0..d} A[I(d+1)+i, l] * Q^i; rows past m read as 0.
+
+    Returns uint64 words of shape (ceil(m/(d+1)), k).
+    """
+    _check_word_width(t, d)
+    A = np.asarray(A)
+    m, k = A.shape
+    e = d + 1
+    mw = -(-m // e)
+    pad = np.zeros((mw * e, k), dtype=np.uint64)
+    pad[:m] = A
+    out = np.zeros((mw, k), dtype=np.uint64)
+    for i in range(e):
+        out += pad[i::e, :] << np.uint64(t * i)
+    return out
+
+
+def redq_left(CC, t: int, d: int, p: int, m: int) -> np.ndarray:
+    """REDQ by its output for left-compressed words: digit i of word (I, j) is the
+    dot product of row I(d+1)+i of A with column j of B; it goes, reduced mod p,
+    to C[I(d+1)+i, j]."""
+    CC = np.asarray(CC)
+    mw, n = CC.shape
+    e = d + 1
+    Q = 1 << t
+    out = np.zeros((mw * e, n), dtype=np.uint8)
+    for I in range(mw):
+        for j in range(n):
+            r = int(CC[I, j])
+            for i in range(e):
+                out[I * e + i, j] = ((r >> (t * i)) % Q) % p
+    return out[:m]
+
+
+def left_compressed_product_mod_p(A: np.ndarray, B: np.ndarray, p: int, t: int, d: int) -> np.ndarray:
+    """Left compression in exact integers: CAl x B (B uncompressed), then REDQ of
+    every word into d+1 entries of a column of C."""
+    CAl = compress_left(A, t, d)
+    CC = _to_pyint(CAl).dot(_to_pyint(np.asarray(B)))
+    return redq_left(CC, t, d, p, np.asarray(A).shape[0])
+
+
+# --------------------------------------------------------------------------
+# Full compression (section 4): A packed along m in Q (degree d_q), B packed
+# along n in Theta (degree d_theta), Theta = Q^(d_q+1) (eq. (6) with equality).
+# Entry (i, j) of a block of C is the coefficient of Q^i Theta^j of one word.
+# --------------------------------------------------------------------------
+def compress_full_right(B: np.ndarray, t: int, dq: int, dth: int, theta_t: int | None = None) -> np.ndarray:
+    """CBt[l, J] = sum_{j=0..d_theta} B[l, J(d_theta+1)+j] * Theta^j with
+    Theta = 2^theta_t (default 2^(t (d_q+1)) = Q^(d_q+1)); columns past n read as 0.
+
+    Returns Python-int words of shape (k, ceil(n/(d_theta+1))) (object array: a
+    word may exceed 64 bits when the bounds are deliberately broken)."""
+    if theta_t is None:
+        theta_t = t * (dq + 1)
+    B = np.asarray(B)
+    k, n = B.shape
+    e = dth + 1
+    nw = -(-n // e)
+    out = np.zeros((k, nw), dtype=object)
+    for l in range(k):
+        for J in range(nw):
+            w = 0
+            for j in range(e):
+                c = J * e + j
+                if c < n:
+                    w += int(B[l, c]) << (theta_t * j)
+            out[l, J] = w
+    return out
+
+
+def full_word_digit(r: int, t: int, dq: int, i: int, j: int, theta_t: int | None = None) -> int:
+    """Coefficient of Q^i Theta^j of a word whose coefficients are all below Q:
+    floor(r / (Q^i Theta^j)) mod Q."""
+    if theta_t is None:
+        theta_t = t * (dq + 1)
+    return (r >> (t * i + theta_t * j)) % (1 << t)
+
+
+def redq_full(CC, t: int, dq: int, dth: int, p: int, m: int, n: int, theta_t: int | None = None) -> np.ndarray:
+    """Two-variable REDQ by its output: word (I, J) yields C[I(d_q+1)+i, J(d_theta+1)+j]
+    = (coefficient of Q^i Theta^j) mod p for every i <= d_q, j <= d_theta."""
+    CC = np.asarray(CC)
+    mw, nw = CC.shape
+    eq, eth = dq + 1, dth + 1
+    out = np.zeros((mw * eq, nw * eth), dtype=np.uint8)
+    for I in range(mw):
+        for J in range(nw):
+            r = int(CC[I, J])
+            for i in range(eq):
+                for j in range(eth):
+                    out[I * eq + i, J * eth + j] = full_word_digit(r, t, dq, i, j, theta_t) % p
+    return out[:m, :n]
+
+
+def full_compressed_product_mod_p(A: np.ndarray, B: np.ndarray, p: int, t: int, dq: int, dth: int,
+                                  theta_t: int | None = None) -> np.ndarray:
+    """Full compression in exact integers: pack A along m (base Q, degree d_q) and B
+    along n (base Theta, degree d_theta), multiply the packed matrices, read every
+    coefficient of the two-variable polynomial words and reduce it mod p.
+
+    Equals modmul(A, B, p) when k (p-1)^2 < Q (eq. (3)) and Theta >= Q^(d_q+1)
+    (eq. (6)); eq. (7) is what keeps the words exact in floating point."""
+    CAl = compress_left(A, t, dq) if t * (dq + 1) <= 63 else None
+    if CAl is None:
+        raise ValueError("A word does not fit 63 bits")
+    CBt = compress_full_right(B, t, dq, dth, theta_t)
+    CC = _to_pyint(CAl).dot(CBt)
+    return redq_full(CC, t, dq, dth, p, np.asarray(A).shape[0], np.asarray(B).shape[1], theta_t)
+
+
+# --------------------------------------------------------------------------
+# ReduceAndCompress (procedure (1)): the product of compressed matrices handed
+# back compressed, so that products can be chained without leaving the packing.
+# --------------------------------------------------------------------------
+def reduce_and_compress(S, t: int, d: int, p: int, offset: int = 0) -> np.ndarray:
+    """Procedure (1)'s second step on accumulated words S (m x n): reduce every entry
+    (digit d mod p, as extract) and compress the rows of the result, reversed, as
+    CompressRows does: out[i, L] = sum_s C[i, L(d+1)+s] Q^(d-s)."""
+    C = extract(S, t, d, p, offset)
+    return compress_rows_rev(C, t, d)

@@ -161,3 +161,52 @@ def test_fp32_accumulation_bound_is_tight(p):
     assert exact % 2 and exact > 1 << 24           # odd above 2^24: not a float32
     assert outside != exact and outside % p != exact % p
 
+
+
+# --- full compression (section 4): eqs. (6) and (7) -------------------------
+@pytest.mark.parametrize("beta,outside,inside", [(24, (5, 5), (2, 11)), (53, (6, 9), (4, 13))])
+def test_eq7_full_word_bound_tight(beta, outside, inside):
+    # p = 2, k = 1, Q = 2 (eq. (3): 1 < 2).  All-ones operands make the product word
+    # sum_{i,j} Q^i Theta^j = 2^D - 1 with D = (d_q+1)(d_theta+1) digits.  With D one
+    # past the mantissa the single rounded product lands on 2^D: every digit reads 0.
+    p, k, t = 2, 1, 1
+    for (eq_, eth), ok in ((outside, False), (inside, True)):
+        dq, dth = eq_ - 1, eth - 1
+        assert bounds.full_ok(p, k, t, dq, dth, beta) == ok
+        A = np.ones((eq_, k), np.uint8)
+        B = np.ones((k, eth), np.uint8)
+        a = int(ref.compress_left(A, t, dq)[0, 0])
+        b = int(ref.compress_full_right(B, t, dq, dth)[0, 0])
+        w = emulate.accumulate([a], [b], beta)
+        got = ref.redq_full(np.array([[w]], dtype=object), t, dq, dth, p, eq_, eth)
+        want = ref.modmul(A, B, p)
+        assert np.array_equal(got, want) == ok
+    # (the strict form of eq. (7) also leaves out t D = beta, where the largest word
+    # 2^beta - 1 is still exact; t D = beta + 1 is the first failure)
+    assert outside[0] * outside[1] == beta + 1
+
+
+def test_eq6_theta_bound_tight():
+    # Theta = Q^(d_q+1) / 2 lets coefficient (d_q, 0) run into coefficient (0, 1):
+    # the worst-case input is wrong; Theta = Q^(d_q+1) is exact.
+    p, k, t, dq, dth = 3, 2, 4, 1, 1        # k (p-1)^2 = 8 < Q = 16
+    A = np.full((2, k), p - 1, np.uint8)
+    B = np.full((k, 2), p - 1, np.uint8)
+    want = ref.modmul(A, B, p)
+    np.testing.assert_array_equal(ref.full_compressed_product_mod_p(A, B, p, t, dq, dth), want)
+    bad = ref.full_compressed_product_mod_p(A, B, p, t, dq, dth, theta_t=t * (dq + 1) - 1)
+    assert not np.array_equal(bad, want)
+
+
+def test_eq3_bound_tight_for_full_compression():
+    # k (p-1)^2 = Q: a coefficient of Q^i Theta^j reaches Q and reads 0.
+    p, t, dq, dth = 3, 6, 1, 1
+    k = (1 << t) // (p - 1) ** 2
+    A = np.full((2, k), p - 1, np.uint8)
+    B = np.full((k, 2), p - 1, np.uint8)
+    assert not bounds.full_ok(p, k, t, dq, dth, 53)
+    assert not np.array_equal(ref.full_compressed_product_mod_p(A, B, p, t, dq, dth), ref.modmul(A, B, p))
+    k -= 1
+    A, B = A[:, :k], B[:k]
+    assert bounds.full_ok(p, k, t, dq, dth, 53)
+    np.testing.assert_array_equal(ref.full_compressed_product_mod_p(A, B, p, t, dq, dth), ref.modmul(A, B, p))

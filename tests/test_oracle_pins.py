@@ -210,3 +210,94 @@ def test_extract_offset_word():
     T = M + (S >> (t * d) << (t * d))
     got = ref.extract(np.array([[T]], dtype=object), t, d, p, offset=M)[0, 0]
     assert got == ((S >> (t * d)) % (1 << t)) % p
+
+
+# --- left and full compression (sections 4 and 5), ReduceAndCompress (procedure (1)) --
+@pytest.mark.parametrize("p", (2, 3, 5, 7))
+def test_worked_example_full_compressed(p):
+    # Section 4: [a+Qc, b+Qd] x [e+Theta f; g+Theta h]
+    #          = (ae+bg) + Q(ce+dg) + Theta(af+bh) + Q Theta(cf+dh),
+    # with A = [a b; c d] packed along m and B = [e f; g h] packed along n.
+    t = 7
+    Q, Th = 1 << t, 1 << (2 * t)   # Theta = Q^(d_q+1), d_q = 1 (eq. (6))
+    for a, b, c, d_, e, f, g, h in _tuples(p):
+        A = np.array([[a, b], [c, d_]], np.uint8)
+        B = np.array([[e, f], [g, h]], np.uint8)
+        CA = ref.compress_left(A, t, 1)
+        CB = ref.compress_full_right(B, t, 1, 1)
+        assert [int(x) for x in CA[0]] == [a + Q * c, b + Q * d_]
+        assert [int(x) for x in CB[:, 0]] == [e + Th * f, g + Th * h]
+        w = int(CA.astype(object).dot(CB)[0, 0])
+        assert w == (a * e + b * g) + Q * (c * e + d_ * g) + Th * (a * f + b * h) + Q * Th * (c * f + d_ * h)
+        np.testing.assert_array_equal(ref.full_compressed_product_mod_p(A, B, p, t, 1, 1),
+                                      ref.modmul_bruteforce(A, B, p))
+
+
+@pytest.mark.parametrize("p", (2, 3, 5, 7))
+def test_worked_example_left_compressed(p):
+    # Left compression (Table 2), the transpose of section 3's example:
+    # [a+Qc, b+Qd] x [e f; g h] = [(ae+bg) + Q(ce+dg), (af+bh) + Q(cf+dh)].
+    t = 7
+    Q = 1 << t
+    for a, b, c, d_, e, f, g, h in _tuples(p):
+        A = np.array([[a, b], [c, d_]], np.uint8)
+        B = np.array([[e, f], [g, h]], np.uint8)
+        CA = ref.compress_left(A, t, 1)
+        CC = CA.astype(object).dot(B.astype(object))
+        assert int(CC[0, 0]) == (a * e + b * g) + Q * (c * e + d_ * g)
+        assert int(CC[0, 1]) == (a * f + b * h) + Q * (c * f + d_ * h)
+        np.testing.assert_array_equal(ref.redq_left(CC, t, 1, p, 2), ref.modmul_bruteforce(A, B, p))
+
+
+def test_compress_left_is_the_transposed_row_compression():
+    # Packing A along m equals packing A^T along n (section 3's row compression).
+    rng = np.random.default_rng(5)
+    A = rng.integers(0, 7, (11, 6), np.uint8)
+    for t, d in [(5, 2), (9, 4), (17, 1)]:
+        np.testing.assert_array_equal(ref.compress_left(A, t, d), ref.compress_rows_fwd(A.T.copy(), t, d).T)
+        np.testing.assert_array_equal(ref.uncompress_rows_fwd(ref.compress_left(A, t, d).T, t, d, 11), A.T)
+
+
+@pytest.mark.parametrize("p,k,dq,dth", [(2, 5, 3, 3), (3, 64, 1, 1), (3, 31, 2, 1), (7, 40, 1, 2),
+                                        (5, 9, 2, 2), (101, 3, 0, 0), (13, 11, 1, 0), (3, 1, 4, 5)])
+def test_left_and_full_models_equal_definition(p, k, dq, dth):
+    t = bounds_smallest_t(p, k)
+    rng = np.random.default_rng(k * p + dq)
+    for m, n in [(1, 1), (7, 5), (9, 13), (4, 4)]:
+        A, B = rnd(rng, (m, k), p), rnd(rng, (k, n), p)
+        want = ref.modmul(A, B, p)
+        np.testing.assert_array_equal(ref.full_compressed_product_mod_p(A, B, p, t, dq, dth), want)
+        np.testing.assert_array_equal(ref.left_compressed_product_mod_p(A, B, p, t, dq), want)
+    # worst case: every residue p-1, so every coefficient is k (p-1)^2 < Q
+    A, B = np.full((5, k), p - 1, np.uint8), np.full((k, 7), p - 1, np.uint8)
+    np.testing.assert_array_equal(ref.full_compressed_product_mod_p(A, B, p, t, dq, dth),
+                                  np.full((5, 7), (k * (p - 1) ** 2) % p, np.uint8))
+
+
+def bounds_smallest_t(p, k):
+    from oracle import bounds
+    return bounds.smallest_t(p, k)
+
+
+@pytest.mark.parametrize("p,k,d", [(3, 64, 4), (7, 100, 1), (2, 33, 9), (5, 17, 3)])
+def test_reduce_and_compress_chains_products(p, k, d):
+    # Procedure (1) hands C back compressed (rows reversed, as CompressRows packs a
+    # left operand), so a chain of products stays packed: A^3 = (A A) A mod p.
+    t = bounds_smallest_t(p, k)
+    rng = np.random.default_rng(p + k)
+    A = rnd(rng, (k, k), p)
+    CA = ref.compress_rows_rev(A, t, d)
+    CB = ref.compress_cols_fwd(A, t, d)
+    CC = ref.reduce_and_compress(ref.packed_product_exact(CA, CB), t, d, p)
+    A2 = ref.modmul(A, A, p)
+    np.testing.assert_array_equal(CC, ref.compress_rows_rev(A2, t, d))
+    np.testing.assert_array_equal(ref.uncompress_rows_rev(CC, t, d, k), A2)
+    A3 = ref.coefficient_mod_p(ref.packed_product_exact(CC, CB), t, d, p)
+    np.testing.assert_array_equal(A3, ref.modmul_bruteforce(A2, A, p))
+    np.testing.assert_array_equal(A3, ref.modmul(A, A2, p))   # associativity
+    # the offset form of the accumulated word gives the same compressed output
+    beta = 53
+    M = (1 << (beta - 1)) << (t * d)
+    S = ref.packed_product_exact(CA, CB)
+    T = np.vectorize(lambda s: M + (int(s) >> (t * d) << (t * d)), otypes=[object])(S)
+    np.testing.assert_array_equal(ref.reduce_and_compress(T, t, d, p, offset=M), CC)
