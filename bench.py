@@ -42,6 +42,8 @@ KERNEL_SOURCES = {
     "fp4": (_CSRC + "qmm_int8.hip", _CSRC + "qmm_device.h"),
     "fp64_qadic": (_CSRC + "qmm_gemm.hip", _CSRC + "qmm_device.h"),
     "fp64_redq": (_CSRC + "qmm_gemm.hip", _CSRC + "qmm_device.h"),
+    "fp64_left": (_CSRC + "qmm_gemm.hip", _CSRC + "qmm_device.h"),
+    "fp64_full": (_CSRC + "qmm_gemm.hip", _CSRC + "qmm_device.h"),
 }
 
 
@@ -91,6 +93,11 @@ class Stepper:
             nw = -(-k // (plan.d + 1))
             self.CA = torch.empty((m, nw), dtype=wd, device=dev)
             self.CB = torch.empty((nw, n), dtype=wd, device=dev)
+        elif plan.path in (qmm.PATH_FP64_LEFT, qmm.PATH_FP32_LEFT, qmm.PATH_FP64_FULL, qmm.PATH_FP32_FULL):
+            wd = qmm.word_dtype(plan)
+            self.CAl = torch.empty((-(-m // (plan.d + 1)), k), dtype=wd, device=dev)
+            if plan.path in (qmm.PATH_FP64_FULL, qmm.PATH_FP32_FULL):
+                self.CBt = torch.empty((k, -(-n // (plan.d2 + 1))), dtype=wd, device=dev)
         else:
             wd = qmm.word_dtype(plan)
             self.CBr = torch.empty((k, -(-n // (plan.d + 1))), dtype=wd, device=dev)
@@ -125,6 +132,21 @@ class Stepper:
                                (L.qmm_pack_cols_fwd, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CB.data_ptr()), q._ld(CB), st))]
             self.prod_calls = [(L.qmm_gemm_packed, (P, m, n, k, vp(CA.data_ptr()), q._ld(CA), vp(CB.data_ptr()),
                                                     q._ld(CB), vp(C.data_ptr()), q._ld(C), st))]
+        elif pl.path in (q.PATH_FP64_LEFT, q.PATH_FP32_LEFT):
+            CAl = self.CAl
+            self.conv_calls = [(L.qmm_pack_left, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CAl.data_ptr()),
+                                                  q._ld(CAl), st))]
+            self.prod_calls = [(L.qmm_gemm_left_packed, (P, m, n, k, vp(CAl.data_ptr()), q._ld(CAl),
+                                                         vp(B.data_ptr()), q._ld(B), vp(C.data_ptr()), q._ld(C), st))]
+        elif pl.path in (q.PATH_FP64_FULL, q.PATH_FP32_FULL):
+            CAl, CBt = self.CAl, self.CBt
+            self.conv_calls = [(L.qmm_pack_left, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CAl.data_ptr()),
+                                                  q._ld(CAl), st)),
+                               (L.qmm_pack_full_right, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CBt.data_ptr()),
+                                                        q._ld(CBt), st))]
+            self.prod_calls = [(L.qmm_gemm_full_packed, (P, m, n, k, vp(CAl.data_ptr()), q._ld(CAl),
+                                                         vp(CBt.data_ptr()), q._ld(CBt), vp(C.data_ptr()), q._ld(C),
+                                                         st))]
         else:
             CBr = self.CBr
             self.conv_calls = [(L.qmm_pack_rows_fwd, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CBr.data_ptr()),
@@ -157,6 +179,12 @@ class Stepper:
         if pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):
             nw = -(-k // (pl.d + 1))
             return 2.0 * m * n * nw, peak, "TFLOP/s", ("fp64" if fp64 else "fp32") + " MFMA flops on packed words"
+        if pl.path in (q.PATH_FP64_LEFT, q.PATH_FP32_LEFT):
+            mw = -(-m // (pl.d + 1))
+            return 2.0 * mw * n * k, peak, "TFLOP/s", ("fp64" if fp64 else "fp32") + " MFMA flops, word x residue"
+        if pl.path in (q.PATH_FP64_FULL, q.PATH_FP32_FULL):
+            mw, nw = -(-m // (pl.d + 1)), -(-n // (pl.d2 + 1))
+            return 2.0 * mw * nw * k, peak, "TFLOP/s", ("fp64" if fp64 else "fp32") + " MFMA flops, word x word"
         nw = -(-n // (pl.d + 1))
         return 2.0 * m * nw * k, peak, "TFLOP/s", ("fp64" if fp64 else "fp32") + " MFMA flops, residue x word"
 
@@ -192,8 +220,11 @@ class Stepper:
 
 
 def plan_dict(qmm, pl):
-    return {"path": qmm.PATH_NAMES[pl.path], "p": pl.p, "t": pl.t, "d": pl.d, "beta": pl.beta,
-            "k_block": pl.k_block, "regime": qmm.REGIME_NAMES[pl.regime]}
+    out = {"path": qmm.PATH_NAMES[pl.path], "p": pl.p, "t": pl.t, "d": pl.d, "beta": pl.beta,
+           "k_block": pl.k_block, "regime": qmm.REGIME_NAMES[pl.regime]}
+    if pl.d2:
+        out["d2"] = pl.d2
+    return out
 
 
 def cpu_baseline(A, B, p, C_gpu, target_s):
@@ -400,13 +431,100 @@ def run_passes(args, torch, qmm):
                       "peak_GBps": PEAK["hbm_GBps"]}))
 
 
+def run_chain(args, torch, qmm):
+    """A^3 mod 3 of a graph's adjacency matrix on the FP64 Q-adic path, with the
+    intermediate A^2 kept packed (procedure (1) with ReduceAndCompress) against the
+    same chain through bytes (product to bytes, then CompressRows of A^2 again)."""
+    import numpy as np
+    import synth
+    w = synth.WORKLOADS["chain"]
+    p, n = w["p"], w["n"]
+    A = synth.symmetric_graph(n, 0.5, w["seed"])
+    dA = torch.from_numpy(A).cuda()
+    pl = qmm.choose_Qd(p, n, n, n, path=qmm.PATH_FP64_QADIC)
+    log(f"[bench] chain: {pl}")
+    CA = qmm.pack_rows_rev(pl, dA)
+    CB = qmm.pack_cols_fwd(pl, dA)
+    C2 = torch.empty((n, n), dtype=torch.uint8, device="cuda")
+    C3 = torch.empty((n, n), dtype=torch.uint8, device="cuda")
+    CA2 = torch.empty_like(CA)
+
+    def through_bytes():
+        qmm.gemm_packed(pl, n, CA, CB, C2)
+        qmm.pack_rows_rev(pl, C2, CA2)
+        qmm.gemm_packed(pl, n, CA2, CB, C3)
+
+    def packed():
+        qmm.gemm_packed_compress(pl, n, CA, CB, CA2)
+        qmm.gemm_packed(pl, n, CA2, CB, C3)
+
+    def loop(fn, steps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    through_bytes()
+    want = C3.clone()
+    packed()
+    torch.cuda.synchronize()
+    if not torch.equal(C3, want):
+        raise SystemExit("the packed chain disagrees with the chain through bytes")
+    steps = max(3, min(args.steps, 20))
+    ms_bytes = loop(through_bytes, steps)
+    ms_packed = loop(packed, steps)
+    ms_prod = loop(lambda: qmm.gemm_packed(pl, n, CA, CB, C2), steps)
+    ms_comp = loop(lambda: qmm.gemm_packed_compress(pl, n, CA, CB, CA2), steps)
+    ms_pack = loop(lambda: qmm.pack_rows_rev(pl, C2, CA2), steps)
+    macs = 2.0 * n ** 3
+    nw = -(-n // (pl.d + 1))
+    ach = 2.0 * n * n * nw / (ms_comp * 1e-3) / 1e12
+    out = {
+        "metric": "mod-p GMAC/s (m*n*k / time), bit-exact; chosen path vs plain FP64 Q-adic; % MFMA peak",
+        "value": macs / (ms_packed * 1e-3) / 1e9, "unit": "mod-p GMAC/s", "n_gpus": 1, "steps": steps,
+        "warmup": 2, "ms_per_step": ms_packed, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"chain: A^3 mod {p}, A a random symmetric 0/1 matrix, n = {n}, density 0.5, "
+                               f"seed {w['seed']}; A^2 kept packed between the two products",
+                   "plan": plan_dict(qmm, pl), "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64_TFLOPs"], "unit": "TFLOP/s",
+                     "frac": ach / PEAK["fp64_TFLOPs"], "traffic": None,
+                     "kernel": "Q-adic product with the ReduceAndCompress epilogue",
+                     "op": "fp64 MFMA flops on packed words", "avg_launch_ms": ms_comp},
+        "chain_through_bytes_ms": ms_bytes,
+        "product_to_bytes_ms": ms_prod, "product_to_words_ms": ms_comp, "compress_rows_of_bytes_ms": ms_pack,
+        "saved_ms_per_link": ms_prod + ms_pack - ms_comp,
+    }
+    log(f"[bench] chain: packed {ms_packed:.3f} ms, through bytes {ms_bytes:.3f} ms; product to bytes "
+        f"{ms_prod:.3f} ms, to words {ms_comp:.3f} ms, CompressRows {ms_pack:.3f} ms")
+    if not args.no_cpu:
+        from oracle import reference as ref
+        rows = 64
+        t0 = time.perf_counter()
+        A2 = ref.modmul(A, A, p)
+        ok = bool(np.array_equal(ref.modmul(A2[:rows], A, p), C3[:rows].cpu().numpy()))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": (n ** 3 + rows * n * n) / dt / 1e9, "unit": "mod-p GMAC/s",
+                               "cores": ref.oracle_threads(), "kind": "oracle",
+                               "sample": f"A^2 whole and the first {rows} rows of A^3, {dt:.2f} s",
+                               "matches_gpu_rows": ok}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="square",
-                    help="square, large, graph, small, batched; or passes (HBM rate of each standalone pass)")
+                    help="square, large, graph, small, thin, batched; chain (a matrix power kept packed "
+                         "between products); or passes (HBM rate of each standalone pass)")
     ap.add_argument("--paths", default="all", help="'all' or 'chosen'")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -442,6 +560,9 @@ def main():
     if args.workload == "passes":
         run_passes(args, torch, qmm)
         return
+    if args.workload == "chain":
+        run_chain(args, torch, qmm)
+        return
     p, A, B = synth.workload(args.workload)
     m, k = A.shape
     n = B.shape[1]
@@ -458,7 +579,10 @@ def main():
                      ("fp64_qadic_paper", qmm.PATH_FP64_QADIC, qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4),
                      ("fp64_redq", qmm.PATH_FP64_REDQ, 0),
                      ("fp32_qadic", qmm.PATH_FP32_QADIC, 0),
-                     ("fp32_redq", qmm.PATH_FP32_REDQ, 0)]
+                     ("fp32_redq", qmm.PATH_FP32_REDQ, 0),
+                     ("fp64_left", qmm.PATH_FP64_LEFT, 0),
+                     ("fp64_full", qmm.PATH_FP64_FULL, 0),
+                     ("fp64_any_compression", qmm.PATH_FP64_QADIC, qmm.PLAN_ANY_COMPRESSION)]
     variants.append(("chosen", qmm.PATH_AUTO, 0))
     results = {}
     reference_C = None

@@ -8,6 +8,12 @@
  *     holds every dot product as its degree-d coefficient (procedures (1), (2));
  *   - section 3: a packed word times a single residue, followed by the
  *     simultaneous reduction REDQ (procedure (5));
+ *   - section 4: full compression, A packed along m in Q and B along n in
+ *     Theta = Q^(d+1), every product word holding a block of C (eqs. (6), (7));
+ *   - section 5, Table 2: left compression (A packed along m) and the choice of
+ *     the compressed dimension from the shape;
+ *   - procedure (1): the product of compressed matrices returned compressed
+ *     (ReduceAndCompress), so products chain without unpacking;
  *   - sections 2.4, 2.5 and 5: the bounds tying p, k, Q, d and the mantissa.
  * Two further forms go beyond the paper: INT8 matrix cores on centred residues
  * with int32 accumulation, and batches of independent products in one launch.
@@ -52,8 +58,14 @@ typedef enum {
     QMM_PATH_FP32_QADIC = 3,  /* as FP64_QADIC with a 24-bit mantissa */
     QMM_PATH_FP32_REDQ = 4,   /* as FP64_REDQ with a 24-bit mantissa */
     QMM_PATH_INT8 = 5,        /* centred residues, int8 matrix cores, int32 accumulation */
-    QMM_PATH_FP4 = 6          /* centred residues as FP4 (e2m1) codes, FP4 matrix cores with
+    QMM_PATH_FP4 = 6,         /* centred residues as FP4 (e2m1) codes, FP4 matrix cores with
                                  FP32 accumulation that stays exact (p <= 8) */
+    QMM_PATH_FP64_LEFT = 7,   /* m-compressed words (d+1 rows of A) times residues + REDQ
+                                 (left compression, Table 2) */
+    QMM_PATH_FP32_LEFT = 8,   /* as FP64_LEFT with a 24-bit mantissa */
+    QMM_PATH_FP64_FULL = 9,   /* A packed along m (degree d in Q) times B packed along n (degree
+                                 d2 in Theta = Q^(d+1)), two-variable REDQ (section 4) */
+    QMM_PATH_FP32_FULL = 10   /* as FP64_FULL with a 24-bit mantissa */
 } qmm_path;
 
 typedef enum {
@@ -71,6 +83,13 @@ typedef enum {
 #define QMM_BOUND_G4       4u  /* assume 4 products may be summed before one rounding */
 #define QMM_BOUND_EQ4      8u  /* also impose eq. (4) as printed, Q^(d+1) < 2^beta, instead of
                                   only its sharper sum form (section 2.5) */
+#define QMM_PLAN_ANY_COMPRESSION 16u
+                               /* with an FP64 (FP32) path: choose among the four compressions of
+                                  that mantissa -- k (procedure (2)), n (procedure (5)), m (left)
+                                  and m and n (full, section 4) -- the one with the fewest
+                                  multiply-adds of packed words for this shape (Table 2 with the
+                                  classical product; the compressed dimension is the largest one
+                                  up to the rounding of each count), ties to k */
 
 /* A plan: everything the kernels need to know about the packing.  Plans are
  * plain values; qmm_choose_Qd fills one, and the product calls re-validate any
@@ -90,6 +109,8 @@ typedef struct {
                           INT8 and FP4: 1 = 128 x 128 output tiles (4 wavefronts),
                           2 = 256 x 256 (8 wavefronts of 128 x 64),
                           3 = 256 x 256 (16 wavefronts of 64 x 64); other values are EINVAL */
+    uint32_t d2;       /* FULL paths: degree in Theta = Q^(d+1), d2+1 columns of B per word
+                          (d+1 rows of A per word); 0 on every other path */
 } qmm_plan;
 
 /* Choose (Q = 2^t, d, k_block, path) for a product of shape m x k times k x n
@@ -162,7 +183,8 @@ qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, i
                                    size_t *bytes);
 
 /* C = A x B mod p from bytes to bytes (procedure (2) for the QADIC paths,
- * procedure (5) for the REDQ paths, INT8 matrix cores for the INT8 path).
+ * procedure (5) for the REDQ paths, left and full compression for the LEFT and
+ * FULL paths, INT8 / FP4 matrix cores for the INT8 / FP4 paths).
  * plan == NULL: qmm_choose_Qd(p, m, n, k, 0, QMM_PATH_AUTO, 0) is used.
  * A: m x k, B: k x n, C: m x n bytes (C must not overlap A or B).
  * ws: device workspace of ws_bytes >= qmm_gemm_workspace_size (may be NULL when
@@ -177,6 +199,45 @@ qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
 qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
                            const void *CA, int64_t ldca, const void *CB, int64_t ldcb,
                            uint8_t *C, int64_t ldc, void *stream);
+
+/* Procedure (1) with ReduceAndCompress: the product of compressed matrices handed
+ * back compressed.  CC[i][L] = sum_{s=0..d} C[i][L(d+1)+s] * Q^(d-s) (the
+ * CompressRows layout, columns past n read as 0) where C = digit d of CA x CB, mod p;
+ * CC is m x ceil(n/(d+1)) words (ldcc >= that) and can be the CA of a next product
+ * with the same plan and k = n (chained products, e.g. powers of a matrix).
+ * CA, CB as for qmm_gemm_packed.  QADIC paths only; plans with d + 1 <= 128. */
+qmm_status qmm_gemm_packed_compress(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                                    const void *CA, int64_t ldca, const void *CB, int64_t ldcb,
+                                    void *CC, int64_t ldcc, void *stream);
+
+/* Left compression (Table 2; section 3's packing applied to the rows of A):
+ * CAl[I][l] = sum_{i=0..d} A[I(d+1)+i][l] * Q^i, rows past m read as 0.
+ * A: m x k bytes (lda >= k).  CAl: ceil(m/(d+1)) x k words (ldcal >= k).
+ * LEFT and FULL plans (the left operand of both). */
+qmm_status qmm_pack_left(const qmm_plan *plan, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
+                         void *CAl, int64_t ldcal, void *stream);
+
+/* Full compression (section 4), right operand packed along n in Theta = Q^(d+1):
+ * CBt[l][J] = sum_{j=0..d2} B[l][J(d2+1)+j] * Theta^j, columns past n read as 0.
+ * B: k x n bytes.  CBt: k x ceil(n/(d2+1)) words (ldcbt >= that).  FULL plans. */
+qmm_status qmm_pack_full_right(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                               void *CBt, int64_t ldcbt, void *stream);
+
+/* Left compression, product step: CC = CAl x B over exact words (every coefficient
+ * below Q by eq. (3), every word below Q^(d+1) < 2^beta by eq. (4)), then REDQ of
+ * each word into its d+1 residues, written to C[I(d+1)+i][j] for rows < m.
+ * CAl from qmm_pack_left with this plan; B: k x n residues.  LEFT plans. */
+qmm_status qmm_gemm_left_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                                const void *CAl, int64_t ldcal, const uint8_t *B, int64_t ldb,
+                                uint8_t *C, int64_t ldc, void *stream);
+
+/* Full compression, product step: CC = CAl x CBt over exact words (eq. (3) for every
+ * coefficient, eq. (7) Q^((d+1)(d2+1)) < 2^beta for the word), then one REDQ per
+ * word: the coefficient of Q^i Theta^j goes, mod p, to C[I(d+1)+i][J(d2+1)+j].
+ * CAl from qmm_pack_left, CBt from qmm_pack_full_right, both with this plan. */
+qmm_status qmm_gemm_full_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
+                                const void *CAl, int64_t ldcal, const void *CBt, int64_t ldcbt,
+                                uint8_t *C, int64_t ldc, void *stream);
 
 /* Procedure (5) on an already row-compressed right operand: C = REDQ(A x CBr).
  * A: m x k residues (converted to words on the fly); CBr: k x ceil(n/(d+1)) words

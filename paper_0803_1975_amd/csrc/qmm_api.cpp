@@ -49,6 +49,14 @@ Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
         const int64_t nw = words_for(n, pl.d);
         L.ld_b = nw;
         L.bytes = align_up((size_t)kk * nw * word_bytes(pl));
+    } else if (path_is_left(pl.path)) {
+        L.ld_a = kk;
+        L.bytes = align_up((size_t)words_for(m, pl.d) * kk * word_bytes(pl));
+    } else if (path_is_full(pl.path)) {
+        L.ld_a = kk;
+        L.ld_b = words_for(n, pl.d2);
+        L.off_b = align_up((size_t)words_for(m, pl.d) * kk * word_bytes(pl));
+        L.bytes = L.off_b + align_up((size_t)kk * L.ld_b * word_bytes(pl));
     } else if (pl.path == QMM_PATH_INT8) {
         L.ld_b = int8_bt_ld(kk);
         L.bytes = align_up((size_t)n * L.ld_b);
@@ -179,6 +187,16 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
         if ((st = launch_pack_rows_fwd(pl, k, n, B, ldb, w, L.ld_b, stream)) != QMM_OK) return st;
         return launch_gemm_redq(pl, m, n, k, A, lda, w, L.ld_b, C, ldc, stream);
     }
+    if (path_is_left(pl.path)) {
+        if ((st = launch_pack_cols_fwd(pl, m, k, A, lda, w, L.ld_a, stream)) != QMM_OK) return st;
+        return launch_gemm_left(pl, m, n, k, w, L.ld_a, B, ldb, C, ldc, stream);
+    }
+    if (path_is_full(pl.path)) {
+        void *CAl = w, *CBt = w + L.off_b;
+        if ((st = launch_pack_cols_fwd(pl, m, k, A, lda, CAl, L.ld_a, stream)) != QMM_OK) return st;
+        if ((st = launch_pack_rows_fwd(theta_plan(pl), k, n, B, ldb, CBt, L.ld_b, stream)) != QMM_OK) return st;
+        return launch_gemm_full(pl, m, n, k, CAl, L.ld_a, CBt, L.ld_b, C, ldc, stream);
+    }
     if (pl.path == QMM_PATH_INT8) {
         int8_t *Bt = (int8_t *)w;
         if ((st = launch_centre_transpose(pl, k, n, B, ldb, Bt, L.ld_b, stream)) != QMM_OK) return st;
@@ -300,4 +318,75 @@ extern "C" qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int
     if (m == 0 || n == 0) return QMM_OK;
     if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
     return launch_gemm_redq(*plan, m, n, k, A, lda, CBr, ldcbr, C, ldc, stream);
+}
+
+extern "C" qmm_status qmm_gemm_packed_compress(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const void *CA,
+                                               int64_t ldca, const void *CB, int64_t ldcb, void *CC, int64_t ldcc,
+                                               void *stream) {
+    if (!plan) return fail(QMM_EINVAL, "plan is NULL");
+    if (!path_is_qadic(plan->path)) return fail(QMM_EINVAL, "qmm_gemm_packed_compress takes a QADIC plan");
+    if (plan->p > 256) return fail(QMM_EINVAL, "residues of the output words need p <= 256");
+    if (plan->d + 1 > 128) return fail(QMM_EUNSUPPORTED, "compressed output needs d + 1 <= 128");
+    qmm_status st = qmm_validate_plan(plan, m, n, k);
+    if (st != QMM_OK) return st;
+    if ((st = check_plan_for_words(plan)) != QMM_OK) return st;
+    const int64_t nw = words_for(k < 1 ? 1 : k, plan->d);
+    if (bad_matrix(m, nw, CA, ldca) || bad_matrix(nw, n, CB, ldcb) || bad_matrix(m, words_for(n, plan->d), CC, ldcc))
+        return fail(QMM_EINVAL, "bad pointer or leading dimension");
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return fail(QMM_EUNSUPPORTED, "compressed output of an empty product (k = 0) is not produced");
+    return launch_gemm_qadic_compress(*plan, m, n, k, CA, ldca, CB, ldcb, CC, ldcc, stream);
+}
+
+extern "C" qmm_status qmm_pack_left(const qmm_plan *plan, int64_t m, int64_t k, const uint8_t *A, int64_t lda,
+                                    void *CAl, int64_t ldcal, void *stream) {
+    qmm_status st = check_plan_for_words(plan);
+    if (st != QMM_OK) return st;
+    if (!path_is_left(plan->path) && !path_is_full(plan->path))
+        return fail(QMM_EINVAL, "qmm_pack_left takes a LEFT or FULL plan");
+    if (bad_matrix(m, k, A, lda)) return fail(QMM_EINVAL, "A: bad size, pointer or lda");
+    if (bad_matrix(words_for(m, plan->d), k, CAl, ldcal)) return fail(QMM_EINVAL, "CAl: bad pointer or ldcal");
+    return launch_pack_cols_fwd(*plan, m, k, A, lda, CAl, ldcal, stream);
+}
+
+extern "C" qmm_status qmm_pack_full_right(const qmm_plan *plan, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
+                                          void *CBt, int64_t ldcbt, void *stream) {
+    if (!plan) return fail(QMM_EINVAL, "plan is NULL");
+    if (!path_is_full(plan->path)) return fail(QMM_EINVAL, "qmm_pack_full_right takes a FULL plan");
+    if ((uint64_t)plan->t * (plan->d + 1) > 63 || plan->d2 > 63) return fail(QMM_EINVAL, "Theta = Q^(d+1) out of range");
+    const qmm_plan tp = theta_plan(*plan);
+    qmm_status st = check_plan_for_words(&tp);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(k, n, B, ldb)) return fail(QMM_EINVAL, "B: bad size, pointer or ldb");
+    if (bad_matrix(k, words_for(n, plan->d2), CBt, ldcbt)) return fail(QMM_EINVAL, "CBt: bad pointer or ldcbt");
+    return launch_pack_rows_fwd(tp, k, n, B, ldb, CBt, ldcbt, stream);
+}
+
+extern "C" qmm_status qmm_gemm_left_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const void *CAl,
+                                           int64_t ldcal, const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc,
+                                           void *stream) {
+    if (!plan || !path_is_left(plan->path)) return fail(QMM_EINVAL, "a LEFT plan is required");
+    if (plan->p > 256) return fail(QMM_EINVAL, "byte results need p <= 256");
+    qmm_status st = qmm_validate_plan(plan, m, n, k);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(words_for(m, plan->d), k, CAl, ldcal) || bad_matrix(k, n, B, ldb) || bad_matrix(m, n, C, ldc))
+        return fail(QMM_EINVAL, "bad pointer or leading dimension");
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
+    return launch_gemm_left(*plan, m, n, k, CAl, ldcal, B, ldb, C, ldc, stream);
+}
+
+extern "C" qmm_status qmm_gemm_full_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const void *CAl,
+                                           int64_t ldcal, const void *CBt, int64_t ldcbt, uint8_t *C, int64_t ldc,
+                                           void *stream) {
+    if (!plan || !path_is_full(plan->path)) return fail(QMM_EINVAL, "a FULL plan is required");
+    if (plan->p > 256) return fail(QMM_EINVAL, "byte results need p <= 256");
+    qmm_status st = qmm_validate_plan(plan, m, n, k);
+    if (st != QMM_OK) return st;
+    if (bad_matrix(words_for(m, plan->d), k, CAl, ldcal) || bad_matrix(k, words_for(n, plan->d2), CBt, ldcbt) ||
+        bad_matrix(m, n, C, ldc))
+        return fail(QMM_EINVAL, "bad pointer or leading dimension");
+    if (m == 0 || n == 0) return QMM_OK;
+    if (k == 0) return launch_fill_u8(C, m, n, ldc, 0, stream);
+    return launch_gemm_full(*plan, m, n, k, CAl, ldcal, CBt, ldcbt, C, ldc, stream);
 }

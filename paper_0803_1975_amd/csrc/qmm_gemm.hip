@@ -2,9 +2,16 @@
 //
 //   EPI_QADIC  procedure (1)/(2): T = start + CA x CB over packed words (CA rows
 //              reversed, CB columns forward), then digit d of every word mod p.
-//   EPI_REDQ   procedure (5): CC = A x CBr with A residues (converted to words on
-//              the way into LDS) and CBr the row-compressed right operand; every
-//              word is then split by REDQ into d+1 residues of consecutive columns.
+//   EPI_REDQ   words that hold a (d_q+1) x (d_theta+1) block of C, split by one
+//              REDQ (one division by p) into all their coefficients mod p:
+//              procedure (5) (A residues times the row-compressed CBr, d_q = 0),
+//              left compression (Table 2: CAl packed along m times B residues,
+//              d_theta = 0) and full compression (section 4: CAl times CBt packed
+//              along n in Theta = Q^(d_q+1)).  Residue operands are converted to
+//              words on the way into LDS.
+//   EPI_PACK   procedure (1) with ReduceAndCompress: as EPI_QADIC, then the
+//              reduced tile goes through LDS and leaves as CompressRows words
+//              (reversed, d+1 columns per word), so products can be chained.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup, 2 x 2 wavefronts of
 // 64 x 64 each, i.e. 4 x 4 MFMA 16x16x4 tiles per wavefront.  K advances 16
@@ -54,17 +61,23 @@ template <> struct Mma<float> {
 constexpr int BM = 128, BN = 128, KT = kQadicKT, NT = 256, APAD = 1;
 static_assert(KT == 16, "the staging maps below assume 16-element K stages");
 
-enum { EPI_QADIC = 0, EPI_REDQ = 1 };
+enum { EPI_QADIC = 0, EPI_REDQ = 1, EPI_PACK = 2 };
 
 struct GemmArgs {
-    int64_t m, n, kdim;      // output rows, output word-columns, inner length of the K loop
+    int64_t m, n, kdim;      // rows and columns of the product of (packed) operands, inner length
     const void *A;
-    int64_t lda;             // Q-adic: CA words; REDQ: residues (bytes)
+    int64_t lda;             // words, or residues (bytes) for procedure (5)
     const void *B;
-    int64_t ldb;             // words
+    int64_t ldb;             // words, or residues (bytes) for left compression
     uint8_t *C;
     int64_t ldc;
-    int64_t n_out;           // columns of C (REDQ: n; Q-adic: n)
+    int64_t m_out, n_out;    // rows and columns of C
+    uint32_t dq, dth;        // EPI_REDQ: a word holds C's (dq+1) x (dth+1) block
+    int32_t tiles_m, tiles_n;
+    int32_t col_step;        // output columns per tile: BN, or whole words of BN (EPI_PACK)
+    int32_t tile_words;      // EPI_PACK: words per tile row
+    void *CW;                // EPI_PACK: compressed output, words
+    int64_t ldcw, n_words;
     int32_t kb_tiles;        // K stages per block (blocked Q-adic plans)
     uint32_t p, t, d, td;
     uint64_t qmask;
@@ -80,8 +93,7 @@ struct GemmArgs {
 // the first remap gives each XCD a contiguous range of tiles, the second walks
 // them in groups of 8 tile-rows so neighbours share A row-panels and B panels in
 // that XCD's L2.
-__device__ __forceinline__ void tile_coords(int64_t m, int64_t n, int &tm, int &tn) {
-    const int tiles_m = (int)ceil_div(m, BM), tiles_n = (int)ceil_div(n, BN);
+__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
     const int nb = gridDim.x;
     int bid = blockIdx.x;
     if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
@@ -95,7 +107,7 @@ __device__ __forceinline__ void tile_coords(int64_t m, int64_t n, int &tm, int &
     tn = local / gsize;
 }
 
-template <typename W, typename AT, int EPI, bool OFFSET, bool BLOCKED>
+template <typename W, typename AT, typename BT, int EPI, bool OFFSET, bool BLOCKED>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     using MM = Mma<W>;
     using acc_t = typename MM::acc_t;
@@ -105,8 +117,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     int tm, tn;
-    tile_coords(g.m, g.n, tm, tn);
-    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+    tile_coords(g.tiles_m, g.tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * g.col_step;
 
     const W start = (W)g.start;
     acc_t acc[4][4];
@@ -130,7 +142,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     const int64_t a_row = row0 + ra_r;
     const bool a_row_ok = a_row < g.m;
     const AT *__restrict__ Ap = (const AT *)g.A + (a_row_ok ? a_row : 0) * g.lda;
-    const W *__restrict__ Bp = (const W *)g.B;
+    const BT *__restrict__ Bp = (const BT *)g.B;
     W ra[8], rb[8];
 
     auto load_stage = [&](int kt) {
@@ -142,11 +154,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
         }
         const int64_t gk = k0 + rb_k;
         const bool krow_ok = gk < g.kdim;
-        const W *brow = Bp + (krow_ok ? gk : 0) * g.ldb;
+        const BT *brow = Bp + (krow_ok ? gk : 0) * g.ldb;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int64_t cc = col0 + rb_c + e;
-            rb[e] = (krow_ok && cc < g.n) ? brow[cc] : (W)0;
+            rb[e] = (krow_ok && cc < g.n) ? (W)brow[cc] : (W)0;
         }
     };
     auto store_stage = [&](int buf) {
@@ -203,6 +215,47 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     }
 
     // Epilogue.
+    // Digit d of the accumulated word at (mi, ni, r), reduced mod p.
+    auto qadic_value = [&](int mi, int ni, int r) -> uint32_t {
+        if constexpr (BLOCKED)
+            return mod_u32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.magic);
+        else if (g.small_digit) return mod_u32(digit32(acc[mi][ni][r]), g.p, g.magic);
+        else return mod_u64(qadic_digit<W>(acc[mi][ni][r], OFFSET, g.td, g.qmask), g.p, g.invp);
+    };
+    if constexpr (EPI == EPI_PACK) {
+        // ReduceAndCompress: the tile's residues go to LDS (the staging buffers are
+        // free once every wavefront has read the last stage), then each thread packs
+        // whole words of d+1 columns, first column in the top power (CompressRows).
+        // Columns past n read as 0, the padding of a short last word.
+        constexpr int LDS_C = BN + 4;
+        static_assert(sizeof(sA) >= BM * LDS_C, "the reduced tile must fit the A staging buffers");
+        uint8_t *sC = (uint8_t *)&sA[0][0][0];
+        __syncthreads();
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rl = wm * 64 + mi * 16 + MM::row(lane, r);
+                    const int cl = wn * 64 + ni * 16 + (lane & 15);
+                    const bool in = row0 + rl < g.m && col0 + cl < g.n && cl < g.col_step;
+                    sC[rl * LDS_C + cl] = in ? (uint8_t)qadic_value(mi, ni, r) : (uint8_t)0;
+                }
+        __syncthreads();
+        const int e = (int)g.d + 1, tw = g.tile_words;
+        W *CW = (W *)g.CW;
+        for (int idx = tid; idx < BM * tw; idx += NT) {
+            const int rl = idx / tw, L = idx - rl * tw;
+            const int64_t row = row0 + rl, wc = (int64_t)tn * tw + L;
+            if (row >= g.m || wc >= g.n_words) continue;
+            const uint8_t *src = sC + rl * LDS_C + L * e;
+            uint64_t w = 0;
+            for (int s = 0; s < e; ++s) w = (w << g.t) | src[s];
+            CW[row * g.ldcw + wc] = word_from_u64<W>(w);
+        }
+        return;
+    }
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -213,25 +266,25 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
                 const int64_t col = col0 + wn * 64 + ni * 16 + (lane & 15);
                 if (row >= g.m || col >= g.n) continue;
                 if constexpr (EPI == EPI_QADIC) {
-                    uint32_t v;
-                    if constexpr (BLOCKED)
-                        v = mod_u32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.magic);
-                    else if (g.small_digit) v = mod_u32(digit32(acc[mi][ni][r]), g.p, g.magic);
-                    else v = mod_u64(qadic_digit<W>(acc[mi][ni][r], OFFSET, g.td, g.qmask), g.p, g.invp);
-                    g.C[row * g.ldc + col] = (uint8_t)v;
+                    g.C[row * g.ldc + col] = (uint8_t)qadic_value(mi, ni, r);
                 } else {
-                    // REDQ of the exact word, then its d+1 residues to consecutive columns.
+                    // REDQ of the exact word r = sum_q c_q Q^q: with s = floor(r/p),
+                    // mu_q = (r >> tq) - p (s >> tq) = floor(r / Q^q) mod p, and
+                    // c_q = mu_q - Q mu_(q+1) (mod p).  Coefficient q = i + j (dq+1) is
+                    // entry (i, j) of the word's block of C.
                     const uint64_t w = u64_from_word(acc[mi][ni][r]);
                     const uint64_t s = div_u64(w, g.p, g.invp);
-                    uint8_t *crow = g.C + row * g.ldc;
                     uint32_t mu_next = 0;
-                    for (int32_t j = (int32_t)g.d; j >= 0; --j) {
-                        const uint32_t sh = g.t * (uint32_t)j;
-                        const uint32_t mu = (uint32_t)((w >> sh) - (uint64_t)g.p * (s >> sh));
-                        const uint64_t v = (uint64_t)mu + (uint64_t)g.qmodp * g.p - (uint64_t)g.qmodp * mu_next;
-                        const int64_t c = col * (g.d + 1) + j;
-                        if (c < g.n_out) crow[c] = (uint8_t)mod_u64(v, g.p, g.invp);
-                        mu_next = mu;
+                    for (int32_t j = (int32_t)g.dth; j >= 0; --j) {
+                        const int64_t co = col * (g.dth + 1) + j;
+                        for (int32_t i = (int32_t)g.dq; i >= 0; --i) {
+                            const uint32_t sh = g.t * (uint32_t)(i + j * (int32_t)(g.dq + 1));
+                            const uint32_t mu = (uint32_t)((w >> sh) - (uint64_t)g.p * (s >> sh));
+                            const uint64_t v = (uint64_t)mu + (uint64_t)g.qmodp * g.p - (uint64_t)g.qmodp * mu_next;
+                            const int64_t ro = row * (g.dq + 1) + i;
+                            if (ro < g.m_out && co < g.n_out) g.C[ro * g.ldc + co] = (uint8_t)mod_u64(v, g.p, g.invp);
+                            mu_next = mu;
+                        }
                     }
                 }
             }
@@ -243,12 +296,35 @@ qmm_status check_launch(const char *what) {
     return QMM_OK;
 }
 
-template <typename W>
+// Fields every variant needs, from the plan.
+void common_args(GemmArgs &g, const qmm_plan &pl) {
+    g.p = pl.p;
+    g.t = pl.t;
+    g.d = pl.d;
+    g.td = pl.t * pl.d;
+    g.qmask = (1ull << pl.t) - 1;
+    g.invp = 1.0 / (double)pl.p;
+    g.magic = mod_magic(pl.p);
+    g.qmodp = (uint32_t)((1ull << pl.t) % pl.p);
+    g.col_step = BN;
+}
+
+dim3 grid_for(GemmArgs &g) {
+    g.tiles_m = (int32_t)ceil_div(g.m, BM);
+    g.tiles_n = (int32_t)ceil_div(g.n, g.col_step);
+    return dim3((unsigned)((int64_t)g.tiles_m * g.tiles_n));
+}
+
+// Procedure (1)/(2), bytes out (EPI_QADIC) or compressed out (EPI_PACK: CW is
+// m x ceil(n/(d+1)) words, leading dimension ldcw).
+template <typename W, int EPI>
 qmm_status launch_qadic_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CA, int64_t ldca,
-                          const void *CB, int64_t ldcb, uint8_t *C, int64_t ldc, hipStream_t s) {
+                          const void *CB, int64_t ldcb, uint8_t *C, int64_t ldc, void *CW, int64_t ldcw,
+                          hipStream_t s) {
     GemmArgs g{};
-    g.m = m;
-    g.n = n;
+    common_args(g, pl);
+    g.m = g.m_out = m;
+    g.n = g.n_out = n;
     g.kdim = words_for(k, pl.d);
     g.A = CA;
     g.lda = ldca;
@@ -256,61 +332,61 @@ qmm_status launch_qadic_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     g.ldb = ldcb;
     g.C = C;
     g.ldc = ldc;
-    g.n_out = n;
     const bool blocked = pl.k_block < k;
     g.kb_tiles = blocked ? (int32_t)((pl.k_block / (pl.d + 1)) / KT) : 0;
-    g.p = pl.p;
-    g.t = pl.t;
-    g.d = pl.d;
-    g.td = pl.t * pl.d;
-    g.qmask = (1ull << pl.t) - 1;
-    g.invp = 1.0 / (double)pl.p;
     const bool offset = pl.regime == QMM_REGIME_OFFSET;
     g.start = offset ? ldexp(1.0, WordTraits<W>::beta - 1 + (int)(pl.t * pl.d)) : 0.0;
-    g.magic = mod_magic(pl.p);
     g.inv_qd = ldexp(1.0, -(int)(pl.t * pl.d));
     g.inv_q = ldexp(1.0, -(int)pl.t);
     g.q = ldexp(1.0, (int)pl.t);
     g.small_digit = pl.t <= 31;
     if (blocked && pl.t > 31) return fail(QMM_EUNSUPPORTED, "blocked plans need t <= 31");
-    const dim3 grid((unsigned)(ceil_div(m, BM) * ceil_div(n, BN)));
+    if (EPI == EPI_PACK) {
+        // A tile covers whole words: the largest multiple of d+1 columns in BN.
+        g.tile_words = BN / (int32_t)(pl.d + 1);
+        if (g.tile_words < 1) return fail(QMM_EUNSUPPORTED, "compressed output needs d + 1 <= 128");
+        g.col_step = g.tile_words * (int32_t)(pl.d + 1);
+        g.CW = CW;
+        g.ldcw = ldcw;
+        g.n_words = words_for(n, pl.d);
+    }
+    const dim3 grid = grid_for(g);
     if (offset && blocked)
-        gemm_kernel<W, W, EPI_QADIC, true, true><<<grid, NT, 0, s>>>(g);
+        gemm_kernel<W, W, W, EPI, true, true><<<grid, NT, 0, s>>>(g);
     else if (offset)
-        gemm_kernel<W, W, EPI_QADIC, true, false><<<grid, NT, 0, s>>>(g);
+        gemm_kernel<W, W, W, EPI, true, false><<<grid, NT, 0, s>>>(g);
     else if (blocked)
-        gemm_kernel<W, W, EPI_QADIC, false, true><<<grid, NT, 0, s>>>(g);
+        gemm_kernel<W, W, W, EPI, false, true><<<grid, NT, 0, s>>>(g);
     else
-        gemm_kernel<W, W, EPI_QADIC, false, false><<<grid, NT, 0, s>>>(g);
-    return check_launch("gemm_qadic");
+        gemm_kernel<W, W, W, EPI, false, false><<<grid, NT, 0, s>>>(g);
+    return check_launch(EPI == EPI_PACK ? "gemm_qadic_compress" : "gemm_qadic");
 }
 
-template <typename W>
-qmm_status launch_redq_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
-                         const void *CBr, int64_t ldcbr, uint8_t *C, int64_t ldc, hipStream_t s) {
+// The REDQ family: the product of (packed) operands is rows x cols words, each
+// holding a (dq+1) x (dth+1) block of the m x n result.
+template <typename W, typename AT, typename BT>
+qmm_status launch_redq_w(const qmm_plan &pl, uint32_t dq, uint32_t dth, int64_t m, int64_t n, int64_t k,
+                         const void *A, int64_t lda, const void *B, int64_t ldb, uint8_t *C, int64_t ldc,
+                         hipStream_t s, const char *what) {
     GemmArgs g{};
-    g.m = m;
-    g.n = words_for(n, pl.d);
+    common_args(g, pl);
+    g.m = words_for(m, dq);
+    g.n = words_for(n, dth);
+    g.m_out = m;
+    g.n_out = n;
+    g.dq = dq;
+    g.dth = dth;
     g.kdim = k;
     g.A = A;
     g.lda = lda;
-    g.B = CBr;
-    g.ldb = ldcbr;
+    g.B = B;
+    g.ldb = ldb;
     g.C = C;
     g.ldc = ldc;
-    g.n_out = n;
-    g.kb_tiles = 0;
-    g.p = pl.p;
-    g.t = pl.t;
-    g.d = pl.d;
-    g.td = pl.t * pl.d;
-    g.qmask = (1ull << pl.t) - 1;
-    g.invp = 1.0 / (double)pl.p;
     g.start = 0.0;
-    g.qmodp = (uint32_t)((1ull << pl.t) % pl.p);
-    const dim3 grid((unsigned)(ceil_div(m, BM) * ceil_div(g.n, BN)));
-    gemm_kernel<W, uint8_t, EPI_REDQ, false, false><<<grid, NT, 0, s>>>(g);
-    return check_launch("gemm_redq");
+    const dim3 grid = grid_for(g);
+    gemm_kernel<W, AT, BT, EPI_REDQ, false, false><<<grid, NT, 0, s>>>(g);
+    return check_launch(what);
 }
 
 }  // namespace
@@ -318,15 +394,45 @@ qmm_status launch_redq_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, co
 qmm_status launch_gemm_qadic(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CA, int64_t ldca,
                              const void *CB, int64_t ldcb, uint8_t *C, int64_t ldc, void *stream) {
     if (m == 0 || n == 0) return QMM_OK;
-    if (pl.beta == 24) return launch_qadic_w<float>(pl, m, n, k, CA, ldca, CB, ldcb, C, ldc, (hipStream_t)stream);
-    return launch_qadic_w<double>(pl, m, n, k, CA, ldca, CB, ldcb, C, ldc, (hipStream_t)stream);
+    const hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24) return launch_qadic_w<float, EPI_QADIC>(pl, m, n, k, CA, ldca, CB, ldcb, C, ldc, nullptr, 0, s);
+    return launch_qadic_w<double, EPI_QADIC>(pl, m, n, k, CA, ldca, CB, ldcb, C, ldc, nullptr, 0, s);
+}
+
+qmm_status launch_gemm_qadic_compress(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CA,
+                                      int64_t ldca, const void *CB, int64_t ldcb, void *CC, int64_t ldcc,
+                                      void *stream) {
+    if (m == 0 || n == 0) return QMM_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24) return launch_qadic_w<float, EPI_PACK>(pl, m, n, k, CA, ldca, CB, ldcb, nullptr, 0, CC, ldcc, s);
+    return launch_qadic_w<double, EPI_PACK>(pl, m, n, k, CA, ldca, CB, ldcb, nullptr, 0, CC, ldcc, s);
 }
 
 qmm_status launch_gemm_redq(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
                             const void *CBr, int64_t ldcbr, uint8_t *C, int64_t ldc, void *stream) {
     if (m == 0 || n == 0) return QMM_OK;
-    if (pl.beta == 24) return launch_redq_w<float>(pl, m, n, k, A, lda, CBr, ldcbr, C, ldc, (hipStream_t)stream);
-    return launch_redq_w<double>(pl, m, n, k, A, lda, CBr, ldcbr, C, ldc, (hipStream_t)stream);
+    const hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24)
+        return launch_redq_w<float, uint8_t, float>(pl, 0, pl.d, m, n, k, A, lda, CBr, ldcbr, C, ldc, s, "gemm_redq");
+    return launch_redq_w<double, uint8_t, double>(pl, 0, pl.d, m, n, k, A, lda, CBr, ldcbr, C, ldc, s, "gemm_redq");
+}
+
+qmm_status launch_gemm_left(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CAl, int64_t ldcal,
+                            const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc, void *stream) {
+    if (m == 0 || n == 0) return QMM_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24)
+        return launch_redq_w<float, float, uint8_t>(pl, pl.d, 0, m, n, k, CAl, ldcal, B, ldb, C, ldc, s, "gemm_left");
+    return launch_redq_w<double, double, uint8_t>(pl, pl.d, 0, m, n, k, CAl, ldcal, B, ldb, C, ldc, s, "gemm_left");
+}
+
+qmm_status launch_gemm_full(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CAl, int64_t ldcal,
+                            const void *CBt, int64_t ldcbt, uint8_t *C, int64_t ldc, void *stream) {
+    if (m == 0 || n == 0) return QMM_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    if (pl.beta == 24)
+        return launch_redq_w<float, float, float>(pl, pl.d, pl.d2, m, n, k, CAl, ldcal, CBt, ldcbt, C, ldc, s, "gemm_full");
+    return launch_redq_w<double, double, double>(pl, pl.d, pl.d2, m, n, k, CAl, ldcal, CBt, ldcbt, C, ldc, s, "gemm_full");
 }
 
 }  // namespace qmm

@@ -41,6 +41,12 @@ bool path_is_fp64(uint32_t path);
 bool path_is_fp32(uint32_t path);
 bool path_is_qadic(uint32_t path);
 bool path_is_redq(uint32_t path);
+bool path_is_left(uint32_t path);
+bool path_is_full(uint32_t path);
+
+// The plan of full compression's right operand: words in base Theta = Q^(d+1)
+// holding d2+1 residues (what qmm_pack_full_right packs with).
+qmm_plan theta_plan(const qmm_plan &pl);
 
 // True when every packed word (p-1)(1 + Q + ... + Q^d) is an exact float of the
 // plan's mantissa and fits the 64-bit integer the pack kernels build it in.
@@ -70,6 +76,16 @@ qmm_status launch_count_nonresidues(uint32_t p, int64_t rows, int64_t cols, cons
 qmm_status launch_gemm_qadic(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                              const void *CA, int64_t ldca, const void *CB, int64_t ldcb,
                              uint8_t *C, int64_t ldc, void *stream);
+// Procedure (1) with ReduceAndCompress: CC = CompressRows(digit d of CA x CB mod p).
+qmm_status launch_gemm_qadic_compress(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CA,
+                                      int64_t ldca, const void *CB, int64_t ldcb, void *CC, int64_t ldcc,
+                                      void *stream);
+// Left compression + REDQ: C = REDQ(CAl x B), blocks of d+1 rows.
+qmm_status launch_gemm_left(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CAl, int64_t ldcal,
+                            const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc, void *stream);
+// Full compression + two-variable REDQ: C = REDQ(CAl x CBt), blocks of (d+1) x (d2+1).
+qmm_status launch_gemm_full(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CAl, int64_t ldcal,
+                            const void *CBt, int64_t ldcbt, uint8_t *C, int64_t ldc, void *stream);
 // Right-compressed GEMM + REDQ (procedure (5)): C = REDQ(A x CBr).
 qmm_status launch_gemm_redq(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const void *CBr, int64_t ldcbr,

@@ -167,6 +167,70 @@ qmm_status choose_redq(uint32_t p, int64_t n, int64_t k, uint32_t beta, uint32_t
     return QMM_OK;
 }
 
+// Left compression (Table 2): the words of section 3 along m, so the same bounds:
+// eq. (3) over the whole k and t(d+1) < beta (eq. (4)); d+1 <= m.
+qmm_status choose_left(uint32_t p, int64_t m, int64_t k, uint32_t beta, uint32_t path, qmm_plan *out) {
+    const qmm_status st = choose_redq(p, m, k, beta, path, out);
+    if (st != QMM_OK) return fail(st, "left compression: k (p-1)^2 must stay below 2^(beta-1)");
+    return QMM_OK;
+}
+
+// Full compression (section 4): eq. (3) fixes t; Theta = Q^(d+1) (eq. (6) with
+// equality) and eq. (7), t (d+1)(d2+1) < beta, bound the two degrees.  Among the
+// admissible pairs the plan takes the one with the fewest packed-word products,
+// ceil(m/(d+1)) ceil(n/(d2+1)) per unit of k; ties go to fewer digits per word,
+// then to the more balanced pair (the paper's d = sqrt(e) - 1 for equal degrees).
+qmm_status choose_full(uint32_t p, int64_t m, int64_t n, int64_t k, uint32_t beta, uint32_t path,
+                       qmm_plan *out) {
+    base_plan(out, p, path);
+    uint32_t t = 1;
+    while (t + 1 <= beta && !eq3_ok(p, k, t)) ++t;
+    if (!eq3_ok(p, k, t) || t > beta - 1)
+        return fail(QMM_EBOUND, "full compression: k (p-1)^2 must stay below 2^(beta-1)");
+    const int64_t D = (int64_t)(beta - 1) / t;  // digits per word, eq. (7)
+    const int64_t mm = m < 1 ? 1 : m, nn = n < 1 ? 1 : n;
+    bool found = false;
+    u128 best_cost = 0;
+    int64_t best_q = 0, best_th = 0;
+    for (int64_t eq_ = 1; eq_ <= D && eq_ <= mm; ++eq_) {
+        for (int64_t eth = 1; eq_ * eth <= D && eth <= nn; ++eth) {
+            const u128 cost = (u128)ceil_div(mm, eq_) * (u128)ceil_div(nn, eth);
+            const int64_t digits = eq_ * eth, bdigits = best_q * best_th;
+            const int64_t skew = eq_ > eth ? eq_ - eth : eth - eq_;
+            const int64_t bskew = best_q > best_th ? best_q - best_th : best_th - best_q;
+            const bool better = !found || cost < best_cost || (cost == best_cost && digits < bdigits) ||
+                                (cost == best_cost && digits == bdigits && skew < bskew);
+            if (better) {
+                found = true;
+                best_cost = cost;
+                best_q = eq_;
+                best_th = eth;
+            }
+        }
+    }
+    out->t = t;
+    out->d = (uint32_t)(best_q - 1);
+    out->d2 = (uint32_t)(best_th - 1);
+    out->beta = beta;
+    out->k_block = k;
+    out->regime = QMM_REGIME_EXACT;
+    return QMM_OK;
+}
+
+// Multiply-adds of packed words of a plan for an m x k by k x n product (Table 2,
+// classical product), plus the planner's per-block extraction cost for blocked
+// k-compressed plans.
+u128 plan_work(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
+    const u128 M = (u128)(m < 1 ? 1 : m), N = (u128)(n < 1 ? 1 : n), K = (u128)(k < 1 ? 1 : k);
+    if (path_is_qadic(pl.path)) {
+        const int64_t blocks = ceil_div(k < 1 ? 1 : k, pl.k_block);
+        return M * N * (u128)(ceil_div(k < 1 ? 1 : k, pl.d + 1) + (blocks - 1) * kBlockCostWords);
+    }
+    if (path_is_redq(pl.path)) return M * (u128)ceil_div((int64_t)N, pl.d + 1) * K;
+    if (path_is_left(pl.path)) return (u128)ceil_div((int64_t)M, pl.d + 1) * N * K;
+    return (u128)ceil_div((int64_t)M, pl.d + 1) * (u128)ceil_div((int64_t)N, pl.d2 + 1) * K;
+}
+
 qmm_status choose_int8(uint32_t p, int64_t k, qmm_plan *out) {
     base_plan(out, p, QMM_PATH_INT8);
     if (p > 256) return fail(QMM_EVALUE, "INT8 path needs p <= 256");
@@ -211,8 +275,23 @@ bool words_exact(const qmm_plan &pl) {
     return word_max(pl.p, pl.t, pl.d) < pow2(pl.beta);
 }
 
-bool path_is_fp64(uint32_t path) { return path == QMM_PATH_FP64_QADIC || path == QMM_PATH_FP64_REDQ; }
-bool path_is_fp32(uint32_t path) { return path == QMM_PATH_FP32_QADIC || path == QMM_PATH_FP32_REDQ; }
+bool path_is_fp64(uint32_t path) {
+    return path == QMM_PATH_FP64_QADIC || path == QMM_PATH_FP64_REDQ || path == QMM_PATH_FP64_LEFT ||
+           path == QMM_PATH_FP64_FULL;
+}
+bool path_is_fp32(uint32_t path) {
+    return path == QMM_PATH_FP32_QADIC || path == QMM_PATH_FP32_REDQ || path == QMM_PATH_FP32_LEFT ||
+           path == QMM_PATH_FP32_FULL;
+}
+bool path_is_left(uint32_t path) { return path == QMM_PATH_FP64_LEFT || path == QMM_PATH_FP32_LEFT; }
+bool path_is_full(uint32_t path) { return path == QMM_PATH_FP64_FULL || path == QMM_PATH_FP32_FULL; }
+qmm_plan theta_plan(const qmm_plan &pl) {
+    qmm_plan q = pl;
+    q.t = pl.t * (pl.d + 1);
+    q.d = pl.d2;
+    q.d2 = 0;
+    return q;
+}
 bool path_is_qadic(uint32_t path) { return path == QMM_PATH_FP64_QADIC || path == QMM_PATH_FP32_QADIC; }
 bool path_is_redq(uint32_t path) { return path == QMM_PATH_FP64_REDQ || path == QMM_PATH_FP32_REDQ; }
 int word_bytes(const qmm_plan &pl) { return pl.beta == 24 ? 4 : 8; }
@@ -239,7 +318,7 @@ extern "C" qmm_status qmm_choose_Qd(uint32_t p, int64_t m, int64_t n, int64_t k,
         const bool fp4 = p <= 8 && (double)m * (double)n * (double)kk >= (double)(1ll << 28);
         pth = fp4 ? QMM_PATH_FP4 : (p <= 256 ? QMM_PATH_INT8 : QMM_PATH_FP64_QADIC);
     }
-    if (pth > QMM_PATH_FP4) return fail(QMM_EINVAL, "unknown path");
+    if (pth > QMM_PATH_FP32_FULL) return fail(QMM_EINVAL, "unknown path");
     if (beta == 0) beta = default_beta(pth);
     if (pth != QMM_PATH_INT8 && pth != QMM_PATH_FP4 && ((path_is_fp64(pth) && beta != 53) || (path_is_fp32(pth) && beta != 24)) &&
         !(flags & QMM_BOUND_PAPER))
@@ -261,7 +340,39 @@ extern "C" qmm_status qmm_choose_Qd(uint32_t p, int64_t m, int64_t n, int64_t k,
     }
     if (pth == QMM_PATH_INT8) return choose_int8(p, kk, out);
     if (pth == QMM_PATH_FP4) return choose_fp4(p, kk, out);
+    if (flags & QMM_PLAN_ANY_COMPRESSION) {
+        // The four compressions of this mantissa; the fewest packed-word products wins
+        // (Table 2: compressing the largest dimension, up to the rounding of each count).
+        const bool fp64 = path_is_fp64(pth);
+        const uint32_t cands[4] = {fp64 ? (uint32_t)QMM_PATH_FP64_QADIC : (uint32_t)QMM_PATH_FP32_QADIC,
+                                   fp64 ? (uint32_t)QMM_PATH_FP64_REDQ : (uint32_t)QMM_PATH_FP32_REDQ,
+                                   fp64 ? (uint32_t)QMM_PATH_FP64_LEFT : (uint32_t)QMM_PATH_FP32_LEFT,
+                                   fp64 ? (uint32_t)QMM_PATH_FP64_FULL : (uint32_t)QMM_PATH_FP32_FULL};
+        bool found = false;
+        u128 best_work = 0;
+        qmm_plan best{};
+        for (uint32_t c : cands) {
+            qmm_plan pl;
+            qmm_status st;
+            if (path_is_qadic(c)) st = choose_qadic(p, kk, beta, c, flags & ~QMM_PLAN_ANY_COMPRESSION, &pl);
+            else if (path_is_redq(c)) st = choose_redq(p, n, kk, beta, c, &pl);
+            else if (path_is_left(c)) st = choose_left(p, m, kk, beta, c, &pl);
+            else st = choose_full(p, m, n, kk, beta, c, &pl);
+            if (st != QMM_OK) continue;
+            const u128 w = plan_work(pl, m, n, kk);
+            if (!found || w < best_work) {
+                found = true;
+                best_work = w;
+                best = pl;
+            }
+        }
+        if (!found) return fail(QMM_EBOUND, "no compression satisfies the bounds for this p, k and mantissa");
+        *out = best;
+        return QMM_OK;
+    }
     if (path_is_redq(pth)) return choose_redq(p, n, kk, beta, pth, out);
+    if (path_is_left(pth)) return choose_left(p, m, kk, beta, pth, out);
+    if (path_is_full(pth)) return choose_full(p, m, n, kk, beta, pth, out);
     return choose_qadic(p, kk, beta, pth, flags, out);
 }
 
@@ -270,6 +381,7 @@ extern "C" qmm_status qmm_validate_plan(const qmm_plan *pl, int64_t m, int64_t n
     if (m < 0 || n < 0 || k < 0) return fail(QMM_EINVAL, "negative size");
     if (pl->p < 2) return fail(QMM_EINVAL, "p must be >= 2");
     const int64_t kk = k < 1 ? 1 : k;
+    if (pl->d2 != 0 && !path_is_full(pl->path)) return fail(QMM_EINVAL, "d2 must be 0 off the FULL paths");
     switch (pl->path) {
     case QMM_PATH_INT8: {
         if (pl->p > 256) return fail(QMM_EVALUE, "INT8 path needs p <= 256");
@@ -326,6 +438,28 @@ extern "C" qmm_status qmm_validate_plan(const qmm_plan *pl, int64_t m, int64_t n
         if ((uint64_t)pl->t * (pl->d + 1) >= beta) return fail(QMM_EBOUND, "eq. (4) violated: Q^(d+1) >= 2^beta");
         if (pl->k_block < kk) return fail(QMM_EUNSUPPORTED, "the REDQ path does not split k");
         if (pl->regime != QMM_REGIME_EXACT) return fail(QMM_EBOUND, "REDQ plans are exact");
+        return QMM_OK;
+    }
+    case QMM_PATH_FP64_LEFT:
+    case QMM_PATH_FP32_LEFT: {
+        const uint32_t beta = path_is_fp64(pl->path) ? 53 : 24;
+        if (pl->beta != beta) return fail(QMM_EBOUND, "plan beta does not match the path");
+        if (pl->t < 1 || !eq3_ok(pl->p, kk, pl->t)) return fail(QMM_EBOUND, "eq. (3) violated: k (p-1)^2 >= Q");
+        if ((uint64_t)pl->t * (pl->d + 1) >= beta) return fail(QMM_EBOUND, "eq. (4) violated: Q^(d+1) >= 2^beta");
+        if (pl->k_block < kk) return fail(QMM_EUNSUPPORTED, "left compression does not split k");
+        if (pl->regime != QMM_REGIME_EXACT) return fail(QMM_EBOUND, "left-compression plans are exact");
+        return QMM_OK;
+    }
+    case QMM_PATH_FP64_FULL:
+    case QMM_PATH_FP32_FULL: {
+        const uint32_t beta = path_is_fp64(pl->path) ? 53 : 24;
+        if (pl->beta != beta) return fail(QMM_EBOUND, "plan beta does not match the path");
+        if (pl->t < 1 || !eq3_ok(pl->p, kk, pl->t)) return fail(QMM_EBOUND, "eq. (3) violated: k (p-1)^2 >= Q");
+        if (pl->d > 63 || pl->d2 > 63 ||
+            (uint64_t)pl->t * (pl->d + 1) * (pl->d2 + 1) >= beta)
+            return fail(QMM_EBOUND, "eq. (7) violated: Q^((d+1)(d2+1)) >= 2^beta");
+        if (pl->k_block < kk) return fail(QMM_EUNSUPPORTED, "full compression does not split k");
+        if (pl->regime != QMM_REGIME_EXACT) return fail(QMM_EBOUND, "full-compression plans are exact");
         return QMM_OK;
     }
     default:

@@ -17,13 +17,15 @@ LIB_PATH = os.path.join(HERE, "libqmm.so")
 OK, EINVAL, EBOUND, EVALUE, ENOSPACE, EDEVICE, EUNSUPPORTED = range(7)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EBOUND", 3: "EVALUE", 4: "ENOSPACE", 5: "EDEVICE", 6: "EUNSUPPORTED"}
 # qmm_path
-PATH_AUTO, PATH_FP64_QADIC, PATH_FP64_REDQ, PATH_FP32_QADIC, PATH_FP32_REDQ, PATH_INT8, PATH_FP4 = range(7)
-PATH_NAMES = {0: "auto", 1: "fp64_qadic", 2: "fp64_redq", 3: "fp32_qadic", 4: "fp32_redq", 5: "int8", 6: "fp4"}
+(PATH_AUTO, PATH_FP64_QADIC, PATH_FP64_REDQ, PATH_FP32_QADIC, PATH_FP32_REDQ, PATH_INT8, PATH_FP4,
+ PATH_FP64_LEFT, PATH_FP32_LEFT, PATH_FP64_FULL, PATH_FP32_FULL) = range(11)
+PATH_NAMES = {0: "auto", 1: "fp64_qadic", 2: "fp64_redq", 3: "fp32_qadic", 4: "fp32_redq", 5: "int8", 6: "fp4",
+              7: "fp64_left", 8: "fp32_left", 9: "fp64_full", 10: "fp32_full"}
 # qmm_regime
 REGIME_EXACT, REGIME_OFFSET, REGIME_PAPER, REGIME_INT = range(4)
 REGIME_NAMES = {0: "exact", 1: "offset", 2: "paper", 3: "int"}
 # flags
-BOUND_PROVEN, BOUND_PAPER, PLAN_UNBLOCKED, BOUND_G4, BOUND_EQ4 = 0, 1, 2, 4, 8
+BOUND_PROVEN, BOUND_PAPER, PLAN_UNBLOCKED, BOUND_G4, BOUND_EQ4, PLAN_ANY_COMPRESSION = 0, 1, 2, 4, 8, 16
 BATCH_FORCE_FP64 = 1
 BATCH_INT8_ONLY = 2
 BATCH_SHAPE_64x64, BATCH_SHAPE_32x128, BATCH_SHAPE_128x32, BATCH_SHAPE_128x128 = 0x100, 0x200, 0x300, 0x400
@@ -39,13 +41,16 @@ EXPORTS = [
     "qmm_last_error", "qmm_version", "qmm_pack_centred_cols", "qmm_gemm_centred",
     "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs", "qmm_count_nonresidues",
     "qmm_pack_fp4_rows", "qmm_pack_fp4_cols", "qmm_gemm_fp4", "qmm_pack_fp4",
+    "qmm_gemm_packed_compress", "qmm_pack_left", "qmm_pack_full_right", "qmm_gemm_left_packed",
+    "qmm_gemm_full_packed",
 ]
 
 
 class Plan(ctypes.Structure):
     _fields_ = [("p", ctypes.c_uint32), ("t", ctypes.c_uint32), ("d", ctypes.c_uint32),
                 ("beta", ctypes.c_uint32), ("k_block", ctypes.c_int64), ("path", ctypes.c_uint32),
-                ("regime", ctypes.c_uint32), ("g", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
+                ("regime", ctypes.c_uint32), ("g", ctypes.c_uint32), ("tile", ctypes.c_uint32),
+                ("d2", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -53,7 +58,7 @@ class Plan(ctypes.Structure):
     def __repr__(self):
         return (f"Plan(p={self.p}, t={self.t}, d={self.d}, beta={self.beta}, k_block={self.k_block}, "
                 f"path={PATH_NAMES.get(self.path, self.path)}, regime={REGIME_NAMES.get(self.regime, self.regime)}, "
-                f"g={self.g}, tile={self.tile})")
+                f"g={self.g}, tile={self.tile}, d2={self.d2})")
 
 
 class Problem(ctypes.Structure):
@@ -106,6 +111,11 @@ def lib():
             "qmm_pack_fp4_cols": [P, i64, i64, vp, i64, vp, i64, vp],
             "qmm_gemm_fp4": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
             "qmm_pack_fp4": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_gemm_packed_compress": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_pack_left": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_pack_full_right": [P, i64, i64, vp, i64, vp, i64, vp],
+            "qmm_gemm_left_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_gemm_full_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -301,6 +311,65 @@ def gemm_packed(plan, k, CA, CB, C=None, stream=None):
         C = torch.empty((m, n), dtype=torch.uint8, device=CA.device)
     _check(lib().qmm_gemm_packed(ctypes.byref(plan), m, n, k, _ptr(CA), _ld(CA), _ptr(CB), _ld(CB), _ptr(C), _ld(C),
                                  _stream(stream)), "qmm_gemm_packed")
+    return C
+
+
+def gemm_packed_compress(plan, k, CA, CB, CC=None, stream=None):
+    """Procedure (1) with ReduceAndCompress: CC = CompressRows(digit d of CA x CB mod p),
+    m x ceil(n/(d+1)) words, usable as the CA of a next product with k = n."""
+    import torch
+    m, n = CA.shape[0], CB.shape[1]
+    if CC is None:
+        CC = torch.empty((m, -(-n // (plan.d + 1))), dtype=word_dtype(plan), device=CA.device)
+    _check(lib().qmm_gemm_packed_compress(ctypes.byref(plan), m, n, k, _ptr(CA), _ld(CA), _ptr(CB), _ld(CB),
+                                          _ptr(CC), _ld(CC), _stream(stream)), "qmm_gemm_packed_compress")
+    return CC
+
+
+def pack_left(plan, A, CAl=None, stream=None):
+    """Left operand packed along m: CAl[I][l] = sum_i A[I(d+1)+i][l] Q^i (LEFT and FULL plans)."""
+    import torch
+    _u8(A, "A")
+    m, k = A.shape
+    if CAl is None:
+        CAl = torch.empty((-(-m // (plan.d + 1)), k), dtype=word_dtype(plan), device=A.device)
+    _check(lib().qmm_pack_left(ctypes.byref(plan), m, k, _ptr(A), _ld(A), _ptr(CAl), _ld(CAl), _stream(stream)),
+           "qmm_pack_left")
+    return CAl
+
+
+def pack_full_right(plan, B, CBt=None, stream=None):
+    """Right operand of full compression, packed along n in Theta = Q^(d+1) (FULL plans)."""
+    import torch
+    _u8(B, "B")
+    k, n = B.shape
+    if CBt is None:
+        CBt = torch.empty((k, -(-n // (plan.d2 + 1))), dtype=word_dtype(plan), device=B.device)
+    _check(lib().qmm_pack_full_right(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(CBt), _ld(CBt),
+                                     _stream(stream)), "qmm_pack_full_right")
+    return CBt
+
+
+def gemm_left_packed(plan, CAl, B, m, C=None, stream=None):
+    """Left compression: C = REDQ(CAl x B), d+1 rows of C per word."""
+    import torch
+    _u8(B, "B")
+    k, n = B.shape
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=B.device)
+    _check(lib().qmm_gemm_left_packed(ctypes.byref(plan), m, n, k, _ptr(CAl), _ld(CAl), _ptr(B), _ld(B), _ptr(C),
+                                      _ld(C), _stream(stream)), "qmm_gemm_left_packed")
+    return C
+
+
+def gemm_full_packed(plan, CAl, CBt, m, n, C=None, stream=None):
+    """Full compression: C = two-variable REDQ of CAl x CBt."""
+    import torch
+    k = CAl.shape[1]
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.uint8, device=CAl.device)
+    _check(lib().qmm_gemm_full_packed(ctypes.byref(plan), m, n, k, _ptr(CAl), _ld(CAl), _ptr(CBt), _ld(CBt),
+                                      _ptr(C), _ld(C), _stream(stream)), "qmm_gemm_full_packed")
     return C
 
 

@@ -13,6 +13,10 @@ names strongly regular graphs as the motivating use; it ships no data):
   batched 2000 products, p in {2,3,5,7,11,13,31,101}, m,n,k uniform in [16, 512], seed 4
   graph   GF(3), A x A for a random symmetric 0/1 matrix, n = 16384, zero diagonal,
           edge density 0.5, seed 5
+  thin    GF(3),   8192 x 256 times 256 x 8192 (a short inner dimension, where
+          packing the outer dimensions pays), residues uniform in [0, 2], seed 6
+  chain   GF(3), A^3 for a random symmetric 0/1 matrix, n = 4096, edge density
+          0.5, seed 7 (a power of a graph's adjacency matrix)
 """
 from __future__ import annotations
 
@@ -25,6 +29,8 @@ WORKLOADS = {
     "square": dict(p=7, m=4096, n=4096, k=4096, seed=2),
     "large": dict(p=101, m=8192, n=8192, k=8192, seed=3),
     "graph": dict(p=3, m=16384, n=16384, k=16384, seed=5),
+    "thin": dict(p=3, m=8192, n=8192, k=256, seed=6),
+    "chain": dict(p=3, m=4096, n=4096, k=4096, seed=7),
 }
 
 

@@ -33,8 +33,8 @@ def test_version_and_error_string():
 
 
 def test_plan_struct_layout():
-    assert ctypes.sizeof(qmm.Plan) == 40
-    assert qmm.Plan.k_block.offset == 16 and qmm.Plan.path.offset == 24
+    assert ctypes.sizeof(qmm.Plan) == 48
+    assert qmm.Plan.k_block.offset == 16 and qmm.Plan.path.offset == 24 and qmm.Plan.d2.offset == 40
 
 
 def test_argument_checks_reject_before_any_device_work():
@@ -148,3 +148,58 @@ def test_fp4_entry_points_check_arguments_before_device_work():
     bad.p = 11
     assert L.qmm_gemm_fp4(ctypes.byref(bad), 4, 4, 256, fake, 128, fake, 128, fake, 4, None) == qmm.EVALUE
     assert qmm.fp4_ld(4096) % 128 == 0 and 2 * qmm.fp4_ld(4096) >= 4096
+
+
+def test_plan_struct_matches_the_header():
+    # compile the header with the host compiler and compare size and offsets
+    import os, subprocess, tempfile
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"qmm.h\"\nint main(void){printf(\"%zu %zu %zu %zu\\n\","
+           "sizeof(qmm_plan), offsetof(qmm_plan, k_block), offsetof(qmm_plan, path), offsetof(qmm_plan, d2));"
+           "return 0;}\n")
+    with tempfile.TemporaryDirectory() as tmp:
+        c, exe = os.path.join(tmp, "l.c"), os.path.join(tmp, "l")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(root, "include"), c, "-o", exe])
+        got = [int(x) for x in subprocess.check_output([exe]).split()]
+    assert got == [ctypes.sizeof(qmm.Plan), qmm.Plan.k_block.offset, qmm.Plan.path.offset, qmm.Plan.d2.offset]
+
+
+def test_left_full_and_compress_entry_points_check_arguments_before_device_work():
+    L = qmm.lib()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below is refused on the host
+    left = qmm.choose_Qd(3, 64, 64, 64, path=qmm.PATH_FP64_LEFT)
+    full = qmm.choose_Qd(3, 64, 64, 64, path=qmm.PATH_FP64_FULL)
+    qad = qmm.choose_Qd(3, 64, 64, 64, path=qmm.PATH_FP64_QADIC)
+    assert full.d2 >= 1 and left.d2 == 0 and qad.d2 == 0
+    # null operands with non-zero sizes
+    assert L.qmm_pack_left(ctypes.byref(left), 4, 4, null, 4, fake, 4, null) == qmm.EINVAL
+    assert L.qmm_pack_full_right(ctypes.byref(full), 4, 4, fake, 4, null, 4, null) == qmm.EINVAL
+    assert L.qmm_gemm_left_packed(ctypes.byref(left), 4, 4, 4, null, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    assert L.qmm_gemm_full_packed(ctypes.byref(full), 4, 4, 4, fake, 4, null, 4, fake, 4, null) == qmm.EINVAL
+    assert L.qmm_gemm_packed_compress(ctypes.byref(qad), 4, 4, 4, fake, 4, fake, 4, null, 4, null) == qmm.EINVAL
+    # wrong path for the call
+    assert L.qmm_pack_full_right(ctypes.byref(left), 4, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    assert L.qmm_pack_left(ctypes.byref(qad), 4, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    assert L.qmm_gemm_left_packed(ctypes.byref(full), 4, 4, 4, fake, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    assert L.qmm_gemm_full_packed(ctypes.byref(left), 4, 4, 4, fake, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    assert L.qmm_gemm_packed_compress(ctypes.byref(left), 4, 4, 4, fake, 4, fake, 4, fake, 4, null) == qmm.EINVAL
+    # short leading dimensions
+    nw = -(-64 // (full.d2 + 1))
+    assert L.qmm_gemm_full_packed(ctypes.byref(full), 64, 64, 64, fake, 63, fake, nw, fake, 64, null) == qmm.EINVAL
+    assert L.qmm_gemm_full_packed(ctypes.byref(full), 64, 64, 64, fake, 64, fake, nw - 1, fake, 64, null) == qmm.EINVAL
+    assert L.qmm_gemm_packed_compress(ctypes.byref(qad), 64, 64, 64, fake, 64, fake, 64, fake,
+                                      -(-64 // (qad.d + 1)) - 1, null) == qmm.EINVAL
+    # plans that break eq. (7), eq. (3) or carry a d2 off the FULL path are refused
+    bad = qmm.Plan.from_buffer_copy(full)
+    bad.d2 = 60
+    assert L.qmm_gemm_full_packed(ctypes.byref(bad), 4, 4, 4, fake, 4, fake, 4, fake, 4, null) == qmm.EBOUND
+    bad = qmm.Plan.from_buffer_copy(full)
+    bad.t = 3                      # 64 (p-1)^2 = 256 >= 2^3
+    assert qmm.validate_plan(bad, 64, 64, 64) == qmm.EBOUND
+    bad = qmm.Plan.from_buffer_copy(left)
+    bad.d2 = 1
+    assert qmm.validate_plan(bad, 64, 64, 64) == qmm.EINVAL
+    # ReduceAndCompress of an empty product is refused, not written
+    assert L.qmm_gemm_packed_compress(ctypes.byref(qad), 4, 4, 0, fake, 4, fake, 4, fake, 4, null) == qmm.EUNSUPPORTED

@@ -165,3 +165,86 @@ def test_int8_blocks():
         assert pl.k_block * h * h + (p - 1) <= 2 ** 31 - 1
         if pl.k_block < k:
             assert pl.k_block % 128 == 0 and (pl.k_block + 128) * h * h + (p - 1) > 2 ** 31 - 1
+
+
+# --- left and full compression, and the choice of the compressed dimension ----
+@pytest.mark.parametrize("beta,path", [(53, qmm.PATH_FP64_LEFT), (24, qmm.PATH_FP32_LEFT)])
+@pytest.mark.parametrize("p,m,k", [(3, 64, 64), (3, 5, 64), (7, 4096, 4096), (101, 100, 1000), (2, 1, 7),
+                                   (13, 9, 1)])
+def test_left_plans(beta, path, p, m, k):
+    st, pl = qmm.try_choose_Qd(p, m, 16, k, path=path)
+    t = bounds.smallest_t(p, k)
+    if t >= beta:
+        assert st == qmm.EBOUND
+        return
+    assert st == qmm.OK and pl.path == path and pl.beta == beta and pl.d2 == 0
+    assert pl.t == t and bounds.left_ok(p, k, pl.t, pl.d, beta)
+    # the largest d the bounds allow, unless m itself is smaller
+    assert pl.d + 1 == m or not bounds.left_ok(p, k, pl.t, pl.d + 1, beta)
+    assert qmm.validate_plan(pl, m, 16, k) == qmm.OK
+
+
+def best_full_pair(p, m, n, k, t, beta):
+    best = None
+    for eq_ in range(1, min(m, beta) + 1):
+        for eth in range(1, min(n, beta) + 1):
+            if not bounds.full_ok(p, k, t, eq_ - 1, eth - 1, beta):
+                continue
+            key = (bounds.table2_word_products("full", m, n, k, eq_ - 1, eth - 1), eq_ * eth, abs(eq_ - eth))
+            if best is None or key < best[0]:
+                best = (key, (eq_ - 1, eth - 1))
+    return best
+
+
+@pytest.mark.parametrize("beta,path", [(53, qmm.PATH_FP64_FULL), (24, qmm.PATH_FP32_FULL)])
+@pytest.mark.parametrize("p,m,n,k", [(3, 64, 64, 64), (2, 1000, 1000, 5), (3, 6, 6, 4), (7, 300, 7, 9),
+                                     (5, 1, 1, 3), (3, 8192, 8192, 256), (101, 64, 64, 64)])
+def test_full_plans_are_valid_and_optimal(beta, path, p, m, n, k):
+    st, pl = qmm.try_choose_Qd(p, m, n, k, path=path)
+    t = bounds.smallest_t(p, k)
+    if t >= beta:
+        assert st == qmm.EBOUND
+        return
+    assert st == qmm.OK and pl.t == t
+    assert bounds.full_ok(p, k, pl.t, pl.d, pl.d2, beta)
+    key = (bounds.table2_word_products("full", m, n, k, pl.d, pl.d2), (pl.d + 1) * (pl.d2 + 1), abs(pl.d - pl.d2))
+    assert key == best_full_pair(p, m, n, k, t, beta)[0]
+    assert qmm.validate_plan(pl, m, n, k) == qmm.OK
+
+
+def table2_count(pl, m, n, k):
+    algo = {qmm.PATH_FP64_QADIC: "qadic", qmm.PATH_FP64_REDQ: "right", qmm.PATH_FP64_LEFT: "left",
+            qmm.PATH_FP64_FULL: "full"}[pl.path]
+    c = bounds.table2_word_products(algo, m, n, k, pl.d, pl.d2)
+    if algo == "qadic":
+        c += m * n * (-(-k // pl.k_block) - 1) * BLOCK_COST
+    return c
+
+
+@pytest.mark.parametrize("p,m,n,k,want", [
+    (3, 8, 8, 4096, qmm.PATH_FP64_QADIC),     # k largest: procedure (2)
+    (3, 8, 4096, 2, qmm.PATH_FP64_REDQ),      # n largest: procedure (5)
+    (3, 4096, 8, 2, qmm.PATH_FP64_LEFT),      # m largest: left compression
+    (3, 8, 4096, 8, qmm.PATH_FP64_QADIC),     # all of k fits one word: a tie, which goes to k
+    (3, 6, 6, 4, qmm.PATH_FP64_FULL),         # full compression wins on the rounding of m/2, n/2
+    (7, 512, 512, 512, None), (101, 200, 3000, 100, None), (2, 33, 65, 129, None), (3, 4096, 4096, 8, None)])
+def test_any_compression_picks_the_fewest_word_products(p, m, n, k, want):
+    pl = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_FP64_QADIC, flags=qmm.PLAN_ANY_COMPRESSION)
+    if want is not None:
+        assert pl.path == want
+    assert qmm.validate_plan(pl, m, n, k) == qmm.OK
+    got = table2_count(pl, m, n, k)
+    # every alternative, planned by the library for its own path
+    for path in (qmm.PATH_FP64_QADIC, qmm.PATH_FP64_REDQ, qmm.PATH_FP64_LEFT, qmm.PATH_FP64_FULL):
+        st, alt = qmm.try_choose_Qd(p, m, n, k, path=path)
+        if st == qmm.OK:
+            assert got <= table2_count(alt, m, n, k)
+    # and the oracle's own degrees for the three exact compressions
+    t = bounds.smallest_t(p, k)
+    for algo, dim in (("right", n), ("left", m)):
+        d = max(d for d in range(0, 53) if bounds.redq_ok(p, k, t, d, 53) or d == 0)
+        d = min(d, dim - 1)
+        assert got <= bounds.table2_word_products(algo, m, n, k, d)
+    bf = best_full_pair(p, m, n, k, t, 53)
+    if bf is not None:
+        assert got <= bf[0][0]
