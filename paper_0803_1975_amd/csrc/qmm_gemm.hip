@@ -2,8 +2,8 @@
 //
 //   EPI_QADIC  procedure (1)/(2): T = start + CA x CB over packed words (CA rows
 //              reversed, CB columns forward), then digit d of every word mod p.
-//   EPI_REDQ   words that hold a (d_q+1) x (d_theta+1) block of C, split by one
-//              REDQ (one division by p) into all their coefficients mod p:
+//   EPI_REDQ   words that hold a (d_q+1) x (d_theta+1) block of C, split by
+//              REDQ into all their coefficients mod p:
 //              procedure (5) (A residues times the row-compressed CBr, d_q = 0),
 //              left compression (Table 2: CAl packed along m times B residues,
 //              d_theta = 0) and full compression (section 4: CAl times CBt packed
@@ -12,6 +12,10 @@
 //   EPI_PACK   procedure (1) with ReduceAndCompress: as EPI_QADIC, then the
 //              reduced tile goes through LDS and leaves as CompressRows words
 //              (reversed, d+1 columns per word), so products can be chained.
+//              Tiles stay 128 columns wide when d+1 residues fit the bytes of a
+//              word: a word cut by a tile edge gets its residues as bytes in its
+//              own slot from both tiles, and a small pass packs those slots
+//              afterwards (no tile count grows by rounding to whole words).
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup, 2 x 2 wavefronts of
 // 64 x 64 each, i.e. 4 x 4 MFMA 16x16x4 tiles per wavefront.  K advances 16
@@ -29,6 +33,7 @@
 // and restart the accumulator at M.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "qmm_device.h"
@@ -75,7 +80,8 @@ struct GemmArgs {
     uint32_t dq, dth;        // EPI_REDQ: a word holds C's (dq+1) x (dth+1) block
     int32_t tiles_m, tiles_n;
     int32_t col_step;        // output columns per tile: BN, or whole words of BN (EPI_PACK)
-    int32_t tile_words;      // EPI_PACK: words per tile row
+    int32_t tile_words;      // EPI_PACK, whole-word tiles: words per tile row
+    int32_t pack_slots;      // EPI_PACK: 128-column tiles, cut words left as bytes in their slots
     void *CW;                // EPI_PACK: compressed output, words
     int64_t ldcw, n_words;
     int32_t kb_tiles;        // K stages per block (blocked Q-adic plans)
@@ -83,8 +89,8 @@ struct GemmArgs {
     uint64_t qmask;
     double invp;
     double start;            // accumulator start value (M or 0)
-    uint32_t qmodp;          // Q mod p (REDQ)
     uint64_t magic;          // mod_u32 multiplier for p
+    uint32_t m32;            // mod_u32_m32 multiplier for p, floor(2^32 / p)
     double inv_qd, inv_q, q; // 2^-td, 2^-t, 2^t (exact-regime digit)
     int32_t small_digit;     // t <= 31: digits fit 32 bits
 };
@@ -243,16 +249,46 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
                     sC[rl * LDS_C + cl] = in ? (uint8_t)qadic_value(mi, ni, r) : (uint8_t)0;
                 }
         __syncthreads();
-        const int e = (int)g.d + 1, tw = g.tile_words;
+        // Words overlapping this tile's columns [col0, col0 + col_step).  A word inside
+        // them is packed (Horner in the word's own type: every partial value is an
+        // integer below the word bound, so exact) and stored; a word cut by an edge
+        // (only with 128-column tiles) gets the residues of its columns below n as
+        // bytes s of its slot, and the slot pass packs it.  Each thread walks the
+        // flattened (row, word) list NT entries at a time without dividing.
+        const int e = (int)g.d + 1;
+        const int64_t cend = col0 + g.col_step;
+        const int64_t L0 = col0 / e;
+        const int64_t L1 = min((cend - 1) / e, g.n_words - 1);
+        const int nwt = (int)(L1 - L0 + 1);
+        const W q = (W)g.q;
         W *CW = (W *)g.CW;
-        for (int idx = tid; idx < BM * tw; idx += NT) {
-            const int rl = idx / tw, L = idx - rl * tw;
-            const int64_t row = row0 + rl, wc = (int64_t)tn * tw + L;
-            if (row >= g.m || wc >= g.n_words) continue;
-            const uint8_t *src = sC + rl * LDS_C + L * e;
-            uint64_t w = 0;
-            for (int s = 0; s < e; ++s) w = (w << g.t) | src[s];
-            CW[row * g.ldcw + wc] = word_from_u64<W>(w);
+        if (nwt > 0) {
+            const int step_r = NT / nwt, step_l = NT - step_r * nwt;
+            int rl = tid / nwt, li = tid - rl * nwt;
+            for (; rl < BM; rl += step_r) {
+                const int64_t row = row0 + rl;
+                if (row < g.m) {
+                    const int64_t L = L0 + li, w0 = L * e;
+                    const uint8_t *srow = sC + rl * LDS_C;
+                    if (w0 >= col0 && w0 + e <= cend) {
+                        const int c0 = (int)(w0 - col0);
+                        W w = (W)0;
+                        for (int s = 0; s < e; ++s) w = w * q + (W)srow[c0 + s];
+                        CW[row * g.ldcw + L] = w;
+                    } else {
+                        uint8_t *slot = (uint8_t *)(CW + row * g.ldcw + L);
+                        for (int s = 0; s < e; ++s) {
+                            const int64_t c = w0 + s;
+                            if (c >= col0 && c < cend && c < g.n) slot[s] = srow[c - col0];
+                        }
+                    }
+                }
+                li += step_l;
+                if (li >= nwt) {
+                    li -= nwt;
+                    ++rl;
+                }
+            }
         }
         return;
     }
@@ -268,26 +304,50 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
                 if constexpr (EPI == EPI_QADIC) {
                     g.C[row * g.ldc + col] = (uint8_t)qadic_value(mi, ni, r);
                 } else {
-                    // REDQ of the exact word r = sum_q c_q Q^q: with s = floor(r/p),
-                    // mu_q = (r >> tq) - p (s >> tq) = floor(r / Q^q) mod p, and
-                    // c_q = mu_q - Q mu_(q+1) (mod p).  Coefficient q = i + j (dq+1) is
-                    // entry (i, j) of the word's block of C.
+                    // The exact word r = sum_q c_q Q^q holds every coefficient c_q < Q
+                    // (eq. (3)) as the bit field [tq, tq + t): REDQ's output, c_q mod p,
+                    // is that field reduced with a 32-bit multiply-high (t <= 32) or the
+                    // double reciprocal.  Coefficient q = i + j (dq+1) is entry (i, j) of
+                    // the word's block of C.
                     const uint64_t w = u64_from_word(acc[mi][ni][r]);
-                    const uint64_t s = div_u64(w, g.p, g.invp);
-                    uint32_t mu_next = 0;
-                    for (int32_t j = (int32_t)g.dth; j >= 0; --j) {
+                    for (int32_t j = 0; j <= (int32_t)g.dth; ++j) {
                         const int64_t co = col * (g.dth + 1) + j;
-                        for (int32_t i = (int32_t)g.dq; i >= 0; --i) {
-                            const uint32_t sh = g.t * (uint32_t)(i + j * (int32_t)(g.dq + 1));
-                            const uint32_t mu = (uint32_t)((w >> sh) - (uint64_t)g.p * (s >> sh));
-                            const uint64_t v = (uint64_t)mu + (uint64_t)g.qmodp * g.p - (uint64_t)g.qmodp * mu_next;
+                        if (co >= g.n_out) break;
+                        for (int32_t i = 0; i <= (int32_t)g.dq; ++i) {
                             const int64_t ro = row * (g.dq + 1) + i;
-                            if (ro < g.m_out && co < g.n_out) g.C[ro * g.ldc + co] = (uint8_t)mod_u64(v, g.p, g.invp);
-                            mu_next = mu;
+                            if (ro >= g.m_out) break;
+                            const uint32_t sh = g.t * (uint32_t)(i + j * (int32_t)(g.dq + 1));
+                            const uint64_t c = (w >> sh) & g.qmask;
+                            const uint32_t v = g.small_digit ? mod_u32_m32((uint32_t)c, g.p, g.m32)
+                                                             : mod_u64(c, g.p, g.invp);
+                            g.C[ro * g.ldc + co] = (uint8_t)v;
                         }
                     }
                 }
             }
+}
+
+// The words of a compressed output that a tile edge cuts (column c = 128 b, for
+// b = 1 .. tiles_n, inside word L = (c - 1) / (d+1) when c is not a multiple of
+// d+1): both tiles left the word's residues as bytes in its slot; pack them.
+// Residues of columns at or past n are the zero padding, whatever the slot holds.
+template <typename W>
+__global__ __launch_bounds__(64) void pack_cut_words_kernel(int64_t m, int32_t tiles_n, int64_t n, int64_t n_words,
+                                                              uint32_t e, uint32_t t, W *CW, int64_t ldcw) {
+    const int32_t b = (int32_t)(blockIdx.x * 64 + threadIdx.x) + 1;
+    if (b > tiles_n) return;
+    const int64_t c = (int64_t)b * BN;
+    if (c % e == 0) return;
+    const int64_t L = (c - 1) / e;
+    if (L >= n_words) return;
+    for (int64_t row = blockIdx.y; row < m; row += gridDim.y) {
+        W *slot = CW + row * ldcw + L;
+        uint8_t bytes[sizeof(W)];
+        __builtin_memcpy(bytes, slot, sizeof(W));
+        uint64_t w = 0;
+        for (uint32_t s = 0; s < e; ++s) w = (w << t) | (L * e + s < n ? (uint64_t)bytes[s] : 0ull);
+        *slot = word_from_u64<W>(w);
+    }
 }
 
 qmm_status check_launch(const char *what) {
@@ -305,7 +365,8 @@ void common_args(GemmArgs &g, const qmm_plan &pl) {
     g.qmask = (1ull << pl.t) - 1;
     g.invp = 1.0 / (double)pl.p;
     g.magic = mod_magic(pl.p);
-    g.qmodp = (uint32_t)((1ull << pl.t) % pl.p);
+    g.m32 = (uint32_t)((1ull << 32) / pl.p);
+    g.small_digit = pl.t <= 31;
     g.col_step = BN;
 }
 
@@ -342,13 +403,16 @@ qmm_status launch_qadic_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     g.small_digit = pl.t <= 31;
     if (blocked && pl.t > 31) return fail(QMM_EUNSUPPORTED, "blocked plans need t <= 31");
     if (EPI == EPI_PACK) {
-        // A tile covers whole words: the largest multiple of d+1 columns in BN.
-        g.tile_words = BN / (int32_t)(pl.d + 1);
-        if (g.tile_words < 1) return fail(QMM_EUNSUPPORTED, "compressed output needs d + 1 <= 128");
-        g.col_step = g.tile_words * (int32_t)(pl.d + 1);
         g.CW = CW;
         g.ldcw = ldcw;
         g.n_words = words_for(n, pl.d);
+        // Residues fit a word's bytes: 128-column tiles and the slot pass for cut
+        // words.  Otherwise a tile covers whole words, the largest multiple of d+1
+        // columns in BN.
+        g.pack_slots = pl.d + 1 <= sizeof(W);
+        g.tile_words = BN / (int32_t)(pl.d + 1);
+        if (g.tile_words < 1) return fail(QMM_EUNSUPPORTED, "compressed output needs d + 1 <= 128");
+        if (!g.pack_slots) g.col_step = g.tile_words * (int32_t)(pl.d + 1);
     }
     const dim3 grid = grid_for(g);
     if (offset && blocked)
@@ -359,6 +423,13 @@ qmm_status launch_qadic_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
         gemm_kernel<W, W, W, EPI, false, true><<<grid, NT, 0, s>>>(g);
     else
         gemm_kernel<W, W, W, EPI, false, false><<<grid, NT, 0, s>>>(g);
+    if (EPI == EPI_PACK && g.pack_slots && BN % (pl.d + 1) != 0) {
+        const qmm_status st = check_launch("gemm_qadic_compress");
+        if (st != QMM_OK) return st;
+        const dim3 sgrid((unsigned)ceil_div(g.tiles_n, 64), (unsigned)std::min<int64_t>(m, 4096));
+        pack_cut_words_kernel<W><<<sgrid, 64, 0, s>>>(m, g.tiles_n, n, g.n_words, pl.d + 1, pl.t, (W *)CW, ldcw);
+        return check_launch("pack_cut_words");
+    }
     return check_launch(EPI == EPI_PACK ? "gemm_qadic_compress" : "gemm_qadic");
 }
 
