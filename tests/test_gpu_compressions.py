@@ -173,7 +173,11 @@ def compress_case(torch, p, m, n, k, path=qmm.PATH_FP64_QADIC, flags=0):
     (7, 260, 257, 200, qmm.PATH_FP64_QADIC),
     (3, 129, 700, 3000, qmm.PATH_FP64_QADIC),    # blocked plan
     (101, 130, 131, 50, qmm.PATH_FP64_QADIC),    # d small
-    (2, 140, 333, 77, qmm.PATH_FP32_QADIC),
+    (2, 140, 333, 77, qmm.PATH_FP32_QADIC),      # 3 residues per float: tiles cut words
+    (2, 150, 301, 15, qmm.PATH_FP32_QADIC),      # 6 residues per float: tiles of whole words
+    (2, 150, 301, 15, qmm.PATH_FP64_QADIC),      # 8 residues per double: the most the slots take
+    (2, 150, 256, 2, qmm.PATH_FP64_QADIC),       # n a multiple of 128
+    (5, 99, 385, 9, qmm.PATH_FP32_QADIC),
     (3, 1, 1, 1, qmm.PATH_FP64_QADIC)])
 def test_reduce_and_compress_matches_oracle(torch, p, m, n, k, path):
     pl, A, B, CC, C = compress_case(torch, p, m, n, k, path)
@@ -221,3 +225,16 @@ def test_reduce_and_compress_output_view_and_guard_words(torch):
     mask = np.ones_like(out, dtype=bool)
     mask[1:m + 1, 2:nw + 2] = False
     assert (out[mask] == -1.0).all()
+
+
+def test_reduce_and_compress_words_wider_than_their_bytes(torch):
+    # nine residues per double (more than its 8 bytes): tiles of whole words, 126 columns
+    p, m, n, k = 2, 150, 301, 15
+    pl = qmm.Plan(p=p, t=5, d=8, beta=53, k_block=k, path=qmm.PATH_FP64_QADIC, regime=qmm.REGIME_OFFSET, g=1)
+    assert qmm.validate_plan(pl, m, n, k) == qmm.OK
+    note("compress whole words", pl)
+    rng = np.random.default_rng(11)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    CC = qmm.gemm_packed_compress(pl, k, qmm.pack_rows_rev(pl, dev(torch, A)), qmm.pack_cols_fwd(pl, dev(torch, B)))
+    np.testing.assert_array_equal(words(host(CC)), ref.compress_rows_rev(ref.modmul(A, B, p), pl.t, pl.d))
