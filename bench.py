@@ -93,14 +93,21 @@ class Stepper:
             nw = -(-k // (plan.d + 1))
             self.CA = torch.empty((m, nw), dtype=wd, device=dev)
             self.CB = torch.empty((nw, n), dtype=wd, device=dev)
-        elif plan.path in (qmm.PATH_FP64_LEFT, qmm.PATH_FP32_LEFT, qmm.PATH_FP64_FULL, qmm.PATH_FP32_FULL):
-            wd = qmm.word_dtype(plan)
-            self.CAl = torch.empty((-(-m // (plan.d + 1)), k), dtype=wd, device=dev)
-            if plan.path in (qmm.PATH_FP64_FULL, qmm.PATH_FP32_FULL):
-                self.CBt = torch.empty((k, -(-n // (plan.d2 + 1))), dtype=wd, device=dev)
         else:
+            # right, left and full compression: both operands as words, the residue
+            # operand of right and left compression converted by a pass of its own
+            # (what qmm_gemm_mod_p does), then the word x word product
             wd = qmm.word_dtype(plan)
-            self.CBr = torch.empty((k, -(-n // (plan.d + 1))), dtype=wd, device=dev)
+            right = plan.path in (qmm.PATH_FP64_REDQ, qmm.PATH_FP32_REDQ)
+            left = plan.path in (qmm.PATH_FP64_LEFT, qmm.PATH_FP32_LEFT)
+            dq, dth = (0, plan.d) if right else ((plan.d, 0) if left else (plan.d, plan.d2))
+            self.one = qmm.Plan.from_buffer_copy(plan)
+            self.one.d, self.one.d2 = 0, 0
+            self.fullp = qmm.Plan.from_buffer_copy(plan)
+            self.fullp.d, self.fullp.d2 = dq, dth
+            self.fullp.path = qmm.PATH_FP64_FULL if plan.beta == 53 else qmm.PATH_FP32_FULL
+            self.CAl = torch.empty((-(-m // (dq + 1)), k), dtype=wd, device=dev)
+            self.CBt = torch.empty((k, -(-n // (dth + 1))), dtype=wd, device=dev)
         self._prepare()
 
     def _prepare(self):
@@ -132,27 +139,25 @@ class Stepper:
                                (L.qmm_pack_cols_fwd, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CB.data_ptr()), q._ld(CB), st))]
             self.prod_calls = [(L.qmm_gemm_packed, (P, m, n, k, vp(CA.data_ptr()), q._ld(CA), vp(CB.data_ptr()),
                                                     q._ld(CB), vp(C.data_ptr()), q._ld(C), st))]
-        elif pl.path in (q.PATH_FP64_LEFT, q.PATH_FP32_LEFT):
-            CAl = self.CAl
-            self.conv_calls = [(L.qmm_pack_left, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CAl.data_ptr()),
-                                                  q._ld(CAl), st))]
-            self.prod_calls = [(L.qmm_gemm_left_packed, (P, m, n, k, vp(CAl.data_ptr()), q._ld(CAl),
-                                                         vp(B.data_ptr()), q._ld(B), vp(C.data_ptr()), q._ld(C), st))]
-        elif pl.path in (q.PATH_FP64_FULL, q.PATH_FP32_FULL):
+        else:
             CAl, CBt = self.CAl, self.CBt
-            self.conv_calls = [(L.qmm_pack_left, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CAl.data_ptr()),
-                                                  q._ld(CAl), st)),
-                               (L.qmm_pack_full_right, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CBt.data_ptr()),
-                                                        q._ld(CBt), st))]
-            self.prod_calls = [(L.qmm_gemm_full_packed, (P, m, n, k, vp(CAl.data_ptr()), q._ld(CAl),
+            P1, PF = ctypes.byref(self.one), ctypes.byref(self.fullp)
+            a_words = (L.qmm_pack_cols_fwd, (P1, m, k, vp(A.data_ptr()), q._ld(A), vp(CAl.data_ptr()), q._ld(CAl), st))
+            b_words = (L.qmm_pack_rows_fwd, (P1, k, n, vp(B.data_ptr()), q._ld(B), vp(CBt.data_ptr()), q._ld(CBt), st))
+            if pl.path in (q.PATH_FP64_REDQ, q.PATH_FP32_REDQ):
+                self.conv_calls = [(L.qmm_pack_rows_fwd, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CBt.data_ptr()),
+                                                          q._ld(CBt), st)), a_words]
+            elif pl.path in (q.PATH_FP64_LEFT, q.PATH_FP32_LEFT):
+                self.conv_calls = [(L.qmm_pack_left, (PF, m, k, vp(A.data_ptr()), q._ld(A), vp(CAl.data_ptr()),
+                                                      q._ld(CAl), st)), b_words]
+            else:
+                self.conv_calls = [(L.qmm_pack_left, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CAl.data_ptr()),
+                                                      q._ld(CAl), st)),
+                                   (L.qmm_pack_full_right, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CBt.data_ptr()),
+                                                            q._ld(CBt), st))]
+            self.prod_calls = [(L.qmm_gemm_full_packed, (PF, m, n, k, vp(CAl.data_ptr()), q._ld(CAl),
                                                          vp(CBt.data_ptr()), q._ld(CBt), vp(C.data_ptr()), q._ld(C),
                                                          st))]
-        else:
-            CBr = self.CBr
-            self.conv_calls = [(L.qmm_pack_rows_fwd, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(CBr.data_ptr()),
-                                                      q._ld(CBr), st))]
-            self.prod_calls = [(L.qmm_gemm_right_packed, (P, m, n, k, vp(A.data_ptr()), q._ld(A), vp(CBr.data_ptr()),
-                                                          q._ld(CBr), vp(C.data_ptr()), q._ld(C), st))]
 
     def _run(self, calls):
         for fn, args in calls:

@@ -188,7 +188,11 @@ qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, i
  * plan == NULL: qmm_choose_Qd(p, m, n, k, 0, QMM_PATH_AUTO, 0) is used.
  * A: m x k, B: k x n, C: m x n bytes (C must not overlap A or B).
  * ws: device workspace of ws_bytes >= qmm_gemm_workspace_size (may be NULL when
- * that size is 0); it holds the packed operands between the kernels. */
+ * that size is 0); it holds the packed operands between the kernels.  The REDQ and
+ * LEFT paths also hold their residue operand there as words (one residue each,
+ * procedure (5)'s Uncompress) and multiply two word matrices; the stage calls
+ * qmm_gemm_right_packed / qmm_gemm_left_packed instead convert that operand on
+ * the fly, with no workspace. */
 qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, uint32_t p,
                           const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
                           uint8_t *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);

@@ -46,12 +46,18 @@ Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
         L.off_b = align_up((size_t)m * nw * wb);
         L.bytes = L.off_b + align_up((size_t)nw * n * wb);
     } else if (path_is_redq(pl.path)) {
+        // CBr, then A as words (the Uncompress of procedure (5))
         const int64_t nw = words_for(n, pl.d);
         L.ld_b = nw;
-        L.bytes = align_up((size_t)kk * nw * word_bytes(pl));
-    } else if (path_is_left(pl.path)) {
         L.ld_a = kk;
-        L.bytes = align_up((size_t)words_for(m, pl.d) * kk * word_bytes(pl));
+        L.off_b = align_up((size_t)kk * nw * word_bytes(pl));
+        L.bytes = L.off_b + align_up((size_t)m * kk * word_bytes(pl));
+    } else if (path_is_left(pl.path)) {
+        // CAl, then B as words
+        L.ld_a = kk;
+        L.ld_b = n;
+        L.off_b = align_up((size_t)words_for(m, pl.d) * kk * word_bytes(pl));
+        L.bytes = L.off_b + align_up((size_t)kk * n * word_bytes(pl));
     } else if (path_is_full(pl.path)) {
         L.ld_a = kk;
         L.ld_b = words_for(n, pl.d2);
@@ -66,6 +72,21 @@ Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
         L.bytes = L.off_b + align_up((size_t)n * L.ld_b);
     }
     return L;
+}
+
+qmm_plan with_degrees(const qmm_plan &pl, uint32_t d, uint32_t d2) {
+    qmm_plan q = pl;
+    q.d = d;
+    q.d2 = d2;
+    return q;
+}
+
+// The full-compression plan (degree d in Q along m, d2 along n) with pl's t and
+// mantissa: the kernel of every word-times-word REDQ product.
+qmm_plan full_plan_of(const qmm_plan &pl, uint32_t d, uint32_t d2) {
+    qmm_plan q = with_degrees(pl, d, d2);
+    q.path = pl.beta == 24 ? QMM_PATH_FP32_FULL : QMM_PATH_FP64_FULL;
+    return q;
 }
 
 qmm_status resolve_plan(const qmm_plan *plan, uint32_t p, int64_t m, int64_t n, int64_t k, qmm_plan *out) {
@@ -183,13 +204,24 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
         if ((st = launch_pack_cols_fwd(pl, k, n, B, ldb, CB, L.ld_b, stream)) != QMM_OK) return st;
         return launch_gemm_qadic(pl, m, n, k, CA, L.ld_a, CB, L.ld_b, C, ldc, stream);
     }
+    // Right and left compression convert their residue operand to words in a pass
+    // of its own (procedure (5)'s Uncompress), then run the product of two word
+    // matrices: converting in the product's load path measured slower.  A word of
+    // one residue is the residue (degree 0), and the product is full compression
+    // with one degree zero.
     if (path_is_redq(pl.path)) {
-        if ((st = launch_pack_rows_fwd(pl, k, n, B, ldb, w, L.ld_b, stream)) != QMM_OK) return st;
-        return launch_gemm_redq(pl, m, n, k, A, lda, w, L.ld_b, C, ldc, stream);
+        void *CBr = w, *Aw = w + L.off_b;
+        const qmm_plan one = with_degrees(pl, 0, 0), fp = full_plan_of(pl, 0, pl.d);
+        if ((st = launch_pack_rows_fwd(pl, k, n, B, ldb, CBr, L.ld_b, stream)) != QMM_OK) return st;
+        if ((st = launch_pack_cols_fwd(one, m, k, A, lda, Aw, L.ld_a, stream)) != QMM_OK) return st;
+        return launch_gemm_full(fp, m, n, k, Aw, L.ld_a, CBr, L.ld_b, C, ldc, stream);
     }
     if (path_is_left(pl.path)) {
-        if ((st = launch_pack_cols_fwd(pl, m, k, A, lda, w, L.ld_a, stream)) != QMM_OK) return st;
-        return launch_gemm_left(pl, m, n, k, w, L.ld_a, B, ldb, C, ldc, stream);
+        void *CAl = w, *Bw = w + L.off_b;
+        const qmm_plan one = with_degrees(pl, 0, 0), fp = full_plan_of(pl, pl.d, 0);
+        if ((st = launch_pack_cols_fwd(pl, m, k, A, lda, CAl, L.ld_a, stream)) != QMM_OK) return st;
+        if ((st = launch_pack_rows_fwd(one, k, n, B, ldb, Bw, L.ld_b, stream)) != QMM_OK) return st;
+        return launch_gemm_full(fp, m, n, k, CAl, L.ld_a, Bw, L.ld_b, C, ldc, stream);
     }
     if (path_is_full(pl.path)) {
         void *CAl = w, *CBt = w + L.off_b;

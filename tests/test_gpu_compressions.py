@@ -238,3 +238,26 @@ def test_reduce_and_compress_words_wider_than_their_bytes(torch):
     B = rng.integers(0, p, (k, n), dtype=np.uint8)
     CC = qmm.gemm_packed_compress(pl, k, qmm.pack_rows_rev(pl, dev(torch, A)), qmm.pack_cols_fwd(pl, dev(torch, B)))
     np.testing.assert_array_equal(words(host(CC)), ref.compress_rows_rev(ref.modmul(A, B, p), pl.t, pl.d))
+
+
+@pytest.mark.parametrize("beta", [53, 24])
+@pytest.mark.parametrize("p,m,n,k", [(3, 389, 300, 61), (7, 130, 257, 33), (101, 200, 131, 20), (2, 1, 1, 1)])
+def test_stage_calls_convert_residues_in_the_load_path(torch, beta, p, m, n, k):
+    # qmm_gemm_right_packed / qmm_gemm_left_packed take the residue operand as bytes
+    # and convert it on its way into LDS (qmm_gemm_mod_p converts it by a pass)
+    rng = np.random.default_rng(m + n + k + beta)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    for path in ((qmm.PATH_FP64_REDQ, qmm.PATH_FP64_LEFT) if beta == 53 else (qmm.PATH_FP32_REDQ, qmm.PATH_FP32_LEFT)):
+        st, pl = qmm.try_choose_Qd(p, m, n, k, path=path)
+        if st != qmm.OK:
+            continue
+        note("stage", qmm.PATH_NAMES[path], p, m, n, k, pl)
+        if path in (qmm.PATH_FP64_REDQ, qmm.PATH_FP32_REDQ):
+            C = qmm.gemm_right_packed(pl, dA, qmm.pack_rows_fwd(pl, dB), n)
+        else:
+            C = qmm.gemm_left_packed(pl, qmm.pack_left(pl, dA), dB, m)
+        np.testing.assert_array_equal(host(C), want)
+        np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=pl)), want)
