@@ -89,7 +89,6 @@ struct GemmArgs {
     uint64_t qmask;
     double invp;
     double start;            // accumulator start value (M or 0)
-    uint64_t magic;          // mod_u32 multiplier for p
     uint32_t m32;            // mod_u32_m32 multiplier for p, floor(2^32 / p)
     double inv_qd, inv_q, q; // 2^-td, 2^-t, 2^t (exact-regime digit)
     int32_t small_digit;     // t <= 31: digits fit 32 bits
@@ -186,7 +185,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
                 uint32_t packed = 0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    packed |= mod_u32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.magic) << (8 * r);
+                    packed |= mod_u32_m32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.m32) << (8 * r);
                 res[mi][ni] = packed;
                 acc[mi][ni] = acc_t{start, start, start, start};
             }
@@ -224,8 +223,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     // Digit d of the accumulated word at (mi, ni, r), reduced mod p.
     auto qadic_value = [&](int mi, int ni, int r) -> uint32_t {
         if constexpr (BLOCKED)
-            return mod_u32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.magic);
-        else if (g.small_digit) return mod_u32(digit32(acc[mi][ni][r]), g.p, g.magic);
+            return mod_u32_m32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.m32);
+        else if (g.small_digit) return mod_u32_m32(digit32(acc[mi][ni][r]), g.p, g.m32);
         else return mod_u64(qadic_digit<W>(acc[mi][ni][r], OFFSET, g.td, g.qmask), g.p, g.invp);
     };
     if constexpr (EPI == EPI_PACK) {
@@ -364,7 +363,6 @@ void common_args(GemmArgs &g, const qmm_plan &pl) {
     g.td = pl.t * pl.d;
     g.qmask = (1ull << pl.t) - 1;
     g.invp = 1.0 / (double)pl.p;
-    g.magic = mod_magic(pl.p);
     g.m32 = (uint32_t)((1ull << 32) / pl.p);
     g.small_digit = pl.t <= 31;
     g.col_step = BN;
