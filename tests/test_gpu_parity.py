@@ -18,7 +18,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 PATHS = (qmm.PATH_FP64_QADIC, qmm.PATH_FP64_REDQ, qmm.PATH_FP32_QADIC, qmm.PATH_FP32_REDQ, qmm.PATH_INT8,
-         qmm.PATH_FP4)
+         qmm.PATH_FP4, qmm.PATH_FP64_LEFT, qmm.PATH_FP32_LEFT, qmm.PATH_FP64_FULL, qmm.PATH_FP32_FULL)
 
 
 @pytest.fixture(scope="module")
@@ -193,7 +193,9 @@ def test_degenerate_shapes(torch, path):
                                       (qmm.PATH_FP64_REDQ, 7, 4096), (qmm.PATH_FP64_REDQ, 101, 8192),
                                       (qmm.PATH_FP32_QADIC, 3, 5000), (qmm.PATH_FP32_QADIC, 101, 4000),
                                       (qmm.PATH_FP32_REDQ, 3, 511), (qmm.PATH_INT8, 251, 1000),
-                                      (qmm.PATH_INT8, 101, 8192)])
+                                      (qmm.PATH_INT8, 101, 8192), (qmm.PATH_FP64_LEFT, 7, 4096),
+                                      (qmm.PATH_FP64_FULL, 3, 2047), (qmm.PATH_FP64_FULL, 101, 8192),
+                                      (qmm.PATH_FP32_FULL, 2, 63)])
 def test_worst_case_all_p_minus_one(torch, path, p, k):
     # every residue p-1: C = k (p-1)^2 = k (mod p); the largest digits, words and low parts
     st, plan = qmm.try_choose_Qd(p, 48, 40, k, path=path)
@@ -309,7 +311,7 @@ def sampled_check(torch, A, B, p, C, nsamp=20000, rows=4, seed=0):
     np.testing.assert_array_equal(C[m - 1], ref.modmul(A[m - 1:m], B, p)[0])
 
 
-@pytest.mark.parametrize("name", ("small", "square", "large"))
+@pytest.mark.parametrize("name", ("small", "square", "large", "thin"))
 def test_workloads_all_paths(torch, name):
     p, A, B = synth.workload(name)
     m, k = A.shape
