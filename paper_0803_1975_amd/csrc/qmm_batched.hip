@@ -544,7 +544,50 @@ qmm_status hip_fail(hipError_t e, const char *what) {
     return fail(QMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// A single small product on the FP64 Q-adic path in one launch: one workgroup per
+// 64 x 64 tile packs its rows of A (reversed) and columns of B (forward) straight
+// from the bytes into LDS, as the batched FP64 tiles do; no packed operands in HBM
+// and no separate pack launches.
+__global__ __launch_bounds__(NT) void fused_qadic_kernel(Desc D, int32_t tiles_n) {
+    __shared__ __attribute__((aligned(16))) double lds[64 * (KW + 1) + KW * 64];
+    const int tm = (int)(blockIdx.x / (uint32_t)tiles_n), tn = (int)(blockIdx.x % (uint32_t)tiles_n);
+    fp64_tile(D, tm, tn, lds, lds + 64 * (KW + 1));
+}
+
 }  // namespace
+
+qmm_status launch_gemm_qadic_fused(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                                   int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc,
+                                   void *stream) {
+    if (m == 0 || n == 0) return QMM_OK;
+    if (pl.beta != 53 || !path_is_qadic(pl.path) || pl.k_block < k || pl.t > 63 ||
+        (uint64_t)pl.t * (pl.d + 1) > 64 || m > INT32_MAX || n > INT32_MAX || k > INT32_MAX)
+        return fail(QMM_EUNSUPPORTED, "the fused Q-adic kernel takes unblocked FP64 plans and 32-bit sizes");
+    Desc D;
+    std::memset(&D, 0, sizeof(D));
+    D.A = A;
+    D.B = B;
+    D.C = C;
+    D.lda = lda;
+    D.ldb = ldb;
+    D.ldc = ldc;
+    D.m = (int32_t)m;
+    D.n = (int32_t)n;
+    D.k = (int32_t)k;
+    D.p = pl.p;
+    D.path = QMM_PATH_FP64_QADIC;
+    D.invp = 1.0 / (double)pl.p;
+    D.t = pl.t;
+    D.d = pl.d;
+    D.offset_regime = pl.regime == QMM_REGIME_OFFSET;
+    D.start = D.offset_regime ? std::ldexp(1.0, 52 + (int)(pl.t * pl.d)) : 0.0;
+    const int64_t tiles_m = ceil_div(m, 64), tiles_n = ceil_div(n, 64);
+    if (tiles_m * tiles_n > INT32_MAX) return fail(QMM_EUNSUPPORTED, "too many tiles for the fused Q-adic kernel");
+    fused_qadic_kernel<<<dim3((unsigned)(tiles_m * tiles_n)), NT, 0, (hipStream_t)stream>>>(D, (int32_t)tiles_n);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QMM_OK : hip_fail(e, "fused_qadic_kernel");
+}
+
 }  // namespace qmm
 
 using namespace qmm;

@@ -86,6 +86,13 @@ qmm_status launch_gemm_left(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
 // Full compression + two-variable REDQ: C = REDQ(CAl x CBt), blocks of (d+1) x (d2+1).
 qmm_status launch_gemm_full(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const void *CAl, int64_t ldcal,
                             const void *CBt, int64_t ldcbt, uint8_t *C, int64_t ldc, void *stream);
+// Procedure (2) for a small product in one launch (FP64, unblocked plans): each
+// tile packs its operands from the bytes into LDS.
+qmm_status launch_gemm_qadic_fused(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                                   int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc,
+                                   void *stream);
+// Largest m n k that qmm_gemm_mod_p runs on the fused Q-adic kernel.
+constexpr double kFusedQadicMaxMacs = 4194304.0;  // 2^22: the staged path wins from between 160^3 and 192^3 (measured)
 // Right-compressed GEMM + REDQ (procedure (5)): C = REDQ(A x CBr).
 qmm_status launch_gemm_redq(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const void *CBr, int64_t ldcbr,

@@ -50,8 +50,12 @@ def test_argument_checks_reject_before_any_device_work():
     # p outside the byte range, p mismatch with the plan
     assert L.qmm_gemm_mod_p(None, 4, 4, 4, 257, fake, 4, fake, 4, fake, 4, null, 0, null) == qmm.EINVAL
     assert L.qmm_gemm_mod_p(ctypes.byref(pl), 4, 4, 4, 5, fake, 4, fake, 4, fake, 4, null, 0, null) == qmm.EINVAL
-    # workspace too small
-    assert L.qmm_gemm_mod_p(ctypes.byref(pl), 4, 4, 4, 7, fake, 4, fake, 4, fake, 4, fake, 8, null) == qmm.ENOSPACE
+    # workspace too small (a product large enough to pack its operands in HBM; small
+    # unblocked FP64 products run in one launch without a workspace)
+    big = qmm.choose_Qd(7, 512, 512, 512, path=qmm.PATH_FP64_QADIC)
+    assert qmm.gemm_workspace_size(big, 512, 512, 512) > 8 and qmm.gemm_workspace_size(pl, 4, 4, 4) == 0
+    assert L.qmm_gemm_mod_p(ctypes.byref(big), 512, 512, 512, 7, fake, 512, fake, 512, fake, 512, fake, 8,
+                            null) == qmm.ENOSPACE
     # an unknown unpack selector, a REDQ plan for procedure (1)
     assert L.qmm_unpack(ctypes.byref(pl), 3, 4, 4, fake, 4, fake, 4, null) == qmm.EINVAL
     rq = qmm.choose_Qd(7, 64, 64, 64, path=qmm.PATH_FP64_REDQ)

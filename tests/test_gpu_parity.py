@@ -488,3 +488,26 @@ def test_fp4_worst_case_and_blocked_accumulation(torch):
         plan = qmm.choose_Qd(p, 50, 40, k, path=qmm.PATH_FP4)
         plan.k_block, plan.tile = 512, tile
         np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=plan)), want, err_msg=f"tile {tile}")
+
+
+@pytest.mark.parametrize("p,m,n,k", [(3, 64, 64, 64), (7, 1, 1, 1), (2, 65, 130, 33), (101, 100, 70, 50),
+                                     (3, 128, 128, 128), (5, 100, 90, 200), (13, 129, 3, 700)])
+def test_fused_small_qadic_matches_staged_calls_and_oracle(torch, p, m, n, k):
+    # qmm_gemm_mod_p runs small unblocked FP64 Q-adic products in one launch that
+    # packs in LDS (no workspace); the staged calls pack in HBM first
+    rng = np.random.default_rng(p * m + n + k)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    for flags in (0, qmm.PLAN_UNBLOCKED | qmm.BOUND_EQ4):
+        st, plan = qmm.try_choose_Qd(p, m, n, k, path=qmm.PATH_FP64_QADIC, flags=flags)
+        if st != qmm.OK or plan.k_block < k:
+            continue
+        note("fused", p, m, n, k, plan)
+        assert qmm.gemm_workspace_size(plan, m, n, k) == 0
+        C = torch.full((m, n), 0xCD, dtype=torch.uint8, device="cuda")
+        qmm.gemm_mod_p(dA, dB, p, plan=plan, C=C, ws=torch.empty(0, dtype=torch.uint8, device="cuda"))
+        np.testing.assert_array_equal(host(C), want)
+        staged = qmm.gemm_packed(plan, k, qmm.pack_rows_rev(plan, dA), qmm.pack_cols_fwd(plan, dB))
+        np.testing.assert_array_equal(host(staged), want)
