@@ -192,7 +192,9 @@ qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, i
  * LEFT paths also hold their residue operand there as words (one residue each,
  * procedure (5)'s Uncompress) and multiply two word matrices; the stage calls
  * qmm_gemm_right_packed / qmm_gemm_left_packed instead convert that operand on
- * the fly, with no workspace. */
+ * the fly, with no workspace.  Small products on an unblocked FP64 Q-adic plan
+ * (m n k <= 2^22) run in one launch that packs the operands in on-chip memory and
+ * need no workspace (qmm_gemm_workspace_size returns 0). */
 qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, uint32_t p,
                           const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
                           uint8_t *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
