@@ -83,7 +83,7 @@ class Stepper:
         self.m, self.n, self.k = m, n, k
         dev = dA.device
         self.C = torch.empty((m, n), dtype=torch.uint8, device=dev)
-        self.fused = (plan.path == qmm.PATH_FP64_QADIC and plan.k_block >= k
+        self.fused = (plan.path in (qmm.PATH_FP64_QADIC, qmm.PATH_INT8) and plan.k_block >= k
                       and qmm.gemm_workspace_size(plan, m, n, k) == 0)
         if plan.path == qmm.PATH_INT8:
             self.Bt = torch.empty((n, qmm.centred_ld(k)), dtype=torch.int8, device=dev)
@@ -123,7 +123,13 @@ class Stepper:
         st = vp(torch.cuda.current_stream().cuda_stream)
         A, B, C = self.dA, self.dB, self.C
         m, n, k = self.m, self.n, self.k
-        if pl.path == q.PATH_INT8:
+        if self.fused:
+            # one launch: qmm_gemm_mod_p runs small unblocked FP64 Q-adic and INT8
+            # products on kernels that pack in LDS (no workspace, no conversion stage)
+            self.conv_calls = []
+            self.prod_calls = [(L.qmm_gemm_mod_p, (P, m, n, k, pl.p, vp(A.data_ptr()), q._ld(A), vp(B.data_ptr()),
+                                                   q._ld(B), vp(C.data_ptr()), q._ld(C), vp(0), 0, st))]
+        elif pl.path == q.PATH_INT8:
             Bt = self.Bt
             self.conv_calls = [(L.qmm_pack_centred_cols, (P, k, n, vp(B.data_ptr()), q._ld(B), vp(Bt.data_ptr()),
                                                           q._ld(Bt), st))]
@@ -135,12 +141,6 @@ class Stepper:
                                                  vp(A4.data_ptr()), q._ld(A4), vp(Bt4.data_ptr()), q._ld(Bt4), st))]
             self.prod_calls = [(L.qmm_gemm_fp4, (P, m, n, k, vp(A4.data_ptr()), q._ld(A4), vp(Bt4.data_ptr()),
                                                  q._ld(Bt4), vp(C.data_ptr()), q._ld(C), st))]
-        elif self.fused:
-            # one launch: qmm_gemm_mod_p runs small unblocked FP64 Q-adic products on a
-            # kernel that packs in LDS (no workspace, no conversion stage)
-            self.conv_calls = []
-            self.prod_calls = [(L.qmm_gemm_mod_p, (P, m, n, k, pl.p, vp(A.data_ptr()), q._ld(A), vp(B.data_ptr()),
-                                                   q._ld(B), vp(C.data_ptr()), q._ld(C), vp(0), 0, st))]
         elif pl.path in (q.PATH_FP64_QADIC, q.PATH_FP32_QADIC):
             CA, CB = self.CA, self.CB
             self.conv_calls = [(L.qmm_pack_rows_rev, (P, m, k, vp(A.data_ptr()), q._ld(A), vp(CA.data_ptr()), q._ld(CA), st)),

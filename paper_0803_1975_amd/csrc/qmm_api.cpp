@@ -41,10 +41,15 @@ bool fused_qadic(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
            (double)m * (double)n * (double)k <= kFusedQadicMaxMacs;
 }
 
+// Small unblocked INT8 products run in one launch that centres and transposes in LDS.
+bool small_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
+    return pl.path == QMM_PATH_INT8 && pl.k_block >= k && (double)m * (double)n * (double)k <= kSmallInt8MaxMacs;
+}
+
 Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
     Layout L;
     const int64_t kk = k < 1 ? 1 : k;
-    if (fused_qadic(pl, m, n, k)) return L;  // no packed operands in HBM
+    if (fused_qadic(pl, m, n, k) || small_int8(pl, m, n, k)) return L;  // no packed operands in HBM
     if (path_is_qadic(pl.path)) {
         const int64_t nw = words_for(kk, pl.d);
         const size_t wb = (size_t)word_bytes(pl);
@@ -206,6 +211,7 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
         return fail(QMM_ENOSPACE, "workspace needs " + std::to_string(L.bytes) + " bytes");
     uint8_t *w = (uint8_t *)ws;
     if (fused_qadic(pl, m, n, k)) return launch_gemm_qadic_fused(pl, m, n, k, A, lda, B, ldb, C, ldc, stream);
+    if (small_int8(pl, m, n, k)) return launch_gemm_int8_small(pl, m, n, k, A, lda, B, ldb, C, ldc, stream);
     if (path_is_qadic(pl.path)) {
         void *CA = w, *CB = w + L.off_b;
         if ((st = launch_pack_rows_rev(pl, m, k, A, lda, CA, L.ld_a, stream)) != QMM_OK) return st;

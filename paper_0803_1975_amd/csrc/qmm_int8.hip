@@ -535,7 +535,103 @@ void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
     neg_p = (256u - p) & 0xffu;
 }
 
+// A small INT8 product in one launch: one 256-thread workgroup per 64 x 64 tile of C
+// (2 x 2 wavefronts, one i32_32x32x32_i8 block each), 64-byte K stages.  A's rows
+// are centred on their way into LDS; B's rows are centred and stored transposed
+// into LDS byte by byte, so the product needs no conversion launch and no
+// workspace.  Unblocked plans only (k (p/2)^2 stays in int32).
+struct SmallInt8Args {
+    int64_t m, n, k;
+    const uint8_t *A;
+    int64_t lda;
+    const uint8_t *B;
+    int64_t ldb;
+    uint8_t *C;
+    int64_t ldc;
+    int32_t tiles_n;
+    uint32_t p, add_h, neg_p, off, magic32;
+};
+constexpr int SM_T = 64, SM_KT = 64, SM_PITCH = SM_KT + 16;
+
+// 16 bytes of row `row` of X from column c0 (zero past rows or cols), as four words.
+__device__ __forceinline__ void load16(const uint8_t *__restrict__ X, int64_t ld, int64_t rows, int64_t cols,
+                                       int64_t row, int64_t c0, uint32_t w[4]) {
+    w[0] = w[1] = w[2] = w[3] = 0;
+    if (row >= rows) return;
+    const uint8_t *src = X + row * ld + c0;
+    for (int b = 0; b < 16; ++b)
+        if (c0 + b < cols) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+}
+
+__global__ __launch_bounds__(256) void small_int8_kernel(SmallInt8Args g) {
+    __shared__ __attribute__((aligned(16))) uint8_t sA[SM_T * SM_PITCH];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[SM_T * SM_PITCH];  // rows: columns of B
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t row0 = (int64_t)(blockIdx.x / (uint32_t)g.tiles_n) * SM_T;
+    const int64_t col0 = (int64_t)(blockIdx.x % (uint32_t)g.tiles_n) * SM_T;
+    const int r = tid >> 2, seg = tid & 3;  // staging: row r, bytes 16 seg .. 16 seg + 15
+    ix16 acc = ix16{};
+    for (int64_t k0 = 0; k0 < g.k; k0 += SM_KT) {
+        uint32_t wa[4], wb[4];
+        load16(g.A, g.lda, g.m, g.k, row0 + r, k0 + 16 * seg, wa);                        // A row, 16 k
+        load16(g.B + col0, g.ldb, g.k, g.n - col0, k0 + r, 16 * seg, wb);                   // B k-row, 16 n
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            wa[i] = centre4(wa[i], g.add_h, g.neg_p);
+            wb[i] = centre4(wb[i], g.add_h, g.neg_p);
+        }
+        *(uint4 *)&sA[r * SM_PITCH + 16 * seg] = make_uint4(wa[0], wa[1], wa[2], wa[3]);
+#pragma unroll
+        for (int b = 0; b < 16; ++b) sB[(16 * seg + b) * SM_PITCH + r] = (uint8_t)(wb[b >> 2] >> (8 * (b & 3)));
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < SM_KT / 32; ++ks) {
+            const ix4 a = *(const ix4 *)&sA[(wm * 32 + (lane & 31)) * SM_PITCH + ks * 32 + 16 * (lane >> 5)];
+            const ix4 b = *(const ix4 *)&sB[(wn * 32 + (lane & 31)) * SM_PITCH + ks * 32 + 16 * (lane >> 5)];
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // register q holds D[8 (q/4) + 4 (l/32) + q % 4][l % 32] of this wavefront's block
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t row = row0 + wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        const int64_t col = col0 + wn * 32 + (lane & 31);
+        if (row < g.m && col < g.n)
+            g.C[row * g.ldc + col] = (uint8_t)mod_u32_m32((uint32_t)acc[q] + g.off, g.p, g.magic32);
+    }
+}
+
 }  // namespace
+
+qmm_status launch_gemm_int8_small(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                                  int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc,
+                                  void *stream) {
+    if (m == 0 || n == 0) return QMM_OK;
+    if (pl.path != QMM_PATH_INT8 || pl.k_block < k || pl.p > 256)
+        return fail(QMM_EUNSUPPORTED, "the one-launch INT8 kernel takes unblocked INT8 plans");
+    SmallInt8Args g{};
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.A = A;
+    g.lda = lda;
+    g.B = B;
+    g.ldb = ldb;
+    g.C = C;
+    g.ldc = ldc;
+    g.p = pl.p;
+    centre_consts(pl.p, g.add_h, g.neg_p);
+    g.off = pl.p * ((1u << 31) / pl.p);
+    g.magic32 = (uint32_t)((1ull << 32) / pl.p);
+    const int64_t tiles_m = ceil_div(m, SM_T), tiles_n = ceil_div(n, SM_T);
+    if (tiles_m * tiles_n > INT32_MAX) return fail(QMM_EUNSUPPORTED, "too many tiles for the one-launch INT8 kernel");
+    g.tiles_n = (int32_t)tiles_n;
+    small_int8_kernel<<<dim3((unsigned)(tiles_m * tiles_n)), 256, 0, (hipStream_t)stream>>>(g);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QMM_OK : fail(QMM_EDEVICE, std::string("small_int8_kernel: ") + hipGetErrorString(e));
+}
 
 // Codes of the residues 0..7 (centred, then e2m1: magnitudes 0, 1, 2, 3, 4 are the
 // codes 0, 2, 4, 5, 6, sign bit 8), bytes 0..3 in lo and 4..7 in hi; residues >= p

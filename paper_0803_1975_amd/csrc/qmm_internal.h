@@ -100,6 +100,12 @@ qmm_status launch_gemm_redq(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
 // INT8: B is first centred and transposed into Bt (n x k, int8, ldbt = k rounded up).
 qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B,
                                    int64_t ldb, int8_t *Bt, int64_t ldbt, void *stream);
+// A small unblocked INT8 product in one launch (B centred and transposed in LDS).
+qmm_status launch_gemm_int8_small(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A,
+                                  int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc,
+                                  void *stream);
+// Largest m n k that qmm_gemm_mod_p runs on the one-launch INT8 kernel.
+constexpr double kSmallInt8MaxMacs = 524288.0;  // 2^19: one launch wins at 64^3 (5.1 vs 8.1 us), loses at 128^3 (10.3 vs 7.1)
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
                             uint8_t *C, int64_t ldc, void *stream);

@@ -511,3 +511,26 @@ def test_fused_small_qadic_matches_staged_calls_and_oracle(torch, p, m, n, k):
         np.testing.assert_array_equal(host(C), want)
         staged = qmm.gemm_packed(plan, k, qmm.pack_rows_rev(plan, dA), qmm.pack_cols_fwd(plan, dB))
         np.testing.assert_array_equal(host(staged), want)
+
+
+@pytest.mark.parametrize("p,m,n,k", [(3, 64, 64, 64), (2, 1, 1, 1), (251, 65, 130, 33), (101, 100, 70, 70),
+                                     (7, 50, 45, 200), (13, 129, 3, 700), (251, 8, 8, 4096)])
+def test_small_int8_one_launch_matches_staged_calls_and_oracle(torch, p, m, n, k):
+    # qmm_gemm_mod_p runs small unblocked INT8 products in one launch that centres A
+    # and B and transposes B in LDS (no workspace); the staged calls convert B in HBM
+    rng = np.random.default_rng(p * m + n + k)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    if k == 4096:   # the largest centred magnitude everywhere: k (p/2)^2 = 64 000 000
+        A[:] = p // 2
+        B[:] = p // 2
+    want = ref.modmul(A, B, p)
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    assert plan.k_block >= k and qmm.gemm_workspace_size(plan, m, n, k) == 0
+    note("small int8", p, m, n, k, plan)
+    dA, dB = dev(torch, A), dev(torch, B)
+    C = torch.full((m, n), 0xCD, dtype=torch.uint8, device="cuda")
+    qmm.gemm_mod_p(dA, dB, p, plan=plan, C=C, ws=torch.empty(0, dtype=torch.uint8, device="cuda"))
+    np.testing.assert_array_equal(host(C), want)
+    staged = qmm.gemm_centred(plan, dA, qmm.pack_centred_cols(plan, dB), n)
+    np.testing.assert_array_equal(host(staged), want)
