@@ -41,9 +41,11 @@ bool fused_qadic(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
            (double)m * (double)n * (double)k <= kFusedQadicMaxMacs;
 }
 
-// Small unblocked INT8 products run in one launch that centres and transposes in LDS.
+// Small unblocked INT8 products run in one launch that centres and transposes in LDS
+// (unless the plan asks for a tile of the two-kernel path).
 bool small_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
-    return pl.path == QMM_PATH_INT8 && pl.k_block >= k && (double)m * (double)n * (double)k <= kSmallInt8MaxMacs;
+    return pl.path == QMM_PATH_INT8 && pl.tile == 0 && pl.k_block >= k &&
+           (double)m * (double)n * (double)k <= kSmallInt8MaxMacs;
 }
 
 Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {

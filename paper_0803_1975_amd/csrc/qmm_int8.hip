@@ -553,12 +553,21 @@ struct SmallInt8Args {
 };
 constexpr int SM_T = 64, SM_KT = 64, SM_PITCH = SM_KT + 16;
 
-// 16 bytes of row `row` of X from column c0 (zero past rows or cols), as four words.
+// 16 bytes of row `row` of X from column c0 (zero past rows or cols), as four words:
+// one 16-byte load when they are whole and aligned, byte loads otherwise.
 __device__ __forceinline__ void load16(const uint8_t *__restrict__ X, int64_t ld, int64_t rows, int64_t cols,
                                        int64_t row, int64_t c0, uint32_t w[4]) {
     w[0] = w[1] = w[2] = w[3] = 0;
-    if (row >= rows) return;
+    if (row >= rows || c0 >= cols) return;
     const uint8_t *src = X + row * ld + c0;
+    if (c0 + 16 <= cols && ((uintptr_t)src & 15) == 0) {
+        const uint4 v = *(const uint4 *)src;
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+        return;
+    }
     for (int b = 0; b < 16; ++b)
         if (c0 + b < cols) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
 }

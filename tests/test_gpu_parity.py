@@ -514,7 +514,8 @@ def test_fused_small_qadic_matches_staged_calls_and_oracle(torch, p, m, n, k):
 
 
 @pytest.mark.parametrize("p,m,n,k", [(3, 64, 64, 64), (2, 1, 1, 1), (251, 65, 130, 33), (101, 100, 70, 70),
-                                     (7, 50, 45, 200), (13, 129, 3, 700), (251, 8, 8, 4096)])
+                                     (7, 50, 45, 200), (13, 129, 3, 700), (251, 8, 8, 4096),
+                                     (101, 300, 260, 700), (31, 777, 65, 1000)])
 def test_small_int8_one_launch_matches_staged_calls_and_oracle(torch, p, m, n, k):
     # qmm_gemm_mod_p runs small unblocked INT8 products in one launch that centres A
     # and B and transposes B in LDS (no workspace); the staged calls convert B in HBM
