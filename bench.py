@@ -296,7 +296,8 @@ def run_batched(args, torch, qmm):
     results = {}
     ref_out = None
     # chosen: the autotuner's cost model, then its measuring stage on this batch
-    for name, flags in (("chosen", qmm.BATCH_MEASURE), ("fp64_qadic_batched", qmm.BATCH_FORCE_FP64)):
+    for name, flags in (("chosen", qmm.BATCH_MEASURE), ("raw_int8_no_pack", qmm.BATCH_RAW),
+                        ("fp64_qadic_batched", qmm.BATCH_FORCE_FP64)):
         batch = qmm.batched_create(dev, flags)
         batch.run()
         torch.cuda.synchronize()

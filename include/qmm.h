@@ -337,12 +337,20 @@ typedef struct qmm_batched qmm_batched;
 #define QMM_BATCH_SHAPE_128x128 0x400u
 #define QMM_BATCH_SHAPE_MASK    0x700u  /* other values under the mask are EINVAL */
 /* QMM_BATCH_MEASURE: the autotuner's second stage.  Builds the cost-model
- * assignment and one batch per uniform INT8 tile shape, times each (three graph
+ * assignment and one batch per uniform INT8 tile shape, with packed operands and
+ * again with raw tiles (QMM_BATCH_RAW), times each (three graph
  * replays after a warm-up, on a private stream, synchronised) on the problems' own
  * buffers, and keeps the fastest.  Every candidate computes the same C_i, so the
  * outputs hold the products when the call returns.  Not combinable with
  * QMM_BATCH_FORCE_FP64 or QMM_BATCH_SHAPE_* (EINVAL). */
 #define QMM_BATCH_MEASURE       0x1000u
+/* QMM_BATCH_RAW: every product on INT8 tiles that read the products' own residue
+ * matrices (A's rows centred in registers, B's rows centred and transposed into
+ * on-chip memory): no pack kernel and no operand workspace, the graph is one kernel
+ * per tile shape.  Products of p <= 8 stay on INT8.  Not combinable with
+ * QMM_BATCH_FORCE_FP64 or QMM_BATCH_MEASURE (EINVAL); QMM_BATCH_MEASURE times the
+ * raw assignments next to the packed ones and keeps the fastest. */
+#define QMM_BATCH_RAW           0x2000u
 qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t flags,
                               qmm_batched **out);
 

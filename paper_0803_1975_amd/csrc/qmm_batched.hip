@@ -257,6 +257,36 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 // segments of a last, 64-byte stage past kp are not loaded.
 __device__ __forceinline__ ix4 gload16(const int8_t *p) { return *(const QMM_GLOBAL ix4 *)p; }
 
+// 16 bytes of a residue matrix from p (any alignment), bytes at positions >= valid
+// zero.  When the dword-aligned 20-byte window around them lies inside the
+// matrix's data [lo, hi) they come from one 16-byte and one 4-byte load and
+// byte-aligning shifts; otherwise from single byte loads.
+__device__ __forceinline__ ix4 raw16(const uint8_t *p, int64_t valid, const uint8_t *lo, const uint8_t *hi) {
+    uint32_t o[4] = {0, 0, 0, 0};
+    if (valid > 0) {
+        const uintptr_t a = (uintptr_t)p;
+        const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
+        if (base >= lo && base + 20 <= hi) {
+            const u32x4a4 v = *(const QMM_GLOBAL u32x4a4 *)base;
+            const uint32_t w[5] = {v.x, v.y, v.z, v.w, *(const QMM_GLOBAL uint32_t *)(base + 16)};
+            const uint32_t sh = (uint32_t)(a & 3);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] = sh ? __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh) : w[j];
+            if (valid < 16) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t left = valid - 4 * j;
+                    o[j] &= left >= 4 ? 0xffffffffu : (left <= 0 ? 0u : (1u << (8 * left)) - 1u);
+                }
+            }
+        } else {
+            const int nb = valid < 16 ? (int)valid : 16;
+            for (int b = 0; b < nb; ++b) o[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)p)[b] << (8 * (b & 3));
+        }
+    }
+    return ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
+}
+
 // An accumulator register as an integer: int32 for INT8 tiles, an FP32 exact
 // integer (|x| <= 2^24) for FP4 tiles.
 __device__ __forceinline__ int32_t acc_value(int32_t bits, bool fp4) {
@@ -266,7 +296,10 @@ __device__ __forceinline__ int32_t acc_value(int32_t bits, bool fp4) {
 constexpr int KT = 128;            // K stage (bytes)
 constexpr int PT = KT + 16;        // LDS row pitch: 8 lanes reading 8 rows hit distinct banks
 constexpr int KP_ALIGN = 64;       // workspace rows: k rounded up to this
-template <int BM, int BN, int WGM, int WGN, bool FP4>
+// RAW: the operands come straight from the products' own residue matrices (no pack
+// kernel, no workspace): A's 16-byte row segments are centred in registers, and B's
+// k-rows, centred, are stored into LDS transposed byte by byte.
+template <int BM, int BN, int WGM, int WGN, bool FP4, bool RAW = false>
 __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
     constexpr int SEGS = KT / 16;
@@ -276,8 +309,9 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
-    const int kp = D.kpb;  // bytes per packed row (k values for INT8, half of them for FP4)
+    const int kp = RAW ? D.k : D.kpb;  // bytes per packed row (k values for INT8, half of them for FP4)
     constexpr bool fp4 = FP4;  // the tile list of an FP4 class holds only FP4 products
+    static_assert(!(RAW && FP4), "raw tiles are INT8");
     const int stages = (kp + KT - 1) / KT;
 
     // Thread tid stages the 16-byte segment seg = tid % 8 of rows tid / 8 + 32 i: the
@@ -285,18 +319,37 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     static_assert(A_SEGS % NT == 0 && B_SEGS % NT == 0, "whole rows per load step");
     constexpr int RSTEP = NT / SEGS;
     const int seg = tid % SEGS, rfirst = tid / SEGS;
-    const int8_t *a_base = D.Ac + (row0 + rfirst) * kp + 16 * seg;
-    const int8_t *b_base = D.Bt + (col0 + rfirst) * kp + 16 * seg;
+    const int8_t *a_base = RAW ? nullptr : D.Ac + (row0 + rfirst) * kp + 16 * seg;
+    const int8_t *b_base = RAW ? nullptr : D.Bt + (col0 + rfirst) * kp + 16 * seg;
     const int slot = rfirst * PT + 16 * seg;
     const int64_t rstride = (int64_t)RSTEP * kp;
+    // RAW: B segment c = tid + NT i is k-row c / CSEG of the stage, columns 16 (c % CSEG) ..
+    constexpr int CSEG = BN / 16;
+    const uint8_t *a_lo = D.A, *a_hi = D.A + (D.m > 0 && D.k > 0 ? (int64_t)(D.m - 1) * D.lda + D.k : 0);
+    const uint8_t *b_lo = D.B, *b_hi = D.B + (D.k > 0 && D.n > 0 ? (int64_t)(D.k - 1) * D.ldb + D.n : 0);
     ix4 ra[A_LOADS], rb[B_LOADS];
     auto fetch = [&](int st) __attribute__((always_inline)) {
         const int k0 = st * KT;
-        const bool ok = k0 + 16 * seg < kp;
+        if constexpr (RAW) {
+            const int64_t kk = k0 + 16 * seg;
 #pragma unroll
-        for (int i = 0; i < A_LOADS; ++i) ra[i] = ok ? gload16(a_base + i * rstride + k0) : ix4{0, 0, 0, 0};
+            for (int i = 0; i < A_LOADS; ++i) {
+                const int64_t row = row0 + rfirst + i * RSTEP;
+                ra[i] = raw16(D.A + row * D.lda + kk, row < D.m ? D.k - kk : 0, a_lo, a_hi);
+            }
 #pragma unroll
-        for (int i = 0; i < B_LOADS; ++i) rb[i] = ok ? gload16(b_base + i * rstride + k0) : ix4{0, 0, 0, 0};
+            for (int i = 0; i < B_LOADS; ++i) {
+                const int c = tid + NT * i;
+                const int64_t krow = k0 + c / CSEG, col = col0 + 16 * (c % CSEG);
+                rb[i] = raw16(D.B + krow * D.ldb + col, krow < D.k ? D.n - col : 0, b_lo, b_hi);
+            }
+        } else {
+            const bool ok = k0 + 16 * seg < kp;
+#pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) ra[i] = ok ? gload16(a_base + i * rstride + k0) : ix4{0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < B_LOADS; ++i) rb[i] = ok ? gload16(b_base + i * rstride + k0) : ix4{0, 0, 0, 0};
+        }
     };
 
     ix16 acc[FM][FN];
@@ -305,17 +358,38 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
 #pragma unroll
         for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
     auto publish = [&]() __attribute__((always_inline)) {
+        if constexpr (RAW) {
 #pragma unroll
-        for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
+            for (int i = 0; i < A_LOADS; ++i) {
+                const ix4 v = ra[i];
+                *(ix4 *)&lds[slot + i * RSTEP * PT] =
+                    ix4{(int)centre4((uint32_t)v.x, D.add_h, D.neg_p), (int)centre4((uint32_t)v.y, D.add_h, D.neg_p),
+                        (int)centre4((uint32_t)v.z, D.add_h, D.neg_p), (int)centre4((uint32_t)v.w, D.add_h, D.neg_p)};
+            }
 #pragma unroll
-        for (int i = 0; i < B_LOADS; ++i) *(ix4 *)&lds[BM * PT + slot + i * RSTEP * PT] = rb[i];
+            for (int i = 0; i < B_LOADS; ++i) {
+                const int c = tid + NT * i, kr = c / CSEG, cs = c % CSEG;
+                const uint32_t w[4] = {centre4((uint32_t)rb[i].x, D.add_h, D.neg_p),
+                                       centre4((uint32_t)rb[i].y, D.add_h, D.neg_p),
+                                       centre4((uint32_t)rb[i].z, D.add_h, D.neg_p),
+                                       centre4((uint32_t)rb[i].w, D.add_h, D.neg_p)};
+                uint8_t *dst = &lds[BM * PT + (16 * cs) * PT + kr];
+#pragma unroll
+                for (int b = 0; b < 16; ++b) dst[b * PT] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
+#pragma unroll
+            for (int i = 0; i < B_LOADS; ++i) *(ix4 *)&lds[BM * PT + slot + i * RSTEP * PT] = rb[i];
+        }
         __syncthreads();
     };
     auto compute = [&](int st) __attribute__((always_inline)) {
         const uint8_t *sA = lds, *sB = lds + BM * PT;
         // 32 bytes of each row per MFMA step: 32 k of int8, or 64 k of e2m1 codes into
         // the FP4 form (FP32 accumulators in the same registers, bit-cast)
-        const int ksteps = min(KT, kp - st * KT) / 32;
+        const int ksteps = (min(KT, kp - st * KT) + 31) / 32;  // bytes past k are zero
         for (int ks = 0; ks < ksteps; ++ks) {
             ix4 bf[FN];
 #pragma unroll
@@ -491,14 +565,14 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // One persistent kernel per tile class (so each gets the registers and occupancy
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
-template <uint32_t SHAPE, bool FP4>
+template <uint32_t SHAPE, bool FP4, bool RAW = false>
 __global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 ? 7 : 5))
 void batched_int8_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles, int32_t ntiles) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PT];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
-        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_wgm(SHAPE), 4 / shape_wgm(SHAPE), FP4>(D, tr.tm, tr.tn, lds);
+        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_wgm(SHAPE), 4 / shape_wgm(SHAPE), FP4, RAW>(D, tr.tm, tr.tn, lds);
     }
 }
 
@@ -610,6 +684,7 @@ struct qmm_batched {
     int8_t *d_ws = nullptr;   // centred, padded INT8 operands
     size_t ws_bytes = 0;
     int32_t class_first[kClasses] = {}, class_count[kClasses] = {};
+    bool raw = false;               // INT8 tiles read the residue matrices themselves (no pack kernel)
     hipStream_t capture = nullptr;  // the stream the graph was recorded on
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -631,6 +706,8 @@ void release(qmm_batched *b) {
 
 qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, qmm_batched *b) {
     b->count = count;
+    b->raw = (flags & QMM_BATCH_RAW) != 0;
+    if (b->raw) flags |= QMM_BATCH_INT8_ONLY;  // raw tiles centre bytes; FP4 codes need the pack
     b->plans.resize((size_t)count);
     std::vector<Desc> descs((size_t)count);
     std::vector<std::pair<double, TileRef>> tiles[kClasses];
@@ -705,7 +782,9 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         }
         b->plans[(size_t)i] = pl;
         if (P.m == 0 || P.n == 0) continue;
-        if (lowp) {
+        if (lowp && b->raw) {
+            D.kp = D.kpb = D.k;  // operands read in place
+        } else if (lowp) {
             // workspace: Ac (mp x kpb) then Bt (np x kpb), each 256-byte aligned
             D.kp = (int32_t)(ceil_div(P.k, KP_ALIGN) * KP_ALIGN);
             D.kpb = D.fp4 ? D.kp / 2 : D.kp;
@@ -739,10 +818,13 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         (const void *)batched_int8_kernel<SHAPE_64x64, true>,   (const void *)batched_int8_kernel<SHAPE_32x128, true>,
         (const void *)batched_int8_kernel<SHAPE_128x32, true>,  (const void *)batched_int8_kernel<SHAPE_128x128, true>,
         (const void *)batched_fp64_kernel};
+    const void *kraw[SHAPE_COUNT] = {
+        (const void *)batched_int8_kernel<SHAPE_64x64, false, true>,  (const void *)batched_int8_kernel<SHAPE_32x128, false, true>,
+        (const void *)batched_int8_kernel<SHAPE_128x32, false, true>, (const void *)batched_int8_kernel<SHAPE_128x128, false, true>};
     int grid[kClasses];
     for (int c = 0; c < kClasses; ++c) {
         int per_cu = 1;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfun[c], NT, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (b->raw && c < SHAPE_COUNT) ? kraw[c] : kfun[c], NT, 0);
         grid[c] = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)tiles[c].size(), (int64_t)cus * std::max(1, per_cu)));
     }
     // Per class, longest first (stable, so the tiles of a product stay together).
@@ -813,6 +895,16 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         const Desc *dd = b->d_desc;
         const TileRef *tt = b->d_tiles + b->class_first[c];
         const int32_t nt = b->class_count[c];
+        if (b->raw && c < SHAPE_COUNT) {
+            switch (c) {
+            case 0: batched_int8_kernel<SHAPE_64x64, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+            case 1: batched_int8_kernel<SHAPE_32x128, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+            case 2: batched_int8_kernel<SHAPE_128x32, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+            default: batched_int8_kernel<SHAPE_128x128, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+            }
+            if (le == hipSuccess) le = hipGetLastError();
+            continue;
+        }
         switch (c) {
         case 0: batched_int8_kernel<SHAPE_64x64, false><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
         case 1: batched_int8_kernel<SHAPE_32x128, false><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
@@ -866,9 +958,19 @@ qmm_status create_measured(int64_t count, const qmm_problem *probs, uint32_t fla
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) st = hip_fail(e, "event");
     qmm_batched *best = nullptr;
     float best_ms = 0.f;
-    for (uint32_t c = 0; c <= SHAPE_COUNT && st == QMM_OK; ++c) {
+    // candidates 0 .. SHAPE_COUNT: the packed operands (cost model, then each shape
+    // everywhere); the same again with raw tiles (no pack kernel), skipped when some
+    // product cannot take them
+    for (uint32_t c = 0; c <= 2 * SHAPE_COUNT + 1 && st == QMM_OK; ++c) {
+        const bool raw = c > SHAPE_COUNT;
+        const uint32_t shape = raw ? c - SHAPE_COUNT - 1 : c;  // 0 = cost model, else 1 + shape
         qmm_batched *b = new qmm_batched();
-        st = build_batch(count, probs, flags | (c << 8), b);  // c = 0: cost model; c >= 1: shape c - 1 everywhere
+        st = build_batch(count, probs, flags | (shape << 8) | (raw ? QMM_BATCH_RAW : 0u), b);
+        if (raw && st == QMM_EUNSUPPORTED) {
+            release(b);
+            st = QMM_OK;
+            continue;
+        }
         float ms = 0.f;
         if (st == QMM_OK) st = time_batch(b, s, e0, e1, 3, &ms);
         if (st == QMM_OK && (!best || ms < best_ms)) {
@@ -896,8 +998,10 @@ extern "C" qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs
     if (!out) return fail(QMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 0 || (count > 0 && !probs)) return fail(QMM_EINVAL, "bad problem array");
-    if (flags & ~(QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK | QMM_BATCH_MEASURE | QMM_BATCH_INT8_ONLY))
+    if (flags & ~(QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK | QMM_BATCH_MEASURE | QMM_BATCH_INT8_ONLY | QMM_BATCH_RAW))
         return fail(QMM_EINVAL, "unknown flags");
+    if ((flags & QMM_BATCH_RAW) && (flags & (QMM_BATCH_FORCE_FP64 | QMM_BATCH_MEASURE)))
+        return fail(QMM_EINVAL, "QMM_BATCH_RAW is an INT8 layout; QMM_BATCH_MEASURE tries it by itself");
     if (((flags & QMM_BATCH_SHAPE_MASK) >> 8) > SHAPE_COUNT) return fail(QMM_EINVAL, "unknown tile shape flag");
     if ((flags & QMM_BATCH_MEASURE) && (flags & (QMM_BATCH_FORCE_FP64 | QMM_BATCH_SHAPE_MASK)))
         return fail(QMM_EINVAL, "QMM_BATCH_MEASURE chooses the INT8 tile shapes itself");

@@ -30,6 +30,7 @@ BATCH_FORCE_FP64 = 1
 BATCH_INT8_ONLY = 2
 BATCH_SHAPE_64x64, BATCH_SHAPE_32x128, BATCH_SHAPE_128x32, BATCH_SHAPE_128x128 = 0x100, 0x200, 0x300, 0x400
 BATCH_MEASURE = 0x1000
+BATCH_RAW = 0x2000
 N_BATCH_COSTS = 8  # (fixed, per_stage) for each of the four INT8 tile shapes
 # unpack selectors
 ROWS_REV, COLS_FWD, ROWS_FWD = 0, 1, 2

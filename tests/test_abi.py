@@ -94,10 +94,11 @@ def test_batched_argument_checks():
     # flags and cost vectors are checked on the host, before any device call
     L = qmm.lib()
     out = ctypes.c_void_p()
-    for bad in (0x500, 0x700, 0x800, 4, 0x2000):
+    for bad in (0x500, 0x700, 0x800, 4, 0x4000):
         assert L.qmm_batched_create(0, None, bad, ctypes.byref(out)) == qmm.EINVAL, hex(bad)
         assert not out.value
-    for bad in (qmm.BATCH_MEASURE | qmm.BATCH_FORCE_FP64, qmm.BATCH_MEASURE | qmm.BATCH_SHAPE_128x128):
+    for bad in (qmm.BATCH_MEASURE | qmm.BATCH_FORCE_FP64, qmm.BATCH_MEASURE | qmm.BATCH_SHAPE_128x128,
+                qmm.BATCH_RAW | qmm.BATCH_FORCE_FP64, qmm.BATCH_RAW | qmm.BATCH_MEASURE):
         assert L.qmm_batched_create(0, None, bad, ctypes.byref(out)) == qmm.EINVAL, hex(bad)
     assert L.qmm_batched_create(0, None, 0, None) == qmm.EINVAL
     assert L.qmm_batched_create(-1, None, 0, ctypes.byref(out)) == qmm.EINVAL

@@ -50,7 +50,9 @@ EDGE_SHAPES = [(7, 1, 1, 1), (3, 16, 16, 16), (101, 17, 33, 5), (2, 513, 31, 70)
 
 @pytest.mark.parametrize("flags", [0, qmm.BATCH_SHAPE_64x64, qmm.BATCH_SHAPE_32x128, qmm.BATCH_SHAPE_128x32,
                                    qmm.BATCH_SHAPE_128x128, qmm.BATCH_FORCE_FP64, qmm.BATCH_INT8_ONLY,
-                                   qmm.BATCH_INT8_ONLY | qmm.BATCH_SHAPE_128x128])
+                                   qmm.BATCH_INT8_ONLY | qmm.BATCH_SHAPE_128x128, qmm.BATCH_RAW,
+                                   qmm.BATCH_RAW | qmm.BATCH_SHAPE_64x64, qmm.BATCH_RAW | qmm.BATCH_SHAPE_32x128,
+                                   qmm.BATCH_RAW | qmm.BATCH_SHAPE_128x32, qmm.BATCH_RAW | qmm.BATCH_SHAPE_128x128])
 def test_batched_edge_shapes(torch, flags):
     note("edge", flags)
     host, dev = make_problems(torch, EDGE_SHAPES, 10 + flags)
@@ -64,7 +66,7 @@ def test_batched_edge_shapes(torch, flags):
             assert pl.p == p
             if flags & qmm.BATCH_FORCE_FP64:
                 want = qmm.PATH_FP64_QADIC
-            elif p <= 8 and not flags & qmm.BATCH_INT8_ONLY:
+            elif p <= 8 and not flags & (qmm.BATCH_INT8_ONLY | qmm.BATCH_RAW):
                 want = qmm.PATH_FP4                   # every edge k here is one exact FP32 block
             else:
                 want = qmm.PATH_INT8
@@ -73,13 +75,14 @@ def test_batched_edge_shapes(torch, flags):
         batch.destroy()
 
 
-def test_graph_replays_match_eager_results(torch):
+@pytest.mark.parametrize("flags", [0, qmm.BATCH_RAW])
+def test_graph_replays_match_eager_results(torch, flags):
     shapes = synth.batched_shapes(count=300, seed=7)
     host, dev = make_problems(torch, shapes, 7)
-    batch = qmm.batched_create(dev)
+    batch = qmm.batched_create(dev, flags)
     try:
         for replay in range(4):
-            note("replay", replay)
+            note("replay", flags, replay)
             for _, _, dC, _ in dev:
                 dC.zero_()                              # eager work between replays
             torch.cuda.synchronize()
@@ -98,7 +101,7 @@ def test_batched_workload_2000_products(torch):
     for (p, m, n, k), (A, B) in zip(shapes, inputs):
         dev.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
                     torch.full((m, n), 255, dtype=torch.uint8, device="cuda"), p))
-    for flags in (0, qmm.BATCH_INT8_ONLY, qmm.BATCH_FORCE_FP64):
+    for flags in (0, qmm.BATCH_INT8_ONLY, qmm.BATCH_FORCE_FP64, qmm.BATCH_RAW):
         note("workload", flags)
         batch = qmm.batched_create(dev, flags)
         try:
@@ -157,3 +160,33 @@ def test_batched_rejects_bad_problems(torch):
     with pytest.raises(qmm.QmmError) as ei:
         qmm.batched_create([(big, bigB, C, 251)])
     assert ei.value.status == qmm.EUNSUPPORTED
+
+
+def test_raw_batches_read_strided_operands(torch):
+    # raw tiles read A and B in place: operands that are views with padded rows and
+    # odd starting columns, C a view too; bytes outside the views stay untouched
+    rng = np.random.default_rng(21)
+    host, dev, bigs = [], [], []
+    for p, m, n, k in [(7, 70, 45, 33), (101, 129, 130, 257), (3, 5, 300, 17), (251, 64, 1, 64)]:
+        Ab = rng.integers(0, p, (m, k + 13), dtype=np.uint8)
+        Bb = rng.integers(0, p, (k, n + 7), dtype=np.uint8)
+        A, B = Ab[:, 5:5 + k], Bb[:, 3:3 + n]
+        Cb = torch.full((m + 2, n + 9), 0xEE, dtype=torch.uint8, device="cuda")
+        dA = torch.from_numpy(Ab).cuda()[:, 5:5 + k]
+        dB = torch.from_numpy(Bb).cuda()[:, 3:3 + n]
+        host.append((np.ascontiguousarray(A), np.ascontiguousarray(B), p))
+        dev.append((dA, dB, Cb[1:m + 1, 2:n + 2], p))
+        bigs.append(Cb)
+    batch = qmm.batched_create(dev, qmm.BATCH_RAW)
+    try:
+        batch.run()
+        torch.cuda.synchronize()
+        check_all(host, dev)
+        for (A, B, p), Cb in zip(host, bigs):
+            out = Cb.cpu().numpy()
+            m, n = A.shape[0], B.shape[1]
+            mask = np.ones_like(out, dtype=bool)
+            mask[1:m + 1, 2:n + 2] = False
+            assert (out[mask] == 0xEE).all()
+    finally:
+        batch.destroy()
