@@ -240,7 +240,7 @@ def plan_dict(qmm, pl):
     return out
 
 
-def cpu_baseline(A, B, p, C_gpu, target_s):
+def cpu_baseline(A, B, p, C_gpu, target_s, single_core=False):
     """The oracle (never tuned) on the first R rows, R sized for about target_s seconds."""
     from oracle import reference as ref
     import numpy as np
@@ -255,9 +255,23 @@ def cpu_baseline(A, B, p, C_gpu, target_s):
     Cs = ref.modmul(A[:rows], B, p)
     dt = time.perf_counter() - t0
     ok = bool(np.array_equal(Cs, C_gpu[:rows]))
-    return {"value": rows * n * k / dt / 1e9, "unit": "mod-p GMAC/s", "cores": ref.oracle_threads(),
-            "kind": "oracle", "sample": f"first {rows} of {m} rows of A times B ({rows}x{n}x{k} MACs), {dt:.2f} s",
-            "matches_gpu_rows": ok}
+    out = {"value": rows * n * k / dt / 1e9, "unit": "mod-p GMAC/s", "cores": ref.oracle_threads(),
+           "kind": "oracle", "sample": f"first {rows} of {m} rows of A times B ({rows}x{n}x{k} MACs), {dt:.2f} s",
+           "matches_gpu_rows": ok}
+    if single_core:
+        # the same oracle on one thread, on a sample sized for about a quarter of the time
+        threads = ref.oracle_threads()
+        ref.set_oracle_threads(1)
+        try:
+            r1 = int(min(m, max(1, rows // max(1, 4 * threads))))
+            t0 = time.perf_counter()
+            ref.modmul(A[:r1], B, p)
+            dt1 = time.perf_counter() - t0
+        finally:
+            ref.set_oracle_threads(threads)
+        out["single_core"] = {"value": r1 * n * k / max(dt1, 1e-9) / 1e9, "unit": "mod-p GMAC/s", "cores": 1,
+                              "sample": f"first {r1} rows ({r1}x{n}x{k} MACs), {dt1:.2f} s"}
+    return out
 
 
 def run_batched(args, torch, qmm):
@@ -667,7 +681,8 @@ def main():
                             "with GotoBLAS dgemm; context, not a target")
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a row sample")
-        out["cpu_baseline"] = cpu_baseline(A, B, p, reference_C.cpu().numpy(), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A, B, p, reference_C.cpu().numpy(), args.cpu_seconds,
+                                           single_core=args.workload in ("small", "square"))
     print(json.dumps(out), flush=True)
 
 

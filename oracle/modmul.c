@@ -76,3 +76,14 @@ int qmm_oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following products (n >= 1; the benchmark times the oracle on all
+ * host cores and on one). */
+void qmm_oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -33,6 +33,8 @@ def _load():
         lib.qmm_oracle_modmul_entries.restype = ctypes.c_int
         lib.qmm_oracle_threads.argtypes = []
         lib.qmm_oracle_threads.restype = ctypes.c_int
+        lib.qmm_oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.qmm_oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -84,6 +86,11 @@ def modmul_entries(A: np.ndarray, B: np.ndarray, p: int, rows, cols) -> np.ndarr
 def oracle_threads() -> int:
     """Number of OpenMP threads the C oracle runs with."""
     return int(_load().qmm_oracle_threads())
+
+
+def set_oracle_threads(n: int) -> None:
+    """Run the following C oracle products on n threads."""
+    _load().qmm_oracle_set_threads(int(n))
 
 
 def modmul_bruteforce(A, B, p: int):
