@@ -195,8 +195,8 @@ qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, i
  * the fly, with no workspace.  Small products on an unblocked FP64 Q-adic plan
  * (m n k <= 2^22) run in one launch that packs the operands in on-chip memory and
  * need no workspace (qmm_gemm_workspace_size returns 0); so do unblocked INT8
- * products of m n k <= 2^29 with plan->tile == 0, which centre and transpose in
- * on-chip memory. */
+ * products of m n k <= 2^32 with plan->tile == 0, which run in one launch that
+ * centres both operands in on-chip memory. */
 qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, uint32_t p,
                           const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
                           uint8_t *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);

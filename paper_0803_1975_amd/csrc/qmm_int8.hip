@@ -537,9 +537,16 @@ void centre_consts(uint32_t p, uint32_t &add_h, uint32_t &neg_p) {
 
 // A small INT8 product in one launch: one 256-thread workgroup per 64 x 64 tile of C
 // (2 x 2 wavefronts, one i32_32x32x32_i8 block each), 64-byte K stages.  A's rows
-// are centred on their way into LDS; B's rows are centred and stored transposed
-// into LDS byte by byte, so the product needs no conversion launch and no
-// workspace.  Unblocked plans only (k (p/2)^2 stays in int32).
+// are centred on their way into LDS; B's rows are centred and stored as they are
+// (k-major), and each wavefront reads its B fragments with the gfx950 LDS
+// transpose load, so the product needs no conversion launch and no workspace.
+// Unblocked plans only (k (p/2)^2 stays in int32).
+//
+// ds_read_b64_tr_b8 (measured with an in-bounds probe): within each group of 16
+// lanes, lane i receives byte i of the 8 x 16 byte block whose row b is the 8 bytes
+// at lane 2b's address followed by the 8 bytes at lane 2b+1's.  So if lane 2b + c of
+// group g points at k-row k0 + b and columns n0 + 8c, lane i of the group gets the
+// 8 bytes of column n0 + i from k-rows k0 .. k0 + 7: the MFMA B operand's order.
 struct SmallInt8Args {
     int64_t m, n, k;
     const uint8_t *A;
@@ -551,7 +558,8 @@ struct SmallInt8Args {
     int32_t tiles_n;
     uint32_t p, add_h, neg_p, off, magic32;
 };
-constexpr int SM_T = 64, SM_KT = 64, SM_PITCH = SM_KT + 16;
+constexpr int SM_T = 64, SM_KT = 64, SM_PITCH = SM_KT + 16, SM_BPITCH = SM_T + 16;
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 // 16 bytes of row `row` of X from column c0 (zero past rows or cols), as four words:
 // one 16-byte load when they are whole and aligned, byte loads otherwise.
@@ -574,7 +582,7 @@ __device__ __forceinline__ void load16(const uint8_t *__restrict__ X, int64_t ld
 
 __global__ __launch_bounds__(256) void small_int8_kernel(SmallInt8Args g) {
     __shared__ __attribute__((aligned(16))) uint8_t sA[SM_T * SM_PITCH];
-    __shared__ __attribute__((aligned(16))) uint8_t sB[SM_T * SM_PITCH];  // rows: columns of B
+    __shared__ __attribute__((aligned(16))) uint8_t sB[SM_KT * SM_BPITCH];  // rows: k, as B is stored
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t row0 = (int64_t)(blockIdx.x / (uint32_t)g.tiles_n) * SM_T;
@@ -591,14 +599,20 @@ __global__ __launch_bounds__(256) void small_int8_kernel(SmallInt8Args g) {
             wb[i] = centre4(wb[i], g.add_h, g.neg_p);
         }
         *(uint4 *)&sA[r * SM_PITCH + 16 * seg] = make_uint4(wa[0], wa[1], wa[2], wa[3]);
-#pragma unroll
-        for (int b = 0; b < 16; ++b) sB[(16 * seg + b) * SM_PITCH + r] = (uint8_t)(wb[b >> 2] >> (8 * (b & 3)));
+        *(uint4 *)&sB[r * SM_BPITCH + 16 * seg] = make_uint4(wb[0], wb[1], wb[2], wb[3]);
         __syncthreads();
+        // B fragment of lane l: column wn 32 + l % 32, k-bytes 16 (l / 32) .. + 15 of the
+        // k-step, as two transpose loads of 8 k each (group g = l / 16, lane 2b + c of it)
+        const int g = lane >> 4, sl = lane & 15;
+        const int b_off = (16 * (g >> 1) + (sl >> 1)) * SM_BPITCH + wn * 32 + 16 * (g & 1) + 8 * (sl & 1);
 #pragma unroll
         for (int ks = 0; ks < SM_KT / 32; ++ks) {
             const ix4 a = *(const ix4 *)&sA[(wm * 32 + (lane & 31)) * SM_PITCH + ks * 32 + 16 * (lane >> 5)];
-            const ix4 b = *(const ix4 *)&sB[(wn * 32 + (lane & 31)) * SM_PITCH + ks * 32 + 16 * (lane >> 5)];
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc, 0, 0, 0);
+            const uint8_t *bp = &sB[b_off + ks * 32 * SM_BPITCH];
+            const v2i b0 = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i *)bp);
+            const v2i b1 = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+                (__attribute__((address_space(3))) v2i *)(bp + 8 * SM_BPITCH));
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, ix4{b0.x, b0.y, b1.x, b1.y}, acc, 0, 0, 0);
         }
         __syncthreads();
     }

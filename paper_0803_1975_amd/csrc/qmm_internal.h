@@ -105,7 +105,7 @@ qmm_status launch_gemm_int8_small(const qmm_plan &pl, int64_t m, int64_t n, int6
                                   int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc,
                                   void *stream);
 // Largest m n k that qmm_gemm_mod_p runs on the one-launch INT8 kernel.
-constexpr double kSmallInt8MaxMacs = 536870912.0;  // 2^29: one launch is faster up to 768^3, slower at 1024^3 (measured)
+constexpr double kSmallInt8MaxMacs = 4294967296.0;  // 2^32: one launch measured faster up to 1536^3
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
                             uint8_t *C, int64_t ldc, void *stream);

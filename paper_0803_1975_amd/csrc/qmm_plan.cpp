@@ -312,10 +312,10 @@ extern "C" qmm_status qmm_choose_Qd(uint32_t p, int64_t m, int64_t n, int64_t k,
     uint32_t pth = (uint32_t)path;
     // Automatic choice: FP4 matrix cores (twice the INT8 rate, half the operand bytes)
     // when every centred residue is an e2m1 value and the product is large enough to
-    // repay FP4's extra conversion launch (measured crossover between 512^3 and 768^3
-    // multiply-adds), INT8 for other byte residues.
+    // repay FP4's conversion launch against INT8's one-launch kernel (measured
+    // crossover between 640^3 and 768^3 multiply-adds), INT8 for other byte residues.
     if (pth == QMM_PATH_AUTO) {
-        const bool fp4 = p <= 8 && (double)m * (double)n * (double)kk >= (double)(1ll << 28);
+        const bool fp4 = p <= 8 && (double)m * (double)n * (double)kk >= 3.8e8;
         pth = fp4 ? QMM_PATH_FP4 : (p <= 256 ? QMM_PATH_INT8 : QMM_PATH_FP64_QADIC);
     }
     if (pth > QMM_PATH_FP32_FULL) return fail(QMM_EINVAL, "unknown path");

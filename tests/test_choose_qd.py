@@ -122,7 +122,8 @@ def test_workload_plans():
         assert pl.path == (qmm.PATH_FP4 if p <= 8 else qmm.PATH_INT8) and pl.k_block == k
     for p in range(2, 257):
         want = qmm.PATH_FP4 if p <= 8 else qmm.PATH_INT8
-        assert qmm.choose_Qd(p, 1024, 1024, 256).path == want, p       # 2^28 multiply-adds
+        assert qmm.choose_Qd(p, 1024, 1024, 512).path == want, p       # 2^29 multiply-adds
+        assert qmm.choose_Qd(p, 1024, 1024, 256).path == qmm.PATH_INT8, p  # 2^28: INT8's one launch wins
         assert qmm.choose_Qd(p, 64, 64, 64).path == qmm.PATH_INT8, p   # too small to repay a launch
         assert p > 8 or bounds.fp4_representable(p)
 
