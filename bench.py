@@ -334,8 +334,10 @@ def run_batched(args, torch, qmm):
     results = {}
     ref_out = None
     # chosen: the autotuner's cost model, then its measuring stage on this batch
-    for name, flags in (("chosen", qmm.BATCH_MEASURE), ("raw_int8_no_pack", qmm.BATCH_RAW),
-                        ("fp64_qadic_batched", qmm.BATCH_FORCE_FP64)):
+    batched_variants = [("chosen", qmm.BATCH_MEASURE)]
+    if args.paths == "all":
+        batched_variants += [("raw_int8_no_pack", qmm.BATCH_RAW), ("fp64_qadic_batched", qmm.BATCH_FORCE_FP64)]
+    for name, flags in batched_variants:
         batch = qmm.batched_create(dev, flags)
         batch.run()
         torch.cuda.synchronize()
@@ -358,7 +360,8 @@ def run_batched(args, torch, qmm):
         batch.destroy()
 
     # one qmm_gemm_mod_p call per product (plans and workspaces made beforehand)
-    for name, path in (("fp64_qadic_per_product", qmm.PATH_FP64_QADIC), ("int8_per_product", qmm.PATH_INT8)):
+    per_product = (("fp64_qadic_per_product", qmm.PATH_FP64_QADIC), ("int8_per_product", qmm.PATH_INT8))
+    for name, path in (per_product if args.paths == "all" else ()):
         calls = []
         for (dA, dB, dC, p) in dev:
             m, k = dA.shape
@@ -395,7 +398,8 @@ def run_batched(args, torch, qmm):
                      "op": "residue bytes read and written (A, B, C of every product) per replay",
                      "avg_launch_ms": chosen["ms_per_step"]},
         "paths": results,
-        "speedup_vs_plain_fp64_qadic": chosen["gmacs"] / results["fp64_qadic_per_product"]["gmacs"],
+        "speedup_vs_plain_fp64_qadic": (chosen["gmacs"] / results["fp64_qadic_per_product"]["gmacs"]
+                                        if "fp64_qadic_per_product" in results else None),
     }
     if not args.no_cpu:
         from oracle import reference as ref

@@ -47,6 +47,7 @@ typedef float fx16 __attribute__((ext_vector_type(16)));
 typedef unsigned int ux2 __attribute__((ext_vector_type(2)));
 typedef double dx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int uint4v __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 // Global-address-space accesses: pointers read from a descriptor in memory are
 // otherwise generic, and a generic (flat) access also counts against the LDS
@@ -258,30 +259,48 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 __device__ __forceinline__ ix4 gload16(const int8_t *p) { return *(const QMM_GLOBAL ix4 *)p; }
 
 // 16 bytes of a residue matrix from p (any alignment), bytes at positions >= valid
-// zero.  When the dword-aligned 20-byte window around them lies inside the
-// matrix's data [lo, hi) they come from one 16-byte and one 4-byte load and
-// byte-aligning shifts; otherwise from single byte loads.
-__device__ __forceinline__ ix4 raw16(const uint8_t *p, int64_t valid, const uint8_t *lo, const uint8_t *hi) {
-    uint32_t o[4] = {0, 0, 0, 0};
+// zero, in two halves so that all of a stage's loads are in flight before any of
+// them is waited for.  raw_issue starts the loads into w: one 16-byte and one
+// 4-byte load of the dword-aligned 20-byte window when it lies inside the matrix's
+// data [lo, hi), else the bytes one by one; it records the byte shift and the
+// valid count in meta.  raw_finish, called once the data is needed, aligns the
+// bytes and zeroes those past valid.
+__device__ __forceinline__ void raw_issue(uint32_t (&w)[5], int32_t &meta, const uint8_t *p, int64_t valid,
+                                          const uint8_t *lo, const uint8_t *hi) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) w[j] = 0;
+    meta = 0;
     if (valid > 0) {
+        const int32_t v = valid < 16 ? (int32_t)valid : 16;
         const uintptr_t a = (uintptr_t)p;
         const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
         if (base >= lo && base + 20 <= hi) {
-            const u32x4a4 v = *(const QMM_GLOBAL u32x4a4 *)base;
-            const uint32_t w[5] = {v.x, v.y, v.z, v.w, *(const QMM_GLOBAL uint32_t *)(base + 16)};
-            const uint32_t sh = (uint32_t)(a & 3);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) o[j] = sh ? __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh) : w[j];
-            if (valid < 16) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int64_t left = valid - 4 * j;
-                    o[j] &= left >= 4 ? 0xffffffffu : (left <= 0 ? 0u : (1u << (8 * left)) - 1u);
-                }
-            }
+            const u32x4a4 x = *(const QMM_GLOBAL u32x4a4 *)base;
+            w[0] = x.x;
+            w[1] = x.y;
+            w[2] = x.z;
+            w[3] = x.w;
+            w[4] = *(const QMM_GLOBAL uint32_t *)(base + 16);
+            meta = v | (int32_t)(a & 3) << 8;
         } else {
-            const int nb = valid < 16 ? (int)valid : 16;
-            for (int b = 0; b < nb; ++b) o[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)p)[b] << (8 * (b & 3));
+#pragma unroll
+            for (int b = 0; b < 16; ++b)
+                if (b < v) w[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)p)[b] << (8 * (b & 3));
+            meta = v;
+        }
+    }
+}
+__device__ __forceinline__ ix4 raw_finish(const uint32_t (&w)[5], int32_t meta) {
+    const uint32_t sh = (uint32_t)(meta >> 8) & 3u;
+    const int32_t v = meta & 0xff;
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
+    if (v < 16) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t left = v - 4 * j;
+            o[j] &= left >= 4 ? 0xffffffffu : (left <= 0 ? 0u : (1u << (8 * left)) - 1u);
         }
     }
     return ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
@@ -296,9 +315,17 @@ __device__ __forceinline__ int32_t acc_value(int32_t bits, bool fp4) {
 constexpr int KT = 128;            // K stage (bytes)
 constexpr int PT = KT + 16;        // LDS row pitch: 8 lanes reading 8 rows hit distinct banks
 constexpr int KP_ALIGN = 64;       // workspace rows: k rounded up to this
+// LDS pitch of B's k-rows in raw tiles: 8 lanes reading 8 consecutive rows at one
+// column hit distinct banks for every tile width used here (32, 64, 128).
+constexpr int raw_bpitch(int bn) { return bn + 16; }
+// LDS bytes of one tile: A rows, then B (n-rows of packed codes, or k-rows when raw)
+constexpr int tile_lds_bytes(int bm, int bn, bool raw) {
+    return bm * PT + (raw && KT * raw_bpitch(bn) > bn * PT ? KT * raw_bpitch(bn) : bn * PT);
+}
 // RAW: the operands come straight from the products' own residue matrices (no pack
 // kernel, no workspace): A's 16-byte row segments are centred in registers, and B's
-// k-rows, centred, are stored into LDS transposed byte by byte.
+// k-rows, centred, go to LDS as they are (k-major); the MFMA's B fragments are read
+// from them with the LDS transpose load.
 template <int BM, int BN, int WGM, int WGN, bool FP4, bool RAW = false>
 __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
@@ -328,6 +355,10 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     const uint8_t *a_lo = D.A, *a_hi = D.A + (D.m > 0 && D.k > 0 ? (int64_t)(D.m - 1) * D.lda + D.k : 0);
     const uint8_t *b_lo = D.B, *b_hi = D.B + (D.k > 0 && D.n > 0 ? (int64_t)(D.k - 1) * D.ldb + D.n : 0);
     ix4 ra[A_LOADS], rb[B_LOADS];
+    // RAW: the windows of a stage's segments, finished into ra / rb when published
+    constexpr int RA = RAW ? A_LOADS : 1, RB = RAW ? B_LOADS : 1;
+    uint32_t wa[RA][5], wb[RB][5];
+    int32_t ma[RA], mb[RB];
     auto fetch = [&](int st) __attribute__((always_inline)) {
         const int k0 = st * KT;
         if constexpr (RAW) {
@@ -335,13 +366,13 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
 #pragma unroll
             for (int i = 0; i < A_LOADS; ++i) {
                 const int64_t row = row0 + rfirst + i * RSTEP;
-                ra[i] = raw16(D.A + row * D.lda + kk, row < D.m ? D.k - kk : 0, a_lo, a_hi);
+                raw_issue(wa[i], ma[i], D.A + row * D.lda + kk, row < D.m ? D.k - kk : 0, a_lo, a_hi);
             }
 #pragma unroll
             for (int i = 0; i < B_LOADS; ++i) {
                 const int c = tid + NT * i;
                 const int64_t krow = k0 + c / CSEG, col = col0 + 16 * (c % CSEG);
-                rb[i] = raw16(D.B + krow * D.ldb + col, krow < D.k ? D.n - col : 0, b_lo, b_hi);
+                raw_issue(wb[i], mb[i], D.B + krow * D.ldb + col, krow < D.k ? D.n - col : 0, b_lo, b_hi);
             }
         } else {
             const bool ok = k0 + 16 * seg < kp;
@@ -360,6 +391,21 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     auto publish = [&]() __attribute__((always_inline)) {
         if constexpr (RAW) {
 #pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) ra[i] = raw_finish(wa[i], ma[i]);
+#pragma unroll
+            for (int i = 0; i < B_LOADS; ++i) rb[i] = raw_finish(wb[i], mb[i]);
+            if (D.neg_p == 0) {  // residues below 128, sum exact uncentred: bytes as they are
+#pragma unroll
+                for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
+#pragma unroll
+                for (int i = 0; i < B_LOADS; ++i) {
+                    const int c = tid + NT * i;
+                    *(ix4 *)&lds[BM * PT + (c / CSEG) * raw_bpitch(BN) + 16 * (c % CSEG)] = rb[i];
+                }
+                __syncthreads();
+                return;
+            }
+#pragma unroll
             for (int i = 0; i < A_LOADS; ++i) {
                 const ix4 v = ra[i];
                 *(ix4 *)&lds[slot + i * RSTEP * PT] =
@@ -369,13 +415,9 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
 #pragma unroll
             for (int i = 0; i < B_LOADS; ++i) {
                 const int c = tid + NT * i, kr = c / CSEG, cs = c % CSEG;
-                const uint32_t w[4] = {centre4((uint32_t)rb[i].x, D.add_h, D.neg_p),
-                                       centre4((uint32_t)rb[i].y, D.add_h, D.neg_p),
-                                       centre4((uint32_t)rb[i].z, D.add_h, D.neg_p),
-                                       centre4((uint32_t)rb[i].w, D.add_h, D.neg_p)};
-                uint8_t *dst = &lds[BM * PT + (16 * cs) * PT + kr];
-#pragma unroll
-                for (int b = 0; b < 16; ++b) dst[b * PT] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
+                *(ix4 *)&lds[BM * PT + kr * raw_bpitch(BN) + 16 * cs] =
+                    ix4{(int)centre4((uint32_t)rb[i].x, D.add_h, D.neg_p), (int)centre4((uint32_t)rb[i].y, D.add_h, D.neg_p),
+                        (int)centre4((uint32_t)rb[i].z, D.add_h, D.neg_p), (int)centre4((uint32_t)rb[i].w, D.add_h, D.neg_p)};
             }
         } else {
 #pragma unroll
@@ -392,9 +434,27 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
         const int ksteps = (min(KT, kp - st * KT) + 31) / 32;  // bytes past k are zero
         for (int ks = 0; ks < ksteps; ++ks) {
             ix4 bf[FN];
+            if constexpr (RAW) {
+                // Lane l's fragment: column l % 32 of the block, k-bytes 16 (l / 32) .. + 15
+                // of the step (the same k order as A's), as two transpose loads of 8 k-rows
+                // each: group g = l / 16 reads rows 16 (g / 2) .., columns 16 (g % 2) ..,
+                // lane 2b + c of the group giving bytes 8c .. 8c + 7 of row b.
+                constexpr int BP = raw_bpitch(BN);
+                const int g = lane >> 4, sl = lane & 15;
 #pragma unroll
-            for (int ni = 0; ni < FN; ++ni)
-                bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
+                for (int ni = 0; ni < FN; ++ni) {
+                    const uint8_t *bp = &sB[(ks * 32 + 16 * (g >> 1) + (sl >> 1)) * BP + wn * WTN + ni * 32 +
+                                            16 * (g & 1) + 8 * (sl & 1)];
+                    const v2i b0 = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i *)bp);
+                    const v2i b1 =
+                        __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i *)(bp + 8 * BP));
+                    bf[ni] = ix4{b0.x, b0.y, b1.x, b1.y};
+                }
+            } else {
+#pragma unroll
+                for (int ni = 0; ni < FN; ++ni)
+                    bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
+            }
 #pragma unroll
             for (int mi = 0; mi < FM; ++mi) {
                 const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
@@ -566,9 +626,9 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
 template <uint32_t SHAPE, bool FP4, bool RAW = false>
-__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 ? 7 : 5))
+__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 && !RAW ? 7 : 5))
 void batched_int8_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles, int32_t ntiles) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[(shape_bm(SHAPE) + shape_bn(SHAPE)) * PT];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[tile_lds_bytes(shape_bm(SHAPE), shape_bn(SHAPE), RAW)];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
@@ -780,6 +840,11 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
             D.offset_regime = pl.regime == QMM_REGIME_OFFSET;
             D.start = D.offset_regime ? std::ldexp(1.0, 52 + (int)(pl.t * pl.d)) : 0.0;
         }
+        // Raw tiles read residues in place: below 128 they are already int8 values
+        // (non-negative), and when k (p-1)^2 fits int32 the uncentred sum is exact, so
+        // these products skip the centring and the epilogue's offset (neg_p = 0 says so).
+        if (lowp && b->raw && P.p <= 128 && (uint64_t)P.k * (P.p - 1) * (P.p - 1) <= (uint64_t)INT32_MAX)
+            D.add_h = D.neg_p = D.off = 0;
         b->plans[(size_t)i] = pl;
         if (P.m == 0 || P.n == 0) continue;
         if (lowp && b->raw) {

@@ -190,3 +190,28 @@ def test_raw_batches_read_strided_operands(torch):
             assert (out[mask] == 0xEE).all()
     finally:
         batch.destroy()
+
+
+def test_raw_tiles_at_the_uncentred_bound(torch):
+    # Raw tiles use residues below 128 as int8 values without centring while
+    # k (p-1)^2 fits int32; all-(p-1) operands at the largest such k, one past it
+    # (centred instead), and the moduli on either side of 128.
+    cases = [(127, 3, 5, 135266), (127, 3, 5, 135267), (128, 4, 3, 1000), (129, 4, 3, 1000), (2, 1, 1, 70000)]
+    host, dev = [], []
+    for p, m, n, k in cases:
+        A = np.full((m, k), p - 1, dtype=np.uint8)
+        B = np.full((k, n), p - 1, dtype=np.uint8)
+        host.append((A, B, p))
+        dev.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
+                    torch.empty((m, n), dtype=torch.uint8, device="cuda"), p))
+    note("raw uncentred bound", cases)
+    batch = qmm.batched_create(dev, qmm.BATCH_RAW)
+    try:
+        batch.run()
+        torch.cuda.synchronize()
+        check_all(host, dev)
+        for (A, B, p), (_, _, dC, _) in zip(host, dev):
+            k = A.shape[1]
+            assert (dC.cpu().numpy() == (k * (p - 1) * (p - 1)) % p).all()
+    finally:
+        batch.destroy()
