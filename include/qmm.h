@@ -345,11 +345,14 @@ typedef struct qmm_batched qmm_batched;
  * QMM_BATCH_FORCE_FP64 or QMM_BATCH_SHAPE_* (EINVAL). */
 #define QMM_BATCH_MEASURE       0x1000u
 /* QMM_BATCH_RAW: every product on INT8 tiles that read the products' own residue
- * matrices (A's rows centred in registers, B's rows centred and transposed into
- * on-chip memory): no pack kernel and no operand workspace, the graph is one kernel
- * per tile shape.  Products of p <= 8 stay on INT8.  Not combinable with
- * QMM_BATCH_FORCE_FP64 or QMM_BATCH_MEASURE (EINVAL); QMM_BATCH_MEASURE times the
- * raw assignments next to the packed ones and keeps the fastest. */
+ * matrices in place (residues of p <= 128 used as they are when k (p-1)^2 < 2^31,
+ * centred otherwise; B's rows read from on-chip memory with the transpose load):
+ * no pack kernel and no operand workspace, the graph is one kernel per tile shape.
+ * Products of p <= 8 stay on INT8.  The tiles address A and B with 32-bit offsets:
+ * a product whose A or B data ((rows - 1) * ld + cols bytes) exceeds 2^32 - 64 is
+ * refused (QMM_EUNSUPPORTED).  Not combinable with QMM_BATCH_FORCE_FP64 or
+ * QMM_BATCH_MEASURE (EINVAL); QMM_BATCH_MEASURE times the raw assignments next to
+ * the packed ones and keeps the fastest (skipping them when a product is refused). */
 #define QMM_BATCH_RAW           0x2000u
 qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t flags,
                               qmm_batched **out);

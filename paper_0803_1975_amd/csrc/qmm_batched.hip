@@ -260,36 +260,11 @@ __device__ __forceinline__ ix4 gload16(const int8_t *p) { return *(const QMM_GLO
 
 // 16 bytes of a residue matrix from p (any alignment), bytes at positions >= valid
 // zero, in two halves so that all of a stage's loads are in flight before any of
-// them is waited for.  raw_issue starts the loads into w: one 16-byte and one
-// 4-byte load of the dword-aligned 20-byte window when it lies inside the matrix's
-// data [lo, hi), else the bytes one by one; it records the byte shift and the
+// them is waited for.  raw_issue32 (below) starts the loads into w: one 16-byte
+// and one 4-byte load of the dword-aligned 20-byte window when it lies inside the
+// matrix's data, else the bytes one by one; it records the byte shift and the
 // valid count in meta.  raw_finish, called once the data is needed, aligns the
 // bytes and zeroes those past valid.
-__device__ __forceinline__ void raw_issue(uint32_t (&w)[5], int32_t &meta, const uint8_t *p, int64_t valid,
-                                          const uint8_t *lo, const uint8_t *hi) {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) w[j] = 0;
-    meta = 0;
-    if (valid > 0) {
-        const int32_t v = valid < 16 ? (int32_t)valid : 16;
-        const uintptr_t a = (uintptr_t)p;
-        const uint8_t *base = (const uint8_t *)(a & ~(uintptr_t)3);
-        if (base >= lo && base + 20 <= hi) {
-            const u32x4a4 x = *(const QMM_GLOBAL u32x4a4 *)base;
-            w[0] = x.x;
-            w[1] = x.y;
-            w[2] = x.z;
-            w[3] = x.w;
-            w[4] = *(const QMM_GLOBAL uint32_t *)(base + 16);
-            meta = v | (int32_t)(a & 3) << 8;
-        } else {
-#pragma unroll
-            for (int b = 0; b < 16; ++b)
-                if (b < v) w[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)p)[b] << (8 * (b & 3));
-            meta = v;
-        }
-    }
-}
 __device__ __forceinline__ ix4 raw_finish(const uint32_t (&w)[5], int32_t meta) {
     const uint32_t sh = (uint32_t)(meta >> 8) & 3u;
     const int32_t v = meta & 0xff;
@@ -304,6 +279,35 @@ __device__ __forceinline__ ix4 raw_finish(const uint32_t (&w)[5], int32_t meta) 
         }
     }
     return ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
+}
+
+// The issue half, the matrix given as a uniform base X and a 32-bit byte offset
+// (every offset of a raw product's operands fits 32 bits, checked on the host):
+// the address is the scalar base plus one vector register, with no 64-bit
+// arithmetic per load.  size is the length of the matrix's data from X.
+__device__ __forceinline__ void raw_issue32(uint32_t (&w)[5], int32_t &meta, const uint8_t *X, uint32_t off,
+                                            int32_t valid, uint32_t size) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) w[j] = 0;
+    meta = 0;
+    if (valid > 0) {
+        const int32_t v = valid < 16 ? valid : 16;
+        const uint32_t o4 = off & ~3u;
+        if (o4 + 20u <= size) {
+            const u32x4a4 x = *(const QMM_GLOBAL u32x4a4 *)(X + o4);
+            w[0] = x.x;
+            w[1] = x.y;
+            w[2] = x.z;
+            w[3] = x.w;
+            w[4] = *(const QMM_GLOBAL uint32_t *)(X + o4 + 16u);
+            meta = v | (int32_t)(off & 3u) << 8;
+        } else {
+#pragma unroll
+            for (int b = 0; b < 16; ++b)
+                if (b < v) w[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)X)[off + (uint32_t)b] << (8 * (b & 3));
+            meta = v;
+        }
+    }
 }
 
 // An accumulator register as an integer: int32 for INT8 tiles, an FP32 exact
@@ -352,8 +356,11 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     const int64_t rstride = (int64_t)RSTEP * kp;
     // RAW: B segment c = tid + NT i is k-row c / CSEG of the stage, columns 16 (c % CSEG) ..
     constexpr int CSEG = BN / 16;
-    const uint8_t *a_lo = D.A, *a_hi = D.A + (D.m > 0 && D.k > 0 ? (int64_t)(D.m - 1) * D.lda + D.k : 0);
-    const uint8_t *b_lo = D.B, *b_hi = D.B + (D.k > 0 && D.n > 0 ? (int64_t)(D.k - 1) * D.ldb + D.n : 0);
+    // RAW: 32-bit offsets into A and B; A's rows and B's columns are fixed per tile
+    const uint32_t a_size = D.m > 0 && D.k > 0 ? (uint32_t)((D.m - 1) * D.lda + D.k) : 0u;
+    const uint32_t b_size = D.k > 0 && D.n > 0 ? (uint32_t)((D.k - 1) * D.ldb + D.n) : 0u;
+    const uint32_t lda32 = (uint32_t)D.lda, ldb32 = (uint32_t)D.ldb;
+    const int32_t b_cols = D.n - (int32_t)(col0 + 16 * (tid % CSEG));  // the same for every B segment
     ix4 ra[A_LOADS], rb[B_LOADS];
     // RAW: the windows of a stage's segments, finished into ra / rb when published
     constexpr int RA = RAW ? A_LOADS : 1, RB = RAW ? B_LOADS : 1;
@@ -362,17 +369,17 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     auto fetch = [&](int st) __attribute__((always_inline)) {
         const int k0 = st * KT;
         if constexpr (RAW) {
-            const int64_t kk = k0 + 16 * seg;
+            const int32_t kk = k0 + 16 * seg;
 #pragma unroll
             for (int i = 0; i < A_LOADS; ++i) {
-                const int64_t row = row0 + rfirst + i * RSTEP;
-                raw_issue(wa[i], ma[i], D.A + row * D.lda + kk, row < D.m ? D.k - kk : 0, a_lo, a_hi);
+                const int32_t row = (int32_t)row0 + rfirst + i * RSTEP;
+                raw_issue32(wa[i], ma[i], D.A, (uint32_t)row * lda32 + (uint32_t)kk, row < D.m ? D.k - kk : 0, a_size);
             }
 #pragma unroll
             for (int i = 0; i < B_LOADS; ++i) {
-                const int c = tid + NT * i;
-                const int64_t krow = k0 + c / CSEG, col = col0 + 16 * (c % CSEG);
-                raw_issue(wb[i], mb[i], D.B + krow * D.ldb + col, krow < D.k ? D.n - col : 0, b_lo, b_hi);
+                const int32_t krow = k0 + (tid + NT * i) / CSEG;
+                raw_issue32(wb[i], mb[i], D.B, (uint32_t)krow * ldb32 + (uint32_t)(col0 + 16 * (tid % CSEG)),
+                            krow < D.k ? b_cols : 0, b_size);
             }
         } else {
             const bool ok = k0 + 16 * seg < kp;
@@ -764,6 +771,10 @@ void release(qmm_batched *b) {
     delete b;
 }
 
+// Longest operand data (bytes from the first element to one past the last) that
+// raw tiles address with 32-bit offsets, with room for their 20-byte windows.
+constexpr int64_t kRawSpan = (int64_t)UINT32_MAX - 63;
+
 qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, qmm_batched *b) {
     b->count = count;
     b->raw = (flags & QMM_BATCH_RAW) != 0;
@@ -801,6 +812,10 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         if (pl.path == QMM_PATH_INT8 && pl.k_block < P.k)
             return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": k needs blocked int32 accumulation, "
                                           "which the batched kernel does not do");
+        if (lowp && b->raw && ((P.m > 0 && P.k > 0 && (P.m - 1) * P.lda + P.k > kRawSpan) ||
+                               (P.k > 0 && P.n > 0 && (P.k - 1) * P.ldb + P.n > kRawSpan)))
+            return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": A or B spans more than 2^32 - 64 bytes, "
+                                          "past the raw tiles' 32-bit operand offsets");
         if (lowp && P.m > 0 && P.n > 0 && (P.m - 1) * P.ldc + P.n > (int64_t)UINT32_MAX)
             return fail(QMM_EUNSUPPORTED, "problem " + std::to_string(i) + ": C spans more than 2^32 bytes, "
                                           "past the batched kernel's 32-bit output offsets");

@@ -120,6 +120,12 @@ def test_batched_refuses_outputs_past_32_bit_offsets_before_device_work():
     big = qmm.Problem(m=2, n=16, k=16, p=7, A=fake, lda=16, B=fake, ldb=16, C=fake, ldc=1 << 32)
     assert L.qmm_batched_create(1, ctypes.byref(big), 0, ctypes.byref(out)) == qmm.EUNSUPPORTED
     assert "2^32" in qmm.last_error() and not out.value
+    # raw tiles address A and B with 32-bit offsets too: the same check on the operands
+    for wide in (qmm.Problem(m=2, n=16, k=16, p=7, A=fake, lda=1 << 32, B=fake, ldb=16, C=fake, ldc=16),
+                 qmm.Problem(m=2, n=16, k=16, p=7, A=fake, lda=16, B=fake, ldb=(1 << 32) // 15, C=fake, ldc=16)):
+        out = ctypes.c_void_p()
+        assert L.qmm_batched_create(1, ctypes.byref(wide), qmm.BATCH_RAW, ctypes.byref(out)) == qmm.EUNSUPPORTED
+        assert "32-bit operand offsets" in qmm.last_error() and not out.value
     bad_p = qmm.Problem(m=2, n=16, k=16, p=300, A=fake, lda=16, B=fake, ldb=16, C=fake, ldc=16)
     assert L.qmm_batched_create(1, ctypes.byref(bad_p), 0, ctypes.byref(out)) == qmm.EINVAL
     bad_ld = qmm.Problem(m=2, n=16, k=16, p=7, A=fake, lda=8, B=fake, ldb=16, C=fake, ldc=16)
