@@ -52,7 +52,6 @@ typedef int v2i __attribute__((ext_vector_type(2)));
 // Global-address-space accesses: pointers read from a descriptor in memory are
 // otherwise generic, and a generic (flat) access also counts against the LDS
 // wait counter, so every LDS wait would wait for outstanding memory traffic too.
-#define QMM_GLOBAL __attribute__((address_space(1)))
 
 constexpr int NT = 256;
 constexpr int KW = 16;          // FP64 K stage (packed words)
@@ -109,7 +108,6 @@ __device__ __forceinline__ uint32_t centre4(uint32_t w, uint32_t add_h, uint32_t
     return w + flag * neg_p;
 }
 
-typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
 
 // 64 bytes of a byte matrix starting at src (any alignment), bytes at positions
 // >= valid zero.  When the dword-aligned 68-byte window around them lies inside
@@ -258,58 +256,6 @@ __global__ __launch_bounds__(NT) void batched_pack_kernel(const Desc *__restrict
 // segments of a last, 64-byte stage past kp are not loaded.
 __device__ __forceinline__ ix4 gload16(const int8_t *p) { return *(const QMM_GLOBAL ix4 *)p; }
 
-// 16 bytes of a residue matrix from p (any alignment), bytes at positions >= valid
-// zero, in two halves so that all of a stage's loads are in flight before any of
-// them is waited for.  raw_issue32 (below) starts the loads into w: one 16-byte
-// and one 4-byte load of the dword-aligned 20-byte window when it lies inside the
-// matrix's data, else the bytes one by one; it records the byte shift and the
-// valid count in meta.  raw_finish, called once the data is needed, aligns the
-// bytes and zeroes those past valid.
-__device__ __forceinline__ ix4 raw_finish(const uint32_t (&w)[5], int32_t meta) {
-    const uint32_t sh = (uint32_t)(meta >> 8) & 3u;
-    const int32_t v = meta & 0xff;
-    uint32_t o[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) o[j] = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
-    if (v < 16) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int32_t left = v - 4 * j;
-            o[j] &= left >= 4 ? 0xffffffffu : (left <= 0 ? 0u : (1u << (8 * left)) - 1u);
-        }
-    }
-    return ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
-}
-
-// The issue half, the matrix given as a uniform base X and a 32-bit byte offset
-// (every offset of a raw product's operands fits 32 bits, checked on the host):
-// the address is the scalar base plus one vector register, with no 64-bit
-// arithmetic per load.  size is the length of the matrix's data from X.
-__device__ __forceinline__ void raw_issue32(uint32_t (&w)[5], int32_t &meta, const uint8_t *X, uint32_t off,
-                                            int32_t valid, uint32_t size) {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) w[j] = 0;
-    meta = 0;
-    if (valid > 0) {
-        const int32_t v = valid < 16 ? valid : 16;
-        const uint32_t o4 = off & ~3u;
-        if (o4 + 20u <= size) {
-            const u32x4a4 x = *(const QMM_GLOBAL u32x4a4 *)(X + o4);
-            w[0] = x.x;
-            w[1] = x.y;
-            w[2] = x.z;
-            w[3] = x.w;
-            w[4] = *(const QMM_GLOBAL uint32_t *)(X + o4 + 16u);
-            meta = v | (int32_t)(off & 3u) << 8;
-        } else {
-#pragma unroll
-            for (int b = 0; b < 16; ++b)
-                if (b < v) w[b >> 2] |= (uint32_t)((const QMM_GLOBAL uint8_t *)X)[off + (uint32_t)b] << (8 * (b & 3));
-            meta = v;
-        }
-    }
-}
-
 // An accumulator register as an integer: int32 for INT8 tiles, an FP32 exact
 // integer (|x| <= 2^24) for FP4 tiles.
 __device__ __forceinline__ int32_t acc_value(int32_t bits, bool fp4) {
@@ -398,9 +344,17 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     auto publish = [&]() __attribute__((always_inline)) {
         if constexpr (RAW) {
 #pragma unroll
-            for (int i = 0; i < A_LOADS; ++i) ra[i] = raw_finish(wa[i], ma[i]);
+            for (int i = 0; i < A_LOADS; ++i) {
+                uint32_t o[4];
+                raw_finish(wa[i], ma[i], o);
+                ra[i] = ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
+            }
 #pragma unroll
-            for (int i = 0; i < B_LOADS; ++i) rb[i] = raw_finish(wb[i], mb[i]);
+            for (int i = 0; i < B_LOADS; ++i) {
+                uint32_t o[4];
+                raw_finish(wb[i], mb[i], o);
+                rb[i] = ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
+            }
             if (D.neg_p == 0) {  // residues below 128, sum exact uncentred: bytes as they are
 #pragma unroll
                 for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
@@ -770,10 +724,6 @@ void release(qmm_batched *b) {
     if (b->d_ws) (void)hipFree(b->d_ws);
     delete b;
 }
-
-// Longest operand data (bytes from the first element to one past the last) that
-// raw tiles address with 32-bit offsets, with room for their 20-byte windows.
-constexpr int64_t kRawSpan = (int64_t)UINT32_MAX - 63;
 
 qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, qmm_batched *b) {
     b->count = count;

@@ -116,4 +116,72 @@ template <> struct WordTraits<float> {
     static constexpr int beta = 24;
 };
 
+// Global-address-space pointers: loads through them use the vector memory path
+// only (a generic pointer would also hold the LDS wait counter).
+#define QMM_GLOBAL __attribute__((address_space(1)))
+typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
+
+// 16 bytes of a residue matrix from p (any alignment), bytes at positions >= valid
+// zero, in two halves so that all of a stage's loads are in flight before any of
+// them is waited for.  raw_issue32 starts the loads into w: one 16-byte
+// and one 4-byte load of the dword-aligned 20-byte window when it lies inside the
+// matrix's data, else the window's dwords that do and the last bytes of the data;
+// it records the byte shift and the valid count in meta.  raw_finish, called once the data is needed, aligns the
+// bytes and zeroes those past valid.
+__device__ __forceinline__ void raw_finish(const uint32_t (&w)[5], int32_t meta, uint32_t (&o)[4]) {
+    const uint32_t sh = (uint32_t)(meta >> 8) & 3u;
+    const int32_t v = meta & 0xff;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
+    if (v < 16) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t left = v - 4 * j;
+            o[j] &= left >= 4 ? 0xffffffffu : (left <= 0 ? 0u : (1u << (8 * left)) - 1u);
+        }
+    }
+}
+
+// The issue half, the matrix given as a uniform base X and a 32-bit byte offset
+// (the caller has checked that the data is at most kRawSpan bytes long):
+// the address is the scalar base plus one vector register, with no 64-bit
+// arithmetic per load.  size is the length of the matrix's data from X.
+__device__ __forceinline__ void raw_issue32(uint32_t (&w)[5], int32_t &meta, const uint8_t *X, uint32_t off,
+                                            int32_t valid, uint32_t size) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) w[j] = 0;
+    meta = 0;
+    if (valid > 0) {
+        const int32_t v = valid < 16 ? valid : 16;
+        const uint32_t o4 = off & ~3u;
+        if (o4 + 20u <= size) {
+            const u32x4a4 x = *(const QMM_GLOBAL u32x4a4 *)(X + o4);
+            w[0] = x.x;
+            w[1] = x.y;
+            w[2] = x.z;
+            w[3] = x.w;
+            w[4] = *(const QMM_GLOBAL uint32_t *)(X + o4 + 16u);
+            meta = v | (int32_t)(off & 3u) << 8;
+        } else {
+            // the window runs past the data: the dwords wholly inside it, then the
+            // bytes of the one the data ends in (none past it is read)
+            const uint32_t whole = (size - o4) >> 2;  // dwords of the window inside the data
+#pragma unroll
+            for (int j = 0; j < 5; ++j)
+                if ((uint32_t)j < whole) w[j] = *(const QMM_GLOBAL uint32_t *)(X + o4 + 4u * (uint32_t)j);
+            if (whole < 5u) {
+                const uint32_t last = o4 + 4u * whole;
+                uint32_t x = 0;
+#pragma unroll
+                for (uint32_t b = 0; b < 3; ++b)
+                    if (last + b < size) x |= (uint32_t)((const QMM_GLOBAL uint8_t *)X)[last + b] << (8 * b);
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    if ((uint32_t)j == whole) w[j] = x;
+            }
+            meta = v | (int32_t)(off & 3u) << 8;
+        }
+    }
+}
+
 }  // namespace qmm

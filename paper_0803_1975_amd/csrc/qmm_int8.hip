@@ -580,6 +580,10 @@ __device__ __forceinline__ void load16(const uint8_t *__restrict__ X, int64_t ld
         if (c0 + b < cols) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
 }
 
+// WINDOWED: for operands with rows that are not whole aligned 16-byte segments;
+// both stage loads go out through raw_issue32 before either is waited for (the
+// byte loads of load16 would each wait for the one before).
+template <bool WINDOWED>
 __global__ __launch_bounds__(256) void small_int8_kernel(SmallInt8Args g) {
     __shared__ __attribute__((aligned(16))) uint8_t sA[SM_T * SM_PITCH];
     __shared__ __attribute__((aligned(16))) uint8_t sB[SM_KT * SM_BPITCH];  // rows: k, as B is stored
@@ -588,11 +592,24 @@ __global__ __launch_bounds__(256) void small_int8_kernel(SmallInt8Args g) {
     const int64_t row0 = (int64_t)(blockIdx.x / (uint32_t)g.tiles_n) * SM_T;
     const int64_t col0 = (int64_t)(blockIdx.x % (uint32_t)g.tiles_n) * SM_T;
     const int r = tid >> 2, seg = tid & 3;  // staging: row r, bytes 16 seg .. 16 seg + 15
+    const uint32_t a_size = (uint32_t)((g.m - 1) * g.lda + g.k), b_size = (uint32_t)((g.k - 1) * g.ldb + g.n);
     ix16 acc = ix16{};
     for (int64_t k0 = 0; k0 < g.k; k0 += SM_KT) {
         uint32_t wa[4], wb[4];
-        load16(g.A, g.lda, g.m, g.k, row0 + r, k0 + 16 * seg, wa);                        // A row, 16 k
-        load16(g.B + col0, g.ldb, g.k, g.n - col0, k0 + r, 16 * seg, wb);                   // B k-row, 16 n
+        if constexpr (WINDOWED) {
+            uint32_t xa[5], xb[5];
+            int32_t ma, mb;
+            const int64_t ar = row0 + r, ac = k0 + 16 * seg, bk = k0 + r, bc = col0 + 16 * seg;
+            raw_issue32(xa, ma, g.A, (uint32_t)(ar * g.lda + ac), ar < g.m ? (int32_t)min(g.k - ac, (int64_t)16) : 0,
+                        a_size);
+            raw_issue32(xb, mb, g.B, (uint32_t)(bk * g.ldb + bc), bk < g.k ? (int32_t)min(g.n - bc, (int64_t)16) : 0,
+                        b_size);
+            raw_finish(xa, ma, wa);
+            raw_finish(xb, mb, wb);
+        } else {
+            load16(g.A, g.lda, g.m, g.k, row0 + r, k0 + 16 * seg, wa);       // A row, 16 k
+            load16(g.B + col0, g.ldb, g.k, g.n - col0, k0 + r, 16 * seg, wb);  // B k-row, 16 n
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             wa[i] = centre4(wa[i], g.add_h, g.neg_p);
@@ -651,7 +668,16 @@ qmm_status launch_gemm_int8_small(const qmm_plan &pl, int64_t m, int64_t n, int6
     const int64_t tiles_m = ceil_div(m, SM_T), tiles_n = ceil_div(n, SM_T);
     if (tiles_m * tiles_n > INT32_MAX) return fail(QMM_EUNSUPPORTED, "too many tiles for the one-launch INT8 kernel");
     g.tiles_n = (int32_t)tiles_n;
-    small_int8_kernel<<<dim3((unsigned)(tiles_m * tiles_n)), 256, 0, (hipStream_t)stream>>>(g);
+    // whole aligned 16-byte row segments everywhere: plain 16-byte loads; otherwise
+    // the windowed loads, whose 32-bit offsets need data of at most kRawSpan bytes
+    const bool aligned = lda % 16 == 0 && ldb % 16 == 0 && k % 16 == 0 && n % 16 == 0 &&
+                         (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0;
+    const bool windowed = !aligned && (m - 1) * lda + k <= kRawSpan && (k - 1) * ldb + n <= kRawSpan;
+    const dim3 grid((unsigned)(tiles_m * tiles_n));
+    if (windowed)
+        small_int8_kernel<true><<<grid, 256, 0, (hipStream_t)stream>>>(g);
+    else
+        small_int8_kernel<false><<<grid, 256, 0, (hipStream_t)stream>>>(g);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? QMM_OK : fail(QMM_EDEVICE, std::string("small_int8_kernel: ") + hipGetErrorString(e));
 }

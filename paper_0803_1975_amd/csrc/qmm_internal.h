@@ -104,6 +104,9 @@ qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, con
 qmm_status launch_gemm_int8_small(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A,
                                   int64_t lda, const uint8_t *B, int64_t ldb, uint8_t *C, int64_t ldc,
                                   void *stream);
+// Longest operand data (bytes from the first element to one past the last) that
+// kernels address with 32-bit offsets, with room for their 20-byte load windows.
+constexpr int64_t kRawSpan = (int64_t)UINT32_MAX - 63;
 // Largest m n k that qmm_gemm_mod_p runs on the one-launch INT8 kernel.
 constexpr double kSmallInt8MaxMacs = 4294967296.0;  // 2^32: one launch measured faster up to 1536^3
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
