@@ -184,4 +184,43 @@ __device__ __forceinline__ void raw_issue32(uint32_t (&w)[5], int32_t &meta, con
     }
 }
 
+// The issue half with a plain pointer p into data that ends at end (any length:
+// the window is checked against end in 64 bits).
+__device__ __forceinline__ void raw_issue_ptr(uint32_t (&w)[5], int32_t &meta, const uint8_t *p, int64_t valid,
+                                              const uint8_t *end) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) w[j] = 0;
+    meta = 0;
+    if (valid > 0) {
+        const int32_t v = valid < 16 ? (int32_t)valid : 16;
+        const uint32_t sh = (uint32_t)((uintptr_t)p & 3);
+        const uint8_t *W = p - sh;
+        const int64_t avail = end - W;
+        if (avail >= 20) {
+            const u32x4a4 x = *(const QMM_GLOBAL u32x4a4 *)W;
+            w[0] = x.x;
+            w[1] = x.y;
+            w[2] = x.z;
+            w[3] = x.w;
+            w[4] = *(const QMM_GLOBAL uint32_t *)(W + 16);
+        } else {
+            const uint32_t whole = (uint32_t)avail >> 2;
+#pragma unroll
+            for (int j = 0; j < 5; ++j)
+                if ((uint32_t)j < whole) w[j] = *(const QMM_GLOBAL uint32_t *)(W + 4 * j);
+            if (whole < 5u) {
+                uint32_t x = 0;
+#pragma unroll
+                for (uint32_t b = 0; b < 3; ++b)
+                    if (4u * whole + b < (uint32_t)avail)
+                        x |= (uint32_t)((const QMM_GLOBAL uint8_t *)W)[4u * whole + b] << (8 * b);
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    if ((uint32_t)j == whole) w[j] = x;
+            }
+        }
+        meta = v | (int32_t)sh << 8;
+    }
+}
+
 }  // namespace qmm

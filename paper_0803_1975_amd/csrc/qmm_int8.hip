@@ -313,7 +313,8 @@ struct Int8Args {
 // AVEC: every row of A is 16-byte aligned and k is a multiple of 16, so each
 // 16-byte segment below k is one vector load; segments past k or rows past m
 // load from a clamped, valid address and are zeroed by a select (no branches in
-// the loop).  Otherwise segments are assembled from byte loads.
+// the loop).  Otherwise each segment is a dword-aligned window, all of a stage's
+// issued before any is aligned (byte loads would each wait for the one before).
 // FP4: both operands are packed e2m1 codes (two k per byte, A already converted,
 // g.k counts packed bytes), and each 16-byte fragment feeds the FP4 form of the
 // MFMA, v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales: 64 k per instruction
@@ -365,8 +366,25 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
         b_ok[i] = brow < g.n;
         b_ptr[i] = g.Bt + (b_ok[i] ? brow : 0) * g.ldbt + (c % SEGS) * 16;
     }
+    const uint8_t *a_end = g.A + (g.m - 1) * g.lda + g.k;  // one past A's data
     auto load_stage = [&](int kt) {
         const int64_t k0 = (int64_t)kt * KT;
+        if constexpr (!AVEC && !FP4) {
+            // unaligned A: every window of the stage issued, then all aligned
+            uint32_t aw[A_LOADS][5];
+            int32_t am[A_LOADS];
+#pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) {
+                const int64_t kk = k0 + ((tid + NT * i) % SEGS) * 16;
+                raw_issue_ptr(aw[i], am[i], a_ptr[i] + k0, a_ok[i] ? g.k - kk : 0, a_end);
+            }
+#pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) {
+                uint32_t o[4];
+                raw_finish(aw[i], am[i], o);
+                ra[i] = make_uint4(o[0], o[1], o[2], o[3]);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < A_LOADS; ++i) {
             const int64_t kk = k0 + ((tid + NT * i) % SEGS) * 16;
@@ -379,16 +397,6 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
                 const bool ok = a_ok[i] && kk < g.k;
                 const uint4 v = *(const uint4 *)(ok ? a_ptr[i] + k0 : g.A);
                 ra[i] = ok ? v : make_uint4(0, 0, 0, 0);
-            } else {
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (a_ok[i]) {
-                    const uint8_t *src = a_ptr[i] + k0;
-                    uint32_t w[4] = {0, 0, 0, 0};
-                    for (int b = 0; b < 16; ++b)
-                        if (kk + b < g.k) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
-                    v = make_uint4(w[0], w[1], w[2], w[3]);
-                }
-                ra[i] = v;
             }
         }
 #pragma unroll
