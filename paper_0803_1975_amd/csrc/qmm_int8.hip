@@ -135,7 +135,7 @@ __device__ __forceinline__ uint32_t fp4_pack(uint32_t c_lo, uint32_t c_hi) {
 // codes at byte 16 sg of the packed row.
 __device__ __forceinline__ void fp4_row_segment(int64_t r, int64_t sg, int64_t k, const uint8_t *__restrict__ A,
                                                 int64_t lda, uint8_t *__restrict__ A4, int64_t lda4, uint32_t lut_lo,
-                                                uint32_t lut_hi, int a_vec) {
+                                                uint32_t lut_hi, int a_vec, const uint8_t *a_end) {
     const uint8_t *row = A + r * lda;
     const int64_t k0 = 32 * sg;
     uint32_t w[8];
@@ -144,10 +144,18 @@ __device__ __forceinline__ void fp4_row_segment(int64_t r, int64_t sg, int64_t k
         w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
         w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
     } else {
+        // two dword-aligned windows (a_end: one past A's data), both issued first
+        uint32_t x0[5], x1[5], o0[4], o1[4];
+        int32_t m0, m1;
+        raw_issue_ptr(x0, m0, row + k0, k - k0, a_end);
+        raw_issue_ptr(x1, m1, row + k0 + 16, k - k0 - 16, a_end);
+        raw_finish(x0, m0, o0);
+        raw_finish(x1, m1, o1);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) w[i] = 0;
-        for (int b = 0; b < 32; ++b)
-            if (k0 + b < k) w[b >> 2] |= (uint32_t)row[k0 + b] << (8 * (b & 3));
+        for (int i = 0; i < 4; ++i) {
+            w[i] = o0[i];
+            w[4 + i] = o1[i];
+        }
     }
     uint32_t o[4];
 #pragma unroll
@@ -161,7 +169,7 @@ __global__ __launch_bounds__(256) void pack_fp4_rows_kernel(int64_t m, int64_t k
     const int64_t segs = lda4 / 16;
     for (int64_t r = blockIdx.y; r < m; r += gridDim.y)
         for (int64_t sg = (int64_t)blockIdx.x * 256 + threadIdx.x; sg < segs; sg += (int64_t)gridDim.x * 256)
-            fp4_row_segment(r, sg, k, A, lda, A4, lda4, lut_lo, lut_hi, a_vec);
+            fp4_row_segment(r, sg, k, A, lda, A4, lda4, lut_lo, lut_hi, a_vec, A + (m - 1) * lda + k);
 }
 
 // Bt4[n0 + c][(k0 + r) / 2] = code(B[k0 + r][n0 + c]) for the 128 (k) x 128 (n) tile
@@ -262,7 +270,8 @@ __global__ __launch_bounds__(256) void pack_fp4_both_kernel(Fp4PackArgs g) {
         const int64_t idx = blk * 256 + threadIdx.x;
         if (idx < g.m * segs) {
             const int64_t r = idx / segs;
-            fp4_row_segment(r, idx - r * segs, g.k, g.A, g.lda, g.A4, g.lda4, g.lut_lo, g.lut_hi, g.a_vec);
+            fp4_row_segment(r, idx - r * segs, g.k, g.A, g.lda, g.A4, g.lda4, g.lut_lo, g.lut_hi, g.a_vec,
+                            g.A + (g.m - 1) * g.lda + g.k);
         }
         return;
     }
