@@ -187,8 +187,9 @@ qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, i
  * FULL paths, INT8 / FP4 matrix cores for the INT8 / FP4 paths).
  * plan == NULL: qmm_choose_Qd(p, m, n, k, 0, QMM_PATH_AUTO, 0) is used.
  * A: m x k, B: k x n, C: m x n bytes (C must not overlap A or B).
- * ws: device workspace of ws_bytes >= qmm_gemm_workspace_size (may be NULL when
- * that size is 0); it holds the packed operands between the kernels.  The REDQ and
+ * ws: device workspace of ws_bytes >= qmm_gemm_workspace_size, 256-byte aligned
+ * (QMM_EINVAL otherwise; it may be NULL when that size is 0); it holds the packed
+ * operands between the kernels.  The REDQ and
  * LEFT paths also hold their residue operand there as words (one residue each,
  * procedure (5)'s Uncompress) and multiply two word matrices; the stage calls
  * qmm_gemm_right_packed / qmm_gemm_left_packed instead convert that operand on
@@ -254,6 +255,15 @@ qmm_status qmm_gemm_right_packed(const qmm_plan *plan, int64_t m, int64_t n, int
                                  const uint8_t *A, int64_t lda, const void *CBr, int64_t ldcbr,
                                  uint8_t *C, int64_t ldc, void *stream);
 
+/* Leading dimension (bytes) of the packed operands of the INT8 and FP4 paths for an
+ * inner dimension k: for an INT8 plan the row stride of Bt that qmm_gemm_mod_p uses
+ * (k rounded up to 128, plus one 128-byte line when that is a multiple of 2048, so
+ * that rows do not crowd a few HBM channels); for an FP4 plan the row stride of A4
+ * and Bt4 (ceil(k/2) rounded the same way).  Callers of the stage entry points
+ * allocate with it; any multiple of 128 >= k (>= k/2) is accepted too.
+ * QMM_EINVAL for other paths, a NULL argument or k < 0.  Host only. */
+qmm_status qmm_operand_ld(const qmm_plan *plan, int64_t k, int64_t *ld);
+
 /* INT8 path, conversion step: Bt[j][l] = centred(B[l][j]) as int8, where
  * centred(x) = x - p if x > (p-1)/2, else x; Bt is n x ldbt with ldbt a multiple
  * of 128 and >= k, columns l >= k are zero.  Bt must be 16-byte aligned.
@@ -318,7 +328,12 @@ typedef struct qmm_batched qmm_batched;
  * one HIP graph: for INT8 products a pack kernel that centres every A_i and
  * centres and transposes every B_i once into a workspace, then one persistent
  * product kernel per tile shape.  probs is a host array; the device buffers it
- * names must stay valid until qmm_batched_destroy.  The batch owns the device
+ * names must stay valid until qmm_batched_destroy.  No output C_i may share a byte
+ * with any A_j, B_j or other C_j (inputs may share bytes with each other): the
+ * products run concurrently, raw tiles read A_j and B_j while other tiles write,
+ * and QMM_BATCH_MEASURE replays the batch several times on these buffers.  The
+ * library does not check this (outputs that are disjoint views into one larger
+ * matrix are allowed and common).  The batch owns the device
  * memory it allocates, including the workspace of sum_i (mp_i + np_i) kp_i bytes
  * (kp_i = k_i rounded up to 64, mp_i and np_i = m_i and n_i rounded up to the
  * product's tile).

@@ -211,6 +211,8 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
     const Layout L = workspace_layout(pl, m, n, k);
     if (L.bytes > 0 && (ws == nullptr || ws_bytes < L.bytes))
         return fail(QMM_ENOSPACE, "workspace needs " + std::to_string(L.bytes) + " bytes");
+    // the packed operands sit at ws and ws + off_b and are read with 16-byte loads
+    if (L.bytes > 0 && (uintptr_t)ws % kAlign != 0) return fail(QMM_EINVAL, "ws must be 256-byte aligned");
     uint8_t *w = (uint8_t *)ws;
     if (fused_qadic(pl, m, n, k)) return launch_gemm_qadic_fused(pl, m, n, k, A, lda, B, ldb, C, ldc, stream);
     if (small_int8(pl, m, n, k)) return launch_gemm_int8_small(pl, m, n, k, A, lda, B, ldb, C, ldc, stream);
@@ -256,6 +258,16 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
         return launch_gemm_fp4(pl, m, n, k, A4, L.ld_a, Bt4, L.ld_b, C, ldc, stream);
     }
     return fail(QMM_EINVAL, "unknown path");
+}
+
+extern "C" qmm_status qmm_operand_ld(const qmm_plan *plan, int64_t k, int64_t *ld) {
+    if (!plan || !ld) return fail(QMM_EINVAL, "plan and ld must not be NULL");
+    if (k < 0) return fail(QMM_EINVAL, "negative k");
+    const int64_t kk = k < 1 ? 1 : k;
+    if (plan->path == QMM_PATH_INT8) *ld = int8_bt_ld(kk);
+    else if (plan->path == QMM_PATH_FP4) *ld = fp4_ld(kk);
+    else return fail(QMM_EINVAL, "qmm_operand_ld takes an INT8 or FP4 plan");
+    return QMM_OK;
 }
 
 extern "C" qmm_status qmm_gemm_packed(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, const void *CA,

@@ -43,7 +43,7 @@ EXPORTS = [
     "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs", "qmm_count_nonresidues",
     "qmm_pack_fp4_rows", "qmm_pack_fp4_cols", "qmm_gemm_fp4", "qmm_pack_fp4",
     "qmm_gemm_packed_compress", "qmm_pack_left", "qmm_pack_full_right", "qmm_gemm_left_packed",
-    "qmm_gemm_full_packed",
+    "qmm_gemm_full_packed", "qmm_operand_ld",
 ]
 
 
@@ -117,6 +117,7 @@ def lib():
             "qmm_pack_full_right": [P, i64, i64, vp, i64, vp, i64, vp],
             "qmm_gemm_left_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
             "qmm_gemm_full_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
+            "qmm_operand_ld": [P, i64, ctypes.POINTER(i64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -146,6 +147,32 @@ def _stream(stream):
         return ctypes.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _side(stream):
+    """The torch stream of a `stream` argument that is not torch's current stream, else None."""
+    if stream is None:
+        return None
+    import torch
+    cur = torch.cuda.current_stream().cuda_stream
+    handle = stream if isinstance(stream, int) else stream.cuda_stream
+    if handle == cur:
+        return None
+    return torch.cuda.ExternalStream(stream) if isinstance(stream, int) else stream
+
+
+def _new(t, stream):
+    """A tensor this binding allocated for work on `stream`.  torch's caching allocator
+    orders a block's uses on torch's current stream only: when `stream` is another one,
+    it first waits for the current stream (earlier users of the block are done), and the
+    block is recorded on it, so that freeing the tensor does not hand its memory to other
+    work before the kernels on `stream` are done with it."""
+    s = _side(stream)
+    if s is not None:
+        import torch
+        s.wait_stream(torch.cuda.current_stream())
+        t.record_stream(s)
+    return t
 
 
 def _ptr(t):
@@ -197,7 +224,7 @@ def pack_rows_rev(plan, A, CA=None, stream=None):
     _u8(A, "A")
     m, k = A.shape
     if CA is None:
-        CA = torch.empty((m, -(-k // (plan.d + 1))), dtype=word_dtype(plan), device=A.device)
+        CA = _new(torch.empty((m, -(-k // (plan.d + 1))), dtype=word_dtype(plan), device=A.device), stream)
     _check(lib().qmm_pack_rows_rev(ctypes.byref(plan), m, k, _ptr(A), _ld(A), _ptr(CA), _ld(CA), _stream(stream)),
            "qmm_pack_rows_rev")
     return CA
@@ -208,7 +235,7 @@ def pack_cols_fwd(plan, B, CB=None, stream=None):
     _u8(B, "B")
     k, n = B.shape
     if CB is None:
-        CB = torch.empty((-(-k // (plan.d + 1)), n), dtype=word_dtype(plan), device=B.device)
+        CB = _new(torch.empty((-(-k // (plan.d + 1)), n), dtype=word_dtype(plan), device=B.device), stream)
     _check(lib().qmm_pack_cols_fwd(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(CB), _ld(CB), _stream(stream)),
            "qmm_pack_cols_fwd")
     return CB
@@ -219,7 +246,7 @@ def pack_rows_fwd(plan, B, CBr=None, stream=None):
     _u8(B, "B")
     k, n = B.shape
     if CBr is None:
-        CBr = torch.empty((k, -(-n // (plan.d + 1))), dtype=word_dtype(plan), device=B.device)
+        CBr = _new(torch.empty((k, -(-n // (plan.d + 1))), dtype=word_dtype(plan), device=B.device), stream)
     _check(lib().qmm_pack_rows_fwd(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(CBr), _ld(CBr), _stream(stream)),
            "qmm_pack_rows_fwd")
     return CBr
@@ -228,7 +255,7 @@ def pack_rows_fwd(plan, B, CBr=None, stream=None):
 def unpack(plan, which, rows, cols, packed, out=None, stream=None):
     import torch
     if out is None:
-        out = torch.empty((rows, cols), dtype=torch.uint8, device=packed.device)
+        out = _new(torch.empty((rows, cols), dtype=torch.uint8, device=packed.device), stream)
     _check(lib().qmm_unpack(ctypes.byref(plan), which, rows, cols, _ptr(packed), _ld(packed), _ptr(out), _ld(out),
                             _stream(stream)), "qmm_unpack")
     return out
@@ -238,7 +265,7 @@ def extract(plan, T, C=None, stream=None):
     import torch
     m, n = T.shape
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=T.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=T.device), stream)
     _check(lib().qmm_extract(ctypes.byref(plan), m, n, _ptr(T), _ld(T), _ptr(C), _ld(C), _stream(stream)),
            "qmm_extract")
     return C
@@ -248,7 +275,7 @@ def redq(plan, CC, n, C=None, stream=None):
     import torch
     m = CC.shape[0]
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=CC.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=CC.device), stream)
     _check(lib().qmm_redq(ctypes.byref(plan), m, n, _ptr(CC), _ld(CC), _ptr(C), _ld(C), _stream(stream)), "qmm_redq")
     return C
 
@@ -271,7 +298,7 @@ def count_nonresidues(p, X, count=None, stream=None):
     import torch
     _u8(X, "X")
     if count is None:
-        count = torch.empty(1, dtype=torch.int32, device=X.device)
+        count = _new(torch.empty(1, dtype=torch.int32, device=X.device), stream)
     rows, cols = X.shape
     _check(lib().qmm_count_nonresidues(p, rows, cols, _ptr(X), _ld(X), _ptr(count), _stream(stream)),
            "qmm_count_nonresidues")
@@ -290,15 +317,19 @@ def gemm_mod_p(A, B, p, plan=None, C=None, ws=None, stream=None, validate=False)
     if k2 != k:
         raise ValueError("inner dimensions differ")
     if validate:
-        bad = [int(count_nonresidues(p, X, stream=stream).item()) for X in (A, B)]
+        counts = [count_nonresidues(p, X, stream=stream) for X in (A, B)]
+        side = _side(stream)
+        if side is not None:
+            side.synchronize()  # .item() below waits for torch's current stream only
+        bad = [int(c.item()) for c in counts]
         if any(bad):
             raise QmmError(EVALUE, "gemm_mod_p", f"{bad[0]} entries of A and {bad[1]} of B are not residues mod {p}")
     if plan is None:
         plan = choose_Qd(p, m, n, k)
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=A.device), stream)
     if ws is None:
-        ws = workspace(plan, m, n, k, A.device)
+        ws = _new(workspace(plan, m, n, k, A.device), stream)
     _check(lib().qmm_gemm_mod_p(ctypes.byref(plan), m, n, k, p, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C),
                                 _ptr(ws), ws.numel(), _stream(stream)), "qmm_gemm_mod_p")
     return C
@@ -309,7 +340,7 @@ def gemm_packed(plan, k, CA, CB, C=None, stream=None):
     import torch
     m, n = CA.shape[0], CB.shape[1]
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=CA.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=CA.device), stream)
     _check(lib().qmm_gemm_packed(ctypes.byref(plan), m, n, k, _ptr(CA), _ld(CA), _ptr(CB), _ld(CB), _ptr(C), _ld(C),
                                  _stream(stream)), "qmm_gemm_packed")
     return C
@@ -321,7 +352,7 @@ def gemm_packed_compress(plan, k, CA, CB, CC=None, stream=None):
     import torch
     m, n = CA.shape[0], CB.shape[1]
     if CC is None:
-        CC = torch.empty((m, -(-n // (plan.d + 1))), dtype=word_dtype(plan), device=CA.device)
+        CC = _new(torch.empty((m, -(-n // (plan.d + 1))), dtype=word_dtype(plan), device=CA.device), stream)
     _check(lib().qmm_gemm_packed_compress(ctypes.byref(plan), m, n, k, _ptr(CA), _ld(CA), _ptr(CB), _ld(CB),
                                           _ptr(CC), _ld(CC), _stream(stream)), "qmm_gemm_packed_compress")
     return CC
@@ -333,7 +364,7 @@ def pack_left(plan, A, CAl=None, stream=None):
     _u8(A, "A")
     m, k = A.shape
     if CAl is None:
-        CAl = torch.empty((-(-m // (plan.d + 1)), k), dtype=word_dtype(plan), device=A.device)
+        CAl = _new(torch.empty((-(-m // (plan.d + 1)), k), dtype=word_dtype(plan), device=A.device), stream)
     _check(lib().qmm_pack_left(ctypes.byref(plan), m, k, _ptr(A), _ld(A), _ptr(CAl), _ld(CAl), _stream(stream)),
            "qmm_pack_left")
     return CAl
@@ -345,7 +376,7 @@ def pack_full_right(plan, B, CBt=None, stream=None):
     _u8(B, "B")
     k, n = B.shape
     if CBt is None:
-        CBt = torch.empty((k, -(-n // (plan.d2 + 1))), dtype=word_dtype(plan), device=B.device)
+        CBt = _new(torch.empty((k, -(-n // (plan.d2 + 1))), dtype=word_dtype(plan), device=B.device), stream)
     _check(lib().qmm_pack_full_right(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(CBt), _ld(CBt),
                                      _stream(stream)), "qmm_pack_full_right")
     return CBt
@@ -357,7 +388,7 @@ def gemm_left_packed(plan, CAl, B, m, C=None, stream=None):
     _u8(B, "B")
     k, n = B.shape
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=B.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=B.device), stream)
     _check(lib().qmm_gemm_left_packed(ctypes.byref(plan), m, n, k, _ptr(CAl), _ld(CAl), _ptr(B), _ld(B), _ptr(C),
                                       _ld(C), _stream(stream)), "qmm_gemm_left_packed")
     return C
@@ -368,7 +399,7 @@ def gemm_full_packed(plan, CAl, CBt, m, n, C=None, stream=None):
     import torch
     k = CAl.shape[1]
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=CAl.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=CAl.device), stream)
     _check(lib().qmm_gemm_full_packed(ctypes.byref(plan), m, n, k, _ptr(CAl), _ld(CAl), _ptr(CBt), _ld(CBt),
                                       _ptr(C), _ld(C), _stream(stream)), "qmm_gemm_full_packed")
     return C
@@ -380,17 +411,24 @@ def gemm_right_packed(plan, A, CBr, n, C=None, stream=None):
     _u8(A, "A")
     m, k = A.shape
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=A.device), stream)
     _check(lib().qmm_gemm_right_packed(ctypes.byref(plan), m, n, k, _ptr(A), _ld(A), _ptr(CBr), _ld(CBr), _ptr(C),
                                        _ld(C), _stream(stream)), "qmm_gemm_right_packed")
     return C
 
 
+def operand_ld(path, k) -> int:
+    """Row stride (bytes) of the packed INT8 (Bt) or FP4 (A4, Bt4) operands for inner
+    dimension k: the library's own choice (qmm_operand_ld)."""
+    pl = Plan(path=path)
+    out = ctypes.c_int64(0)
+    _check(lib().qmm_operand_ld(ctypes.byref(pl), k, ctypes.byref(out)), "qmm_operand_ld")
+    return out.value
+
+
 def centred_ld(k) -> int:
-    """Leading dimension of the centred, transposed right operand: k rounded up to 128,
-    plus one 128-byte line when that is a multiple of 2048 (the library's own choice)."""
-    r = max(1, -(-k // 128)) * 128
-    return r + 128 if r % 2048 == 0 else r
+    """Leading dimension of the centred, transposed right operand of the INT8 path."""
+    return operand_ld(PATH_INT8, k)
 
 
 def pack_centred_cols(plan, B, Bt=None, stream=None):
@@ -399,7 +437,7 @@ def pack_centred_cols(plan, B, Bt=None, stream=None):
     _u8(B, "B")
     k, n = B.shape
     if Bt is None:
-        Bt = torch.empty((n, centred_ld(k)), dtype=torch.int8, device=B.device)
+        Bt = _new(torch.empty((n, centred_ld(k)), dtype=torch.int8, device=B.device), stream)
     _check(lib().qmm_pack_centred_cols(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(Bt), _ld(Bt), _stream(stream)),
            "qmm_pack_centred_cols")
     return Bt
@@ -411,7 +449,7 @@ def gemm_centred(plan, A, Bt, n, C=None, stream=None):
     _u8(A, "A")
     m, k = A.shape
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=A.device), stream)
     _check(lib().qmm_gemm_centred(ctypes.byref(plan), m, n, k, _ptr(A), _ld(A), _ptr(Bt), _ld(Bt), _ptr(C), _ld(C),
                                   _stream(stream)), "qmm_gemm_centred")
     return C
@@ -464,10 +502,8 @@ def batched_set_costs(costs):
 
 
 def fp4_ld(k) -> int:
-    """Row stride (bytes) of packed FP4 operands: ceil(k/2) rounded up to 128, plus one
-    128-byte line when that is a multiple of 2048 (the library's own choice)."""
-    r = max(1, -(-(-(-max(k, 1) // 2)) // 128)) * 128
-    return r + 128 if r % 2048 == 0 else r
+    """Row stride (bytes) of packed FP4 operands."""
+    return operand_ld(PATH_FP4, k)
 
 
 def pack_fp4_rows(plan, A, A4=None, stream=None):
@@ -476,7 +512,7 @@ def pack_fp4_rows(plan, A, A4=None, stream=None):
     _u8(A, "A")
     m, k = A.shape
     if A4 is None:
-        A4 = torch.empty((m, fp4_ld(k)), dtype=torch.uint8, device=A.device)
+        A4 = _new(torch.empty((m, fp4_ld(k)), dtype=torch.uint8, device=A.device), stream)
     _check(lib().qmm_pack_fp4_rows(ctypes.byref(plan), m, k, _ptr(A), _ld(A), _ptr(A4), _ld(A4), _stream(stream)),
            "qmm_pack_fp4_rows")
     return A4
@@ -488,7 +524,7 @@ def pack_fp4_cols(plan, B, Bt4=None, stream=None):
     _u8(B, "B")
     k, n = B.shape
     if Bt4 is None:
-        Bt4 = torch.empty((n, fp4_ld(k)), dtype=torch.uint8, device=B.device)
+        Bt4 = _new(torch.empty((n, fp4_ld(k)), dtype=torch.uint8, device=B.device), stream)
     _check(lib().qmm_pack_fp4_cols(ctypes.byref(plan), k, n, _ptr(B), _ld(B), _ptr(Bt4), _ld(Bt4), _stream(stream)),
            "qmm_pack_fp4_cols")
     return Bt4
@@ -499,7 +535,7 @@ def gemm_fp4(plan, A4, Bt4, k, C=None, stream=None):
     import torch
     m, n = A4.shape[0], Bt4.shape[0]
     if C is None:
-        C = torch.empty((m, n), dtype=torch.uint8, device=A4.device)
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=A4.device), stream)
     _check(lib().qmm_gemm_fp4(ctypes.byref(plan), m, n, k, _ptr(A4), _ld(A4), _ptr(Bt4), _ld(Bt4), _ptr(C), _ld(C),
                               _stream(stream)), "qmm_gemm_fp4")
     return C
@@ -513,9 +549,9 @@ def pack_fp4(plan, A, B, A4=None, Bt4=None, stream=None):
     m, k = A.shape
     n = B.shape[1]
     if A4 is None:
-        A4 = torch.empty((m, fp4_ld(k)), dtype=torch.uint8, device=A.device)
+        A4 = _new(torch.empty((m, fp4_ld(k)), dtype=torch.uint8, device=A.device), stream)
     if Bt4 is None:
-        Bt4 = torch.empty((n, fp4_ld(k)), dtype=torch.uint8, device=B.device)
+        Bt4 = _new(torch.empty((n, fp4_ld(k)), dtype=torch.uint8, device=B.device), stream)
     _check(lib().qmm_pack_fp4(ctypes.byref(plan), m, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(A4), _ld(A4),
                               _ptr(Bt4), _ld(Bt4), _stream(stream)), "qmm_pack_fp4")
     return A4, Bt4

@@ -37,6 +37,10 @@ def test_json_line_carries_metric_roofline_and_cpu_baseline():
     assert d["n_gpus"] == 1 and d["steps"] == 20 and d["warmup"] == 2
     assert d["unit"] == "mod-p GMAC/s" and d["higher_is_better"] is True and d["data"] == "synthetic"
     assert d["value"] > 0 and d["ms_per_step"] > 0
+    # the headline is the paper's arithmetic (FP64 Q-adic words); the library's own
+    # choice rides along with its speed-up over it
+    assert d["dtype"] == "f64" and d["config"]["path"] == "fp64_qadic"
+    assert d["paths"]["chosen"]["speedup_vs_headline"] > 0
     # value is m n k over the step time
     c = d["config"]
     assert "workload" in c

@@ -229,6 +229,31 @@ def test_int8_blocked_accumulation(torch):
         np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=plan)), want, err_msg=f"tile {tile}")
 
 
+@pytest.mark.parametrize("p,k", [(2, 20), (2, 12), (3, 15), (5, 13), (7, 7)])
+def test_fp32_offset_plans_rely_on_one_rounding_per_product(torch, p, k):
+    # The planner's FP32 Q-adic plans for these (p, k) are in the offset regime with a
+    # low part that only a correctly rounded step per product floors away: the oracle's
+    # 24-bit emulation gives the right digit with one rounding per product and a wrong
+    # one with four products summed before a rounding.  On all-(p-1) operands every
+    # low part is maximal, so the GPU result shows which the FP32 matrix cores do.
+    from oracle import emulate
+    plan = qmm.choose_Qd(p, 48, 40, k, path=qmm.PATH_FP32_QADIC)
+    note("fp32 rounding", plan)
+    assert plan.regime == qmm.REGIME_OFFSET and plan.g == 1 and plan.k_block == k
+    assert bounds.offset_ok(p, k, plan.t, plan.d, 24, g=1) and not bounds.offset_ok(p, k, plan.t, plan.d, 24, g=4)
+    a = np.full(k, p - 1, dtype=np.uint8)
+    want = (k * (p - 1) ** 2) % p
+    assert emulate.qadic_entry(a, a, p, plan.t, plan.d, 24, "offset", g=1) == want
+    assert emulate.qadic_entry(a, a, p, plan.t, plan.d, 24, "offset", g=4) != want
+    A = torch.full((48, k), p - 1, dtype=torch.uint8, device="cuda")
+    B = torch.full((k, 40), p - 1, dtype=torch.uint8, device="cuda")
+    C = host(qmm.gemm_mod_p(A, B, p, plan=plan))
+    assert (C == want).all(), (plan, np.unique(C))
+    # the same plan through the stage calls (pack, then procedure (1) on the words)
+    C1 = host(qmm.gemm_packed(plan, k, qmm.pack_rows_rev(plan, A), qmm.pack_cols_fwd(plan, B)))
+    assert (C1 == want).all()
+
+
 def test_offset_regime_relies_on_one_rounding_per_product(torch):
     # p = 3, t = 7, d = 5, k = 24: every product's low part sits just below Q^d/2.
     # One correctly rounded step per product (what the matrix cores do) floors each
@@ -367,7 +392,8 @@ def test_graph_workload_and_paley_closed_form(torch):
 
 
 @pytest.mark.parametrize("p,m,n,k", [(7, 300, 272, 1040), (2, 1, 16, 16), (251, 257, 512, 4096), (3, 640, 48, 130048),
-                                     (101, 33, 1024, 16), (256, 96, 64, 1984)])
+                                     (101, 33, 1024, 16), (256, 96, 64, 1984), (101, 300, 260, 1001),
+                                     (7, 257, 130, 4097), (13, 70, 300, 333)])
 def test_int8_stages_match_one_call_and_oracle(torch, p, m, n, k):
     # The two INT8 stage calls (centring transpose, product) give what qmm_gemm_mod_p
     # gives; every tile variant (128 x 128, 256 x 256 with 8 or 16 wavefronts); k past
@@ -535,3 +561,59 @@ def test_small_int8_one_launch_matches_staged_calls_and_oracle(torch, p, m, n, k
     np.testing.assert_array_equal(host(C), want)
     staged = qmm.gemm_centred(plan, dA, qmm.pack_centred_cols(plan, dB), n)
     np.testing.assert_array_equal(host(staged), want)
+
+
+@pytest.mark.parametrize("k", (1001, 4097, 2049))
+def test_int8_unaligned_rows_on_every_tile(torch, k):
+    # k odd: rows of A start at every byte offset within a dword, so the product
+    # kernel's windowed loads of A take each byte shift on every tile variant; one case
+    # is also cut into blocks.
+    p = 101
+    m, n = 300, 260
+    rng = np.random.default_rng(k)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    Bt = qmm.pack_centred_cols(plan, dB)
+    for tile in (1, 2, 3):
+        for k_block in ((plan.k_block, 512) if k == 4097 else (plan.k_block,)):
+            plan.tile, plan.k_block = tile, k_block
+            note("int8 unaligned", k, "tile", tile, "k_block", k_block)
+            np.testing.assert_array_equal(host(qmm.gemm_centred(plan, dA, Bt, n)), want,
+                                          err_msg=f"tile {tile} k_block {k_block}")
+            np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=plan)), want)
+        plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+
+
+@pytest.mark.parametrize("validate", (False, True))
+def test_products_on_a_side_stream(torch, validate):
+    # gemm_mod_p on a stream that is not torch's current one: the binding's own
+    # workspace and output stay allocated until that stream's kernels are done, and
+    # validation reads its counts after them.
+    p = 7
+    rng = np.random.default_rng(31)
+    A = rng.integers(0, p, (700, 900), dtype=np.uint8)
+    B = rng.integers(0, p, (900, 500), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for path in (qmm.PATH_FP64_QADIC, qmm.PATH_INT8, qmm.PATH_FP4, qmm.PATH_FP64_REDQ):
+        plan = qmm.choose_Qd(p, 700, 500, 900, path=path)
+        plan.tile = 1 if path in (qmm.PATH_INT8, qmm.PATH_FP4) else 0   # the two-kernel form, with a workspace
+        outs.append((plan, qmm.gemm_mod_p(dA, dB, p, plan=plan, stream=side, validate=validate)))
+        # churn the allocator on the current stream while the side stream may still run
+        junk = [torch.empty(1 << 20, dtype=torch.uint8, device="cuda").fill_(0xAB) for _ in range(8)]
+        del junk
+    side.synchronize()
+    for plan, C in outs:
+        np.testing.assert_array_equal(host(C), want, err_msg=str(plan))
+    if validate:
+        dB[5, 5] = 200
+        torch.cuda.current_stream().synchronize()
+        with pytest.raises(qmm.QmmError) as ei:
+            qmm.gemm_mod_p(dA, dB, p, stream=side, validate=True)
+        assert ei.value.status == qmm.EVALUE
