@@ -202,6 +202,27 @@ qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
                           const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
                           uint8_t *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
 
+/* Largest workspace, in bytes, that qmm_gemm_mod_p_noalloc can hold (64 MiB). */
+#define QMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): qmm_gemm_mod_p with the same
+ * arguments, plan choice and kernels, but the workspace is a scratch array of
+ * QMM_NOALLOC_SCRATCH_BYTES that the library keeps in every GPU it runs on until
+ * the process ends.  The call allocates nothing: no hipMalloc, no hipFree.  The
+ * caller still passes A, B and C.  The first call on a device looks up that
+ * device's scratch address (with the device current); later calls reuse it.
+ * Every call on one GPU shares that GPU's scratch, which keeps the last call's
+ * contents (no kernel needs it cleared), so calls that overlap on one GPU --
+ * concurrent streams, or threads without ordering -- race and must be
+ * serialised by the caller.
+ * Errors: those of qmm_gemm_mod_p; QMM_ENOSPACE when the product's workspace
+ * (qmm_gemm_workspace_size) exceeds QMM_NOALLOC_SCRATCH_BYTES (nothing is
+ * launched); QMM_EDEVICE if the scratch address cannot be looked up. */
+qmm_status qmm_gemm_mod_p_noalloc(const qmm_plan *plan, int64_t m, int64_t n, int64_t k, uint32_t p,
+                                  const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
+                                  uint8_t *C, int64_t ldc, void *stream);
+
 /* Procedure (1) on already compressed operands: C = digit d of CA x CB, mod p.
  * CA: m x ceil(k/(d+1)) words from qmm_pack_rows_rev; CB: ceil(k/(d+1)) x n words
  * from qmm_pack_cols_fwd, both with this plan.  QADIC paths only; p <= 256. */

@@ -31,6 +31,7 @@ BATCH_INT8_ONLY = 2
 BATCH_SHAPE_64x64, BATCH_SHAPE_32x128, BATCH_SHAPE_128x32, BATCH_SHAPE_128x128 = 0x100, 0x200, 0x300, 0x400
 BATCH_MEASURE = 0x1000
 BATCH_RAW = 0x2000
+NOALLOC_SCRATCH_BYTES = 64 << 20  # QMM_NOALLOC_SCRATCH_BYTES
 N_BATCH_COSTS = 8  # (fixed, per_stage) for each of the four INT8 tile shapes
 # unpack selectors
 ROWS_REV, COLS_FWD, ROWS_FWD = 0, 1, 2
@@ -43,7 +44,7 @@ EXPORTS = [
     "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs", "qmm_count_nonresidues",
     "qmm_pack_fp4_rows", "qmm_pack_fp4_cols", "qmm_gemm_fp4", "qmm_pack_fp4",
     "qmm_gemm_packed_compress", "qmm_pack_left", "qmm_pack_full_right", "qmm_gemm_left_packed",
-    "qmm_gemm_full_packed", "qmm_operand_ld",
+    "qmm_gemm_full_packed", "qmm_operand_ld", "qmm_gemm_mod_p_noalloc",
 ]
 
 
@@ -118,6 +119,7 @@ def lib():
             "qmm_gemm_left_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
             "qmm_gemm_full_packed": [P, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp],
             "qmm_operand_ld": [P, i64, ctypes.POINTER(i64)],
+            "qmm_gemm_mod_p_noalloc": [P, i64, i64, i64, u32, vp, i64, vp, i64, vp, i64, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -332,6 +334,25 @@ def gemm_mod_p(A, B, p, plan=None, C=None, ws=None, stream=None, validate=False)
         ws = _new(workspace(plan, m, n, k, A.device), stream)
     _check(lib().qmm_gemm_mod_p(ctypes.byref(plan), m, n, k, p, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C),
                                 _ptr(ws), ws.numel(), _stream(stream)), "qmm_gemm_mod_p")
+    return C
+
+
+def gemm_mod_p_noalloc(A, B, p, plan=None, C=None, stream=None):
+    """C = A x B mod p through qmm_gemm_mod_p_noalloc: no workspace argument, the
+    library's per-GPU scratch instead (products whose workspace exceeds
+    NOALLOC_SCRATCH_BYTES raise QmmError(ENOSPACE)).  plan=None passes NULL, so the
+    library chooses the plan, as qmm_gemm_mod_p does."""
+    import torch
+    _u8(A, "A")
+    _u8(B, "B")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = _new(torch.empty((m, n), dtype=torch.uint8, device=A.device), stream)
+    _check(lib().qmm_gemm_mod_p_noalloc(ctypes.byref(plan) if plan is not None else None, m, n, k, p, _ptr(A), _ld(A),
+                                        _ptr(B), _ld(B), _ptr(C), _ld(C), _stream(stream)), "qmm_gemm_mod_p_noalloc")
     return C
 
 
