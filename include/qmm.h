@@ -396,16 +396,50 @@ qmm_status qmm_batched_create(int64_t count, const qmm_problem *probs, uint32_t 
 /* Replays the recorded launch on `stream`: every product of the batch. */
 qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream);
 
-/* Autotuner calibration: times whole batches of each INT8 tile shape on
- * synthetic products (allocating and freeing its own device buffers,
- * synchronising `stream`) and fits per-tile cost = fixed + per_stage * (k / 128).
- * Later qmm_batched_create calls use the fit.  costs (may be NULL) receives 8
- * doubles: (fixed, per_stage) for 64x64, 32x128, 128x32 and 128x128, in units of
- * one 128-byte K stage of a 64x64 tile. */
-qmm_status qmm_batched_tune(void *stream, double *costs);
+/* Autotuner calibration (the measured half of the cost model of section 5,
+ * Table 2 being the prior): times whole batches of each tile shape on synthetic
+ * m x n products at prime p, with k = 128 and k = 1024 (synchronising `stream`),
+ * and fits per-tile cost = fixed + per_stage * (k / 128).  costs (may be NULL)
+ * receives 8 doubles: (fixed, per_stage) for 64x64, 32x128, 128x32 and 128x128,
+ * in units of one 128-byte K stage of a 64x64 tile.  The calibration products
+ * read and write the caller's workspace ws (device, ws_bytes >=
+ * qmm_batched_tune_workspace_size(m, n); its contents are overwritten); the only
+ * device memory allocated is that of the calibration batches, inside
+ * qmm_batched_create, freed before the call returns.  The fit becomes the
+ * default costs of this process and is stored in the tune cache under (this
+ * GPU's architecture, the encoding of p -- FP4 codes for p <= 8, centred int8
+ * otherwise --, the shape bucket of m x n); when the environment variable
+ * QMM_TUNE_CACHE names a file, the cache is written there.
+ * Errors: QMM_EINVAL for p outside [2, 256] or m, n outside [1, 4096],
+ * QMM_ENOSPACE for a short workspace, QMM_EDEVICE for runtime failures. */
+qmm_status qmm_batched_tune(uint32_t p, int64_t m, int64_t n, void *ws, size_t ws_bytes, void *stream,
+                            double *costs);
 
-/* Installs previously measured costs (8 doubles, as qmm_batched_tune returns). */
+/* Workspace bytes qmm_batched_tune(p, m, n, ...) needs. */
+qmm_status qmm_batched_tune_workspace_size(int64_t m, int64_t n, size_t *bytes);
+
+/* Installs default costs (8 doubles, as qmm_batched_tune returns), used for
+ * products that the tune cache has no entry for. */
 qmm_status qmm_batched_set_costs(const double *costs);
+
+/* The tune cache (host only).  Entries map (arch -- the device's gcnArchName up
+ * to the first ':', e.g. "gfx950" --, encoding of p, shape bucket of max(m, n):
+ * up to 128, up to 512, above) to the 8 costs of qmm_batched_tune.
+ * qmm_batched_create reads the file named by QMM_TUNE_CACHE (if set) the first
+ * time it runs in a process, then gives each product the costs of the entry with
+ * its device's architecture and its encoding whose bucket is nearest its own,
+ * or the default costs when there is none.  The file is JSON:
+ *   {"version": 1, "entries": [{"arch": "gfx950", "enc": "fp4" | "int8",
+ *    "bucket": "le128" | "le512" | "gt512", "costs": [8 numbers]}, ...]}
+ * put stores (replacing an entry of the same key); get returns the entry of the
+ * same arch and encoding with the nearest bucket (QMM_EVALUE if there is none);
+ * load merges a file into memory (QMM_EINVAL if it is missing or malformed);
+ * save writes every entry (to path.tmp, then renamed); clear empties memory. */
+qmm_status qmm_tune_cache_put(const char *arch, uint32_t p, int64_t m, int64_t n, const double *costs);
+qmm_status qmm_tune_cache_get(const char *arch, uint32_t p, int64_t m, int64_t n, double *costs);
+qmm_status qmm_tune_cache_load(const char *path);
+qmm_status qmm_tune_cache_save(const char *path);
+qmm_status qmm_tune_cache_clear(void);
 
 /* Plan chosen for product i of the batch (host copy); plan->tile holds the INT8
  * tile shape (0 = 64x64, 1 = 32x128, 2 = 128x32, 3 = 128x128). */

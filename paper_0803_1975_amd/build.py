@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmm.so")
-SOURCES = ["qmm_plan.cpp", "qmm_api.cpp", "qmm_pack.hip", "qmm_gemm.hip", "qmm_int8.hip", "qmm_batched.hip",
+SOURCES = ["qmm_plan.cpp", "qmm_api.cpp", "qmm_tune_cache.cpp", "qmm_pack.hip", "qmm_gemm.hip", "qmm_int8.hip", "qmm_batched.hip",
            "qmm_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

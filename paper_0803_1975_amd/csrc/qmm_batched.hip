@@ -617,16 +617,16 @@ struct ShapeCost {
 };
 ShapeCost g_costs[SHAPE_COUNT] = {{2.0, 1.0}, {2.0, 1.1}, {2.0, 1.1}, {3.0, 3.0}};
 
-double tile_cost(uint32_t shape, int64_t m, int64_t n, int64_t k) {
+double tile_cost(const ShapeCost *costs, uint32_t shape, int64_t m, int64_t n, int64_t k) {
     const int64_t tiles = ceil_div(m, shape_bm(shape)) * ceil_div(n, shape_bn(shape));
-    return (double)tiles * (g_costs[shape].fixed + g_costs[shape].per_stage * (double)ceil_div(k, KT));
+    return (double)tiles * (costs[shape].fixed + costs[shape].per_stage * (double)ceil_div(k, KT));
 }
 
-uint32_t tune_shape(int64_t m, int64_t n, int64_t k) {
+uint32_t tune_shape(const ShapeCost *costs, int64_t m, int64_t n, int64_t k) {
     uint32_t best = SHAPE_64x64;
-    double bc = tile_cost(SHAPE_64x64, m, n, k);
+    double bc = tile_cost(costs, SHAPE_64x64, m, n, k);
     for (uint32_t s = 1; s < SHAPE_COUNT; ++s) {
-        const double c = tile_cost(s, m, n, k);
+        const double c = tile_cost(costs, s, m, n, k);
         if (c < bc) {
             bc = c;
             best = s;
@@ -637,6 +637,19 @@ uint32_t tune_shape(int64_t m, int64_t n, int64_t k) {
 
 qmm_status hip_fail(hipError_t e, const char *what) {
     return fail(QMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Architecture name of the current device ("gfx950"), the key of the tune cache.
+qmm_status device_arch(std::string &arch) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return QMM_OK;
 }
 
 // A single small product on the FP64 Q-adic path in one launch: one workgroup per
@@ -730,6 +743,10 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
     b->raw = (flags & QMM_BATCH_RAW) != 0;
     if (b->raw) flags |= QMM_BATCH_INT8_ONLY;  // raw tiles centre bytes; FP4 codes need the pack
     b->plans.resize((size_t)count);
+    const qmm_status st0 = tune_cache_load_env_once();
+    if (st0 != QMM_OK) return st0;
+    std::string arch;        // the device's, looked up at the first tile-cost lookup
+    bool arch_known = false;
     std::vector<Desc> descs((size_t)count);
     std::vector<std::pair<double, TileRef>> tiles[kClasses];
     std::vector<PackJob> jobs;
@@ -788,6 +805,7 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         D.c_vec = ((uintptr_t)P.C % 4 == 0) && (P.ldc % 4 == 0);
         D.invp = 1.0 / (double)P.p;
         int bm = 64, bn = 64;
+        ShapeCost costs[SHAPE_COUNT];  // the product's tile costs (INT8 and FP4 tiles)
         if (lowp) {
             const uint32_t h = (P.p - 1) / 2;
             D.add_h = (127u - h) * 0x01010101u;
@@ -795,7 +813,19 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
             D.fp4 = pl.path == QMM_PATH_FP4;
             if (D.fp4) fp4_lut(P.p, D.lut_lo, D.lut_hi);
             const uint32_t forced = (flags & QMM_BATCH_SHAPE_MASK) >> 8;  // 1 + shape, 0 = autotuned
-            D.shape = forced ? forced - 1 : tune_shape(P.m, P.n, P.k);
+            // costs tuned for this architecture, encoding and shape bucket when the
+            // cache has them, else the current defaults
+            double cached[kTuneCosts];
+            if (!arch_known) {
+                if (device_arch(arch) != QMM_OK) arch.clear();  // no device: no cached costs apply
+                arch_known = true;
+            }
+            if (!arch.empty() && tune_cache_lookup(arch, D.fp4 ? 1u : 0u, tune_bucket(P.m, P.n), cached)) {
+                for (uint32_t sh = 0; sh < SHAPE_COUNT; ++sh) costs[sh] = ShapeCost{cached[2 * sh], cached[2 * sh + 1]};
+            } else {
+                for (uint32_t sh = 0; sh < SHAPE_COUNT; ++sh) costs[sh] = g_costs[sh];
+            }
+            D.shape = forced ? forced - 1 : tune_shape(costs, P.m, P.n, P.k);
             pl.tile = D.shape;
             bm = shape_bm(D.shape);
             bn = shape_bn(D.shape);
@@ -831,7 +861,7 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         }
         const int32_t tmax = (int32_t)ceil_div(P.m, bm), nmax = (int32_t)ceil_div(P.n, bn);
         // cost in K-stage units: an FP4 tile streams half the bytes of an INT8 one
-        const double cost = lowp ? tile_cost(D.shape, bm, bn, D.fp4 ? ceil_div(P.k, 2) : P.k)
+        const double cost = lowp ? tile_cost(costs, D.shape, bm, bn, D.fp4 ? ceil_div(P.k, 2) : P.k)
                                  : (double)ceil_div(words_for(P.k < 1 ? 1 : P.k, pl.d), KW) * 4.0;
         const int cls = lowp ? (int)D.shape + (D.fp4 ? kFp4Class : 0) : kFp64Class;
         for (int32_t tm = 0; tm < tmax; ++tm)
@@ -1054,32 +1084,67 @@ extern "C" qmm_status qmm_gemm_mod_p_batched(qmm_batched *batch, void *stream) {
     return QMM_OK;
 }
 
-extern "C" qmm_status qmm_batched_tune(void *stream, double *costs) {
-    // Times whole batches (pack and product) on two synthetic workloads per tile
-    // shape (a short and a long k) and fits cost = fixed + per_stage * stages per
-    // tile, in units of one 128-byte stage of the 64 x 64 shape.
-    const int64_t mm = 256, nn = 256, reps = 10;
-    const int64_t ks[2] = {128, 1024};
-    const int count = 256;
-    hipError_t e;
-    uint8_t *buf = nullptr;
-    const size_t abytes = (size_t)mm * 1024, bbytes = (size_t)1024 * nn, cbytes = (size_t)mm * nn;
-    if ((e = hipMalloc(&buf, abytes + bbytes + cbytes * count)) != hipSuccess) return hip_fail(e, "hipMalloc");
-    if ((e = hipMemsetAsync(buf, 1, abytes + bbytes, (hipStream_t)stream)) != hipSuccess) {
-        (void)hipFree(buf);
-        return hip_fail(e, "hipMemsetAsync");
-    }
+namespace {
+// Calibration batches of qmm_batched_tune: `count` products of m x n x k (k = 128
+// and 1024), all reading one A (m x 1024) and one B (1024 x n) and writing their
+// own C, enough tiles to fill the GPU.
+int64_t tune_count(int64_t m, int64_t n) {
+    const int64_t c = ((int64_t)1 << 24) / std::max<int64_t>(1, m * n);
+    return std::min<int64_t>(1024, std::max<int64_t>(16, c));
+}
+constexpr int64_t kTuneKMax = 1024;
+struct TuneLayout {
+    size_t a = 0, b = 0, c = 0, bytes = 0;
+};
+TuneLayout tune_layout(int64_t m, int64_t n) {
+    TuneLayout L;
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    L.b = up((size_t)m * kTuneKMax);
+    L.c = L.b + up((size_t)kTuneKMax * n);
+    L.bytes = L.c + up((size_t)tune_count(m, n) * m * n);
+    return L;
+}
+}  // namespace
+
+extern "C" qmm_status qmm_batched_tune_workspace_size(int64_t m, int64_t n, size_t *bytes) {
+    if (!bytes) return fail(QMM_EINVAL, "bytes is NULL");
+    if (m < 1 || n < 1 || m > 4096 || n > 4096) return fail(QMM_EINVAL, "calibration products need 1 <= m, n <= 4096");
+    *bytes = tune_layout(m, n).bytes;
+    return QMM_OK;
+}
+
+extern "C" qmm_status qmm_batched_tune(uint32_t p, int64_t m, int64_t n, void *ws, size_t ws_bytes, void *stream,
+                                       double *costs) {
+    // Times whole batches (pack and product) of each tile shape on two synthetic
+    // workloads of m x n products at prime p (a short and a long k) and fits
+    // cost = fixed + per_stage * stages per tile, in units of one 128-byte stage of
+    // the 64 x 64 shape.  The buffers are the caller's workspace.
+    if (p < 2 || p > 256) return fail(QMM_EINVAL, "p must be in [2, 256]");
+    if (m < 1 || n < 1 || m > 4096 || n > 4096) return fail(QMM_EINVAL, "calibration products need 1 <= m, n <= 4096");
+    const TuneLayout L = tune_layout(m, n);
+    if (!ws || ws_bytes < L.bytes)
+        return fail(QMM_ENOSPACE, "calibration workspace needs " + std::to_string(L.bytes) + " bytes");
+    const int64_t reps = 10, count = tune_count(m, n);
+    const int64_t ks[2] = {128, kTuneKMax};
+    uint8_t *buf = (uint8_t *)ws;
+    qmm_status st = launch_fill_u8(buf, 1, (int64_t)L.c, (int64_t)L.c, 1, stream);  // A and B: residue 1
+    if (st != QMM_OK) return st;
+    std::string arch;
+    if ((st = device_arch(arch)) != QMM_OK) return st;
     double ms[SHAPE_COUNT][2];
     hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    qmm_status st = QMM_OK;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
     for (uint32_t sh = 0; sh < SHAPE_COUNT && st == QMM_OK; ++sh) {
         for (int ki = 0; ki < 2 && st == QMM_OK; ++ki) {
             std::vector<qmm_problem> probs((size_t)count);
-            for (int i = 0; i < count; ++i)
-                probs[(size_t)i] = qmm_problem{mm, nn, ks[ki], 7, buf, 1024, buf + abytes, nn,
-                                               buf + abytes + bbytes + (size_t)i * cbytes, nn};
+            for (int64_t i = 0; i < count; ++i)
+                probs[(size_t)i] = qmm_problem{m, n, ks[ki], p, buf, kTuneKMax, buf + L.b, n,
+                                               buf + L.c + (size_t)i * m * n, n};
             qmm_batched *b = nullptr;
             st = qmm_batched_create(count, probs.data(), (sh + 1) << 8, &b);
             if (st != QMM_OK) break;
@@ -1087,33 +1152,35 @@ extern "C" qmm_status qmm_batched_tune(void *stream, double *costs) {
             (void)hipEventRecord(e0, (hipStream_t)stream);
             for (int r = 0; r < reps; ++r) (void)qmm_gemm_mod_p_batched(b, stream);
             (void)hipEventRecord(e1, (hipStream_t)stream);
-            (void)hipEventSynchronize(e1);
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
             float t = 0.f;
             (void)hipEventElapsedTime(&t, e0, e1);
-            const double tiles = (double)(ceil_div(mm, shape_bm(sh)) * ceil_div(nn, shape_bn(sh)) * count);
+            const double tiles = (double)(ceil_div(m, shape_bm(sh)) * ceil_div(n, shape_bn(sh)) * count);
             ms[sh][ki] = (double)t / reps / tiles;  // per tile
             qmm_batched_destroy(b);
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipFree(buf);
     if (st != QMM_OK) return st;
     // per-tile time = fixed + per_stage * stages; unit: one stage of the 64 x 64 shape
     const double s0 = (double)ceil_div(ks[0], KT), s1 = (double)ceil_div(ks[1], KT);
     const double unit = (ms[0][1] - ms[0][0]) / (s1 - s0);
     if (!(unit > 0)) return fail(QMM_EDEVICE, "tuning runs gave no usable timing");
+    double fit[kTuneCosts];
     for (uint32_t sh = 0; sh < SHAPE_COUNT; ++sh) {
         const double per = (ms[sh][1] - ms[sh][0]) / (s1 - s0) / unit;
         const double fixed = ms[sh][0] / unit - per * s0;
         g_costs[sh].per_stage = per > 0.05 ? per : 0.05;
         g_costs[sh].fixed = fixed > 0 ? fixed : 0;
-        if (costs) {
-            costs[2 * sh] = g_costs[sh].fixed;
-            costs[2 * sh + 1] = g_costs[sh].per_stage;
-        }
+        fit[2 * sh] = g_costs[sh].fixed;
+        fit[2 * sh + 1] = g_costs[sh].per_stage;
     }
-    return QMM_OK;
+    if (costs) std::memcpy(costs, fit, sizeof(fit));
+    // the calibration batches ran FP4 codes for p <= 8 and centred bytes otherwise
+    if ((st = tune_cache_load_env_once()) != QMM_OK) return st;
+    tune_cache_put(arch, tune_enc(p), tune_bucket(m, n), fit);
+    return tune_cache_save_env();
 }
 
 extern "C" qmm_status qmm_batched_set_costs(const double *costs) {

@@ -84,6 +84,26 @@ template <> __device__ __forceinline__ float word_from_u64<float>(uint64_t v) { 
 __device__ __forceinline__ uint64_t u64_from_word(double w) { return (uint64_t)w; }
 __device__ __forceinline__ uint64_t u64_from_word(float w) { return (uint64_t)w; }
 
+// The bits of an exact word 0 <= w < 2^(beta-1) (a product word of the exact
+// regime: every coefficient below Q and t (d+1) <= beta - 1) with one addition:
+// w + 2^(beta-1) lies in [2^(beta-1), 2^beta), where the ulp is 1, so the sum is
+// exact and its low beta-1 mantissa bits are w.  (A conversion to a 64-bit integer
+// takes a sequence of instructions.)
+__device__ __forceinline__ uint64_t exact_word_bits(double w) {
+    return (uint64_t)__double_as_longlong(w + 4503599627370496.0) & ((1ull << 52) - 1);
+}
+__device__ __forceinline__ uint64_t exact_word_bits(float w) {
+    return (uint64_t)(__float_as_uint(w + 8388608.0f) & ((1u << 23) - 1));
+}
+
+// Bit field [sh, sh + t) of a 64-bit value with t <= 32, from its 32-bit halves
+// (alignbit shifts the pair hi:lo right by sh < 32).
+__device__ __forceinline__ uint32_t bit_field(uint64_t x, uint32_t sh, uint32_t mask) {
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const uint32_t v = sh < 32 ? __builtin_amdgcn_alignbit(hi, lo, sh) : hi >> (sh - 32);
+    return v & mask;
+}
+
 // Low 32 bits of the encoding: in the OFFSET regime they are the low bits of
 // floor(S / Q^d), i.e. digit d in the low t bits.
 __device__ __forceinline__ uint32_t low_mantissa_bits(double w) {

@@ -28,9 +28,11 @@
 // Exactness (see the planner): the MFMA on gfx950 adds each product to the
 // accumulator with one fused, correctly rounded step, in k order.  In the EXACT
 // regime nothing rounds; in the OFFSET regime the accumulator starts at
-// M = 2^(beta-1) Q^d and each step floors onto a multiple of Q^d.  Blocked plans
-// reduce digit d of every block mod p into integer registers at block boundaries
-// and restart the accumulator at M.
+// M = 2^(beta-1) Q^d and each step floors onto a multiple of Q^d.  Blocked plans collect digit d of every finished block in integer registers:
+// for t <= 15 as plain sums in 16-bit fields, two outputs to a register (four
+// integer operations per pair of outputs and block), reduced mod p only every
+// few blocks, before a field could overflow; for larger t each block's digit is
+// reduced mod p into a byte field at once.  The accumulators then restart at M.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,6 +69,9 @@ constexpr int BM = 128, BN = 128, KT = kQadicKT, NT = 256, APAD = 1;
 static_assert(KT == 16, "the staging maps below assume 16-element K stages");
 
 enum { EPI_QADIC = 0, EPI_REDQ = 1, EPI_PACK = 2 };
+// Blocked k (reading of section 2.4's bound per block): none, digits reduced mod p
+// into byte fields at every block, or summed into 16-bit fields (t <= 15).
+enum { BLK_NONE = 0, BLK_BYTE = 1, BLK_SUM16 = 2 };
 
 struct GemmArgs {
     int64_t m, n, kdim;      // rows and columns of the product of (packed) operands, inner length
@@ -85,6 +90,7 @@ struct GemmArgs {
     void *CW;                // EPI_PACK: compressed output, words
     int64_t ldcw, n_words;
     int32_t kb_tiles;        // K stages per block (blocked Q-adic plans)
+    int32_t fold_blocks;     // BLK_SUM16: blocks summed into a 16-bit field between reductions
     uint32_t p, t, d, td;
     uint64_t qmask;
     double invp;
@@ -92,6 +98,7 @@ struct GemmArgs {
     uint32_t m32;            // mod_u32_m32 multiplier for p, floor(2^32 / p)
     double inv_qd, inv_q, q; // 2^-td, 2^-t, 2^t (exact-regime digit)
     int32_t small_digit;     // t <= 31: digits fit 32 bits
+    int32_t lds_epi;         // C and ldc 4-byte aligned and 4 x 512 E bytes fit the staging buffers
 };
 
 // Output tile of this workgroup.  Workgroups are dealt round-robin to the 8 XCDs;
@@ -112,8 +119,9 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int &tm, i
     tn = local / gsize;
 }
 
-template <typename W, typename AT, typename BT, int EPI, bool OFFSET, bool BLOCKED>
+template <typename W, typename AT, typename BT, int EPI, bool OFFSET, int BLK>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
+    constexpr bool BLOCKED = BLK != BLK_NONE;
     using MM = Mma<W>;
     using acc_t = typename MM::acc_t;
     __shared__ W sA[2][BM][KT + APAD];
@@ -131,14 +139,18 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = acc_t{start, start, start, start};
-    // Blocked plans: the residues of the finished blocks, reduced mod p (< 256, since
-    // results are bytes), four to a register.
-    uint32_t res[4][4];
+    // Blocked plans: what the finished blocks left for each output.  BLK_BYTE: their
+    // digits reduced mod p (< 256, since results are bytes), four to a register;
+    // BLK_SUM16: the sum of their digits (a residue after each fold), two to a register.
+    constexpr int RES_W = BLK == BLK_SUM16 ? 2 : 1;
+    uint32_t res[4][4][RES_W];
     if constexpr (BLOCKED) {
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni) res[mi][ni] = 0;
+            for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                for (int h = 0; h < RES_W; ++h) res[mi][ni][h] = 0;
     }
 
     // Staging: A row ra_r, elements ra_k..ra_k+7; B row rb_k, columns rb_c..rb_c+7.
@@ -177,27 +189,40 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
         if constexpr (OFFSET) return low_mantissa_bits(a) & (uint32_t)g.qmask;
         else return exact_digit<W>(a, (W)g.inv_qd, (W)g.inv_q, (W)g.q);
     };
+    // End of a block: its digits join the finished blocks'.
     auto reduce_block = [&]() {
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni) {
-                uint32_t packed = 0;
+                if constexpr (BLK == BLK_SUM16) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    packed |= mod_u32_m32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.m32) << (8 * r);
-                res[mi][ni] = packed;
-                acc[mi][ni] = acc_t{start, start, start, start};
+                    for (int h = 0; h < 2; ++h)
+                        res[mi][ni][h] += digit32(acc[mi][ni][2 * h]) | digit32(acc[mi][ni][2 * h + 1]) << 16;
+                } else {
+                    uint32_t packed = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        packed |= mod_u32_m32(((res[mi][ni][0] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p,
+                                              g.m32) << (8 * r);
+                    res[mi][ni][0] = packed;
+                }
             }
     };
-
-    const int ntiles = (int)ceil_div(g.kdim, KT);
-    load_stage(0);
-    store_stage(0);
-    __syncthreads();
-    for (int kt = 0; kt < ntiles; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < ntiles) load_stage(kt + 1);
+    // BLK_SUM16: every field back to a residue, so fold_blocks more digits fit.
+    auto fold = [&]() {
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                for (int h = 0; h < RES_W; ++h) {
+                    const uint32_t v = res[mi][ni][h];
+                    res[mi][ni][h] = mod_u32_m32(v & 0xffffu, g.p, g.m32) | mod_u32_m32(v >> 16, g.p, g.m32) << 16;
+                }
+    };
+    // The four k-steps of one LDS stage.
+    auto mma_stage = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < KT / 4; ++ks) {
             W af[4], bf[4];
@@ -208,10 +233,37 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = MM::mma(af[mi], bf[ni], acc[mi][ni]);
+                for (int ni = 0; ni < 4; ++ni) {
+                    acc[mi][ni] = MM::mma(af[mi], bf[ni], acc[mi][ni]);
+                }
         }
+    };
+
+    const int ntiles = (int)ceil_div(g.kdim, KT);
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+    int blk_left = g.kb_tiles;      // stages left in the current block (blocked plans)
+    int fold_left = g.fold_blocks;  // blocks before the next fold (BLK_SUM16)
+    for (int kt = 0; kt < ntiles; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < ntiles) load_stage(kt + 1);
+        mma_stage(buf);
         if constexpr (BLOCKED) {
-            if ((kt + 1) % g.kb_tiles == 0 && kt + 1 < ntiles) reduce_block();
+            if (--blk_left == 0 && kt + 1 < ntiles) {
+                blk_left = g.kb_tiles;
+                reduce_block();
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = acc_t{start, start, start, start};
+                if constexpr (BLK == BLK_SUM16) {
+                    if (--fold_left == 0) {
+                        fold_left = g.fold_blocks;
+                        fold();
+                    }
+                }
+            }
         }
         if (kt + 1 < ntiles) {
             store_stage(buf ^ 1);
@@ -222,8 +274,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     // Epilogue.
     // Digit d of the accumulated word at (mi, ni, r), reduced mod p.
     auto qadic_value = [&](int mi, int ni, int r) -> uint32_t {
-        if constexpr (BLOCKED)
-            return mod_u32_m32(((res[mi][ni] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.m32);
+        if constexpr (BLK == BLK_SUM16)
+            return mod_u32_m32(((res[mi][ni][r >> 1] >> (16 * (r & 1))) & 0xffffu) + digit32(acc[mi][ni][r]), g.p, g.m32);
+        else if constexpr (BLOCKED)
+            return mod_u32_m32(((res[mi][ni][0] >> (8 * r)) & 0xffu) + digit32(acc[mi][ni][r]), g.p, g.m32);
         else if (g.small_digit) return mod_u32_m32(digit32(acc[mi][ni][r]), g.p, g.m32);
         else return mod_u64(qadic_digit<W>(acc[mi][ni][r], OFFSET, g.td, g.qmask), g.p, g.invp);
     };
@@ -291,6 +345,99 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
         }
         return;
     }
+    // Residue (i, j) of the word at (mi, ni, r): entry (i, j) of the word's
+    // (dq+1) x (dth+1) block of C.  The exact word r = sum_q c_q Q^q holds every
+    // coefficient c_q < Q (eq. (3)) as the bit field [tq, tq + t): REDQ's output,
+    // c_q mod p, is that field reduced with a 32-bit multiply-high (t <= 32) or the
+    // double reciprocal; coefficient q = i + j (dq+1).
+    auto redq_value = [&](uint64_t w, int32_t i, int32_t j) -> uint32_t {
+        const uint32_t sh = g.t * (uint32_t)(i + j * (int32_t)(g.dq + 1));
+        if (g.small_digit) return mod_u32_m32(bit_field(w, sh, (uint32_t)g.qmask), g.p, g.m32);
+        return mod_u64((w >> sh) & g.qmask, g.p, g.invp);
+    };
+    if constexpr (EPI == EPI_QADIC) {
+        if (g.lds_epi && row0 + BM <= g.m && col0 + BN <= g.n) {
+            // Whole tile, one residue per word: the four registers of a lane are four
+            // rows of one column, and the four lanes of a quad hold four consecutive
+            // columns of the same rows.  Packed into a dword and transposed across the
+            // quad (two DPP exchanges), they become four consecutive bytes of one row
+            // per lane: one dword store per lane and block instead of four byte stores.
+            const int j = lane & 3;
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) w |= qadic_value(mi, ni, r) << (8 * r);
+                    w = quad_transpose_bytes(w, j);
+                    const int64_t row = row0 + wm * 64 + mi * 16 + MM::row(lane, j);
+                    const int64_t col = col0 + wn * 64 + ni * 16 + (lane & 15) - j;
+                    *(uint32_t *)(g.C + row * g.ldc + col) = w;
+                }
+            return;
+        }
+    }
+    if (EPI != EPI_QADIC && g.lds_epi) {
+        // Coalesced stores: one 16 x 16 MFMA block of words at a time, each wavefront
+        // lays its words' residues out in LDS as the bytes of C they become (a block
+        // of 16 (dq+1) rows by 16 (dth+1) bytes), then every lane reads back whole
+        // dwords of those rows and stores them: E = (dq+1)(dth+1) dword stores per
+        // lane and block instead of 4 E scattered byte stores.  The staging buffers
+        // are free once every wavefront has read the last stage; each wavefront
+        // alternates between two regions of 256 E bytes, so one barrier per block
+        // orders the writes before the reads (and the reads of a region before its
+        // next writes, two blocks later).
+        const int dq1 = EPI == EPI_QADIC ? 1 : (int)g.dq + 1, dt1 = EPI == EPI_QADIC ? 1 : (int)g.dth + 1;
+        const int E = dq1 * dt1, rowb = 16 * dt1, row_dw = 4 * dt1;
+        uint8_t *region = (uint8_t *)&sA[0][0][0] + wave * 512 * E;
+        // lane's first dword of a block: row lr0, dword ld0; then 64 dwords further on
+        const int step_r = 64 / row_dw, step_d = 64 - step_r * row_dw;
+        const int lr0 = lane / row_dw, ld0 = lane - lr0 * row_dw;
+        __syncthreads();
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                uint8_t *blk = region + ((mi * 4 + ni) & 1) * 256 * E;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int wr = MM::row(lane, r), wc = lane & 15;
+                    if constexpr (EPI == EPI_QADIC) {
+                        blk[wr * 16 + wc] = (uint8_t)qadic_value(mi, ni, r);
+                    } else {
+                        const uint64_t w = exact_word_bits(acc[mi][ni][r]);
+                        for (int32_t j = 0; j < dt1; ++j)
+                            for (int32_t i = 0; i < dq1; ++i)
+                                blk[(wr * dq1 + i) * rowb + wc * dt1 + j] = (uint8_t)redq_value(w, i, j);
+                    }
+                }
+                __syncthreads();
+                const int64_t orow = (row0 + wm * 64 + mi * 16) * dq1, ocol = (col0 + wn * 64 + ni * 16) * dt1;
+                int lr = lr0, ld = ld0;
+                for (int u = 0; u < E; ++u) {
+                    const uint32_t v = *(const uint32_t *)(blk + lr * rowb + 4 * ld);
+                    const int64_t ro = orow + lr, co = ocol + 4 * ld;
+                    if (ro < g.m_out) {
+                        uint8_t *dst = g.C + ro * g.ldc + co;
+                        if (co + 4 <= g.n_out) {
+                            *(uint32_t *)dst = v;
+                        } else {
+#pragma unroll
+                            for (int b = 0; b < 4; ++b)
+                                if (co + b < g.n_out) dst[b] = (uint8_t)(v >> (8 * b));
+                        }
+                    }
+                    lr += step_r;
+                    ld += step_d;
+                    if (ld >= row_dw) {
+                        ld -= row_dw;
+                        ++lr;
+                    }
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -303,23 +450,14 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
                 if constexpr (EPI == EPI_QADIC) {
                     g.C[row * g.ldc + col] = (uint8_t)qadic_value(mi, ni, r);
                 } else {
-                    // The exact word r = sum_q c_q Q^q holds every coefficient c_q < Q
-                    // (eq. (3)) as the bit field [tq, tq + t): REDQ's output, c_q mod p,
-                    // is that field reduced with a 32-bit multiply-high (t <= 32) or the
-                    // double reciprocal.  Coefficient q = i + j (dq+1) is entry (i, j) of
-                    // the word's block of C.
-                    const uint64_t w = u64_from_word(acc[mi][ni][r]);
+                    const uint64_t w = exact_word_bits(acc[mi][ni][r]);
                     for (int32_t j = 0; j <= (int32_t)g.dth; ++j) {
                         const int64_t co = col * (g.dth + 1) + j;
                         if (co >= g.n_out) break;
                         for (int32_t i = 0; i <= (int32_t)g.dq; ++i) {
                             const int64_t ro = row * (g.dq + 1) + i;
                             if (ro >= g.m_out) break;
-                            const uint32_t sh = g.t * (uint32_t)(i + j * (int32_t)(g.dq + 1));
-                            const uint64_t c = (w >> sh) & g.qmask;
-                            const uint32_t v = g.small_digit ? mod_u32_m32((uint32_t)c, g.p, g.m32)
-                                                             : mod_u64(c, g.p, g.invp);
-                            g.C[ro * g.ldc + co] = (uint8_t)v;
+                            g.C[ro * g.ldc + co] = (uint8_t)redq_value(w, i, j);
                         }
                     }
                 }
@@ -368,6 +506,14 @@ void common_args(GemmArgs &g, const qmm_plan &pl) {
     g.col_step = BN;
 }
 
+// The coalesced epilogue stores C as dwords (C and ldc 4-byte aligned) and stages
+// each wavefront's block of E residues per word twice over in the A staging buffers.
+template <typename W>
+void set_lds_epi(GemmArgs &g, int64_t E) {
+    const size_t staging = sizeof(W) * 2 * BM * (KT + APAD);
+    g.lds_epi = ((uintptr_t)g.C % 4 == 0) && (g.ldc % 4 == 0) && (size_t)(4 * 512 * E) <= staging;
+}
+
 dim3 grid_for(GemmArgs &g) {
     g.tiles_m = (int32_t)ceil_div(g.m, BM);
     g.tiles_n = (int32_t)ceil_div(g.n, g.col_step);
@@ -393,6 +539,10 @@ qmm_status launch_qadic_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     g.ldc = ldc;
     const bool blocked = pl.k_block < k;
     g.kb_tiles = blocked ? (int32_t)((pl.k_block / (pl.d + 1)) / KT) : 0;
+    // A 16-bit field holds a residue (< p) plus fold_blocks digits (each < Q).
+    const int64_t fold_blocks = pl.t <= 15 ? (int64_t)(0xffff - (pl.p - 1)) / (int64_t)((1u << pl.t) - 1) : 0;
+    const bool sum16 = blocked && fold_blocks >= 1;
+    g.fold_blocks = sum16 ? (int32_t)std::min<int64_t>(fold_blocks, 1 << 30) : 0;
     const bool offset = pl.regime == QMM_REGIME_OFFSET;
     g.start = offset ? ldexp(1.0, WordTraits<W>::beta - 1 + (int)(pl.t * pl.d)) : 0.0;
     g.inv_qd = ldexp(1.0, -(int)(pl.t * pl.d));
@@ -412,15 +562,20 @@ qmm_status launch_qadic_w(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
         if (g.tile_words < 1) return fail(QMM_EUNSUPPORTED, "compressed output needs d + 1 <= 128");
         if (!g.pack_slots) g.col_step = g.tile_words * (int32_t)(pl.d + 1);
     }
+    set_lds_epi<W>(g, 1);
     const dim3 grid = grid_for(g);
-    if (offset && blocked)
-        gemm_kernel<W, W, W, EPI, true, true><<<grid, NT, 0, s>>>(g);
+    if (offset && sum16)
+        gemm_kernel<W, W, W, EPI, true, BLK_SUM16><<<grid, NT, 0, s>>>(g);
+    else if (offset && blocked)
+        gemm_kernel<W, W, W, EPI, true, BLK_BYTE><<<grid, NT, 0, s>>>(g);
     else if (offset)
-        gemm_kernel<W, W, W, EPI, true, false><<<grid, NT, 0, s>>>(g);
+        gemm_kernel<W, W, W, EPI, true, BLK_NONE><<<grid, NT, 0, s>>>(g);
+    else if (sum16)
+        gemm_kernel<W, W, W, EPI, false, BLK_SUM16><<<grid, NT, 0, s>>>(g);
     else if (blocked)
-        gemm_kernel<W, W, W, EPI, false, true><<<grid, NT, 0, s>>>(g);
+        gemm_kernel<W, W, W, EPI, false, BLK_BYTE><<<grid, NT, 0, s>>>(g);
     else
-        gemm_kernel<W, W, W, EPI, false, false><<<grid, NT, 0, s>>>(g);
+        gemm_kernel<W, W, W, EPI, false, BLK_NONE><<<grid, NT, 0, s>>>(g);
     if (EPI == EPI_PACK && g.pack_slots && BN % (pl.d + 1) != 0) {
         const qmm_status st = check_launch("gemm_qadic_compress");
         if (st != QMM_OK) return st;
@@ -453,8 +608,9 @@ qmm_status launch_redq_w(const qmm_plan &pl, uint32_t dq, uint32_t dth, int64_t 
     g.C = C;
     g.ldc = ldc;
     g.start = 0.0;
+    set_lds_epi<W>(g, (int64_t)(dq + 1) * (dth + 1));
     const dim3 grid = grid_for(g);
-    gemm_kernel<W, AT, BT, EPI_REDQ, false, false><<<grid, NT, 0, s>>>(g);
+    gemm_kernel<W, AT, BT, EPI_REDQ, false, BLK_NONE><<<grid, NT, 0, s>>>(g);
     return check_launch(what);
 }
 

@@ -57,23 +57,25 @@ __device__ __forceinline__ uint32_t centre4(uint32_t w, uint32_t add_h, uint32_t
 // bytes in registers (4 x 4 blocks by byte permutes) and writes four 16-byte
 // k-runs, one per column, into Bt.
 constexpr int CT = 128;
-__global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
-                                                                int64_t ldb, int8_t *__restrict__ Bt, int64_t ldbt,
-                                                                uint32_t add_h, uint32_t neg_p, int b_vec) {
-    __shared__ uint32_t tile[CT][CT / 4 + 1];  // k rows x 128 column bytes, padded by one word
-    const int64_t k0 = (int64_t)blockIdx.y * CT, n0 = (int64_t)blockIdx.x * CT;
-    const int t = threadIdx.x;
-    {
-        const int seg = t & 7, r0 = t >> 3;  // 16-byte segment of a 128-byte row; rows r0 + 32 i
-        const int64_t nn = n0 + 16 * seg;
-        uint4 v[4];
+
+// The four 16-byte row segments a thread of a 128 x 128 transposing tile reads: B
+// rows k0 + r0 + 32 i, columns nn .. nn + 15 (bytes past k or n read as zero).
+// B_VEC (B and ldb 16-byte aligned): whole segments are one 16-byte load each,
+// and a segment cut by n (only in the last column tile) is read byte by byte.
+// Otherwise every segment is a dword-aligned window (raw_issue_ptr), all four
+// issued before the first is aligned, where byte loads would each wait for the one
+// before.
+template <bool B_VEC>
+__device__ __forceinline__ void load_tile_segments(const uint8_t *__restrict__ B, int64_t ldb, int64_t k, int64_t n,
+                                                   int64_t k0, int r0, int64_t nn, uint4 (&v)[4]) {
+    if constexpr (B_VEC) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t kk = k0 + r0 + 32 * i;
             v[i] = make_uint4(0, 0, 0, 0);
             if (kk < k) {
                 const uint8_t *src = B + kk * ldb + nn;
-                if (b_vec && nn + 16 <= n) {
+                if (nn + 16 <= n) {
                     v[i] = *(const uint4 *)src;
                 } else {
                     uint32_t w[4] = {0, 0, 0, 0};
@@ -83,6 +85,42 @@ __global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_
                 }
             }
         }
+        return;
+    }
+    const uint8_t *end = B + (k - 1) * ldb + n;  // one past B's data
+    uint32_t w[4][5];
+    int32_t meta[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t kk = k0 + r0 + 32 * i;
+        v[i] = make_uint4(0, 0, 0, 0);
+        meta[i] = 0;
+        if (kk < k && nn < n) {
+            raw_issue_ptr(w[i], meta[i], B + kk * ldb + nn, n - nn, end);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (meta[i] != 0) {
+            uint32_t o[4];
+            raw_finish(w[i], meta[i], o);
+            v[i] = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+    }
+}
+
+template <bool B_VEC>
+__global__ __launch_bounds__(256) void centre_transpose_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
+                                                                int64_t ldb, int8_t *__restrict__ Bt, int64_t ldbt,
+                                                                uint32_t add_h, uint32_t neg_p) {
+    __shared__ uint32_t tile[CT][CT / 4 + 1];  // k rows x 128 column bytes, padded by one word
+    const int64_t k0 = (int64_t)blockIdx.y * CT, n0 = (int64_t)blockIdx.x * CT;
+    const int t = threadIdx.x;
+    {
+        const int seg = t & 7, r0 = t >> 3;  // 16-byte segment of a 128-byte row; rows r0 + 32 i
+        const int64_t nn = n0 + 16 * seg;
+        uint4 v[4];
+        load_tile_segments<B_VEC>(B, ldb, k, n, k0, r0, nn, v);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             uint32_t *dst = &tile[r0 + 32 * i][4 * seg];
@@ -176,9 +214,10 @@ __global__ __launch_bounds__(256) void pack_fp4_rows_kernel(int64_t m, int64_t k
 // (tx, ty): the loads, LDS tile and register transposes of centre_transpose_kernel,
 // with the codes looked up on the way into LDS and each column's 16 k packed into 8
 // bytes.  Every thread of the workgroup calls it (it holds a barrier).
+template <bool B_VEC>
 __device__ __forceinline__ void fp4_cols_tile(int64_t tx, int64_t ty, int64_t k, int64_t n,
                                               const uint8_t *__restrict__ B, int64_t ldb, uint8_t *__restrict__ Bt4,
-                                              int64_t ldbt4, uint32_t lut_lo, uint32_t lut_hi, int b_vec,
+                                              int64_t ldbt4, uint32_t lut_lo, uint32_t lut_hi,
                                               uint32_t (*tile)[CT / 4 + 1]) {
     const int64_t k0 = ty * CT, n0 = tx * CT;
     const int t = threadIdx.x;
@@ -186,22 +225,7 @@ __device__ __forceinline__ void fp4_cols_tile(int64_t tx, int64_t ty, int64_t k,
         const int seg = t & 7, r0 = t >> 3;
         const int64_t nn = n0 + 16 * seg;
         uint4 v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t kk = k0 + r0 + 32 * i;
-            v[i] = make_uint4(0, 0, 0, 0);
-            if (kk < k) {
-                const uint8_t *src = B + kk * ldb + nn;
-                if (b_vec && nn + 16 <= n) {
-                    v[i] = *(const uint4 *)src;
-                } else {
-                    uint32_t w[4] = {0, 0, 0, 0};
-                    for (int b = 0; b < 16; ++b)
-                        if (nn + b < n) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
-                    v[i] = make_uint4(w[0], w[1], w[2], w[3]);
-                }
-            }
-        }
+        load_tile_segments<B_VEC>(B, ldb, k, n, k0, r0, nn, v);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             uint32_t *dst = &tile[r0 + 32 * i][4 * seg];
@@ -238,11 +262,12 @@ __device__ __forceinline__ void fp4_cols_tile(int64_t tx, int64_t ty, int64_t k,
     }
 }
 
+template <bool B_VEC>
 __global__ __launch_bounds__(256) void pack_fp4_cols_kernel(int64_t k, int64_t n, const uint8_t *__restrict__ B,
                                                             int64_t ldb, uint8_t *__restrict__ Bt4, int64_t ldbt4,
-                                                            uint32_t lut_lo, uint32_t lut_hi, int b_vec) {
+                                                            uint32_t lut_lo, uint32_t lut_hi) {
     __shared__ uint32_t tile[CT][CT / 4 + 1];
-    fp4_cols_tile(blockIdx.x, blockIdx.y, k, n, B, ldb, Bt4, ldbt4, lut_lo, lut_hi, b_vec, tile);
+    fp4_cols_tile<B_VEC>(blockIdx.x, blockIdx.y, k, n, B, ldb, Bt4, ldbt4, lut_lo, lut_hi, tile);
 }
 
 // Both conversions of an FP4 product in one launch (two kernels this size each
@@ -259,9 +284,10 @@ struct Fp4PackArgs {
     uint8_t *Bt4;
     int64_t ldbt4;
     uint32_t lut_lo, lut_hi;
-    int a_vec, b_vec;
+    int a_vec;
     int64_t a_blocks, b_tiles_x;
 };
+template <bool B_VEC>
 __global__ __launch_bounds__(256) void pack_fp4_both_kernel(Fp4PackArgs g) {
     __shared__ uint32_t tile[CT][CT / 4 + 1];
     const int64_t blk = blockIdx.x;
@@ -276,8 +302,8 @@ __global__ __launch_bounds__(256) void pack_fp4_both_kernel(Fp4PackArgs g) {
         return;
     }
     const int64_t tb = blk - g.a_blocks;
-    fp4_cols_tile(tb % g.b_tiles_x, tb / g.b_tiles_x, g.k, g.n, g.B, g.ldb, g.Bt4, g.ldbt4, g.lut_lo, g.lut_hi,
-                  g.b_vec, tile);
+    fp4_cols_tile<B_VEC>(tb % g.b_tiles_x, tb / g.b_tiles_x, g.k, g.n, g.B, g.ldb, g.Bt4, g.ldbt4, g.lut_lo,
+                         g.lut_hi, tile);
 }
 
 template <int BM, int BN>
@@ -728,8 +754,10 @@ qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, con
     uint32_t add_h, neg_p;
     centre_consts(pl.p, add_h, neg_p);
     const dim3 grid((unsigned)ceil_div(n, CT), (unsigned)ceil_div(ldbt, CT));
-    const int b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
-    centre_transpose_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt, ldbt, add_h, neg_p, b_vec);
+    if (((uintptr_t)B % 16 == 0) && (ldb % 16 == 0))
+        centre_transpose_kernel<true><<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt, ldbt, add_h, neg_p);
+    else
+        centre_transpose_kernel<false><<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt, ldbt, add_h, neg_p);
     return check_launch("centre_transpose");
 }
 
@@ -799,8 +827,10 @@ qmm_status launch_pack_fp4_cols(const qmm_plan &pl, int64_t k, int64_t n, const 
     uint32_t lo, hi;
     fp4_lut(pl.p, lo, hi);
     const dim3 grid((unsigned)ceil_div(n, CT), (unsigned)ceil_div(2 * ldbt4, CT));
-    const int b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
-    pack_fp4_cols_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt4, ldbt4, lo, hi, b_vec);
+    if (((uintptr_t)B % 16 == 0) && (ldb % 16 == 0))
+        pack_fp4_cols_kernel<true><<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt4, ldbt4, lo, hi);
+    else
+        pack_fp4_cols_kernel<false><<<grid, 256, 0, (hipStream_t)stream>>>(k, n, B, ldb, Bt4, ldbt4, lo, hi);
     return check_launch("pack_fp4_cols");
 }
 
@@ -822,12 +852,15 @@ qmm_status launch_pack_fp4_both(const qmm_plan &pl, int64_t m, int64_t n, int64_
     g.ldbt4 = ldbt4;
     fp4_lut(pl.p, g.lut_lo, g.lut_hi);
     g.a_vec = ((uintptr_t)A % 16 == 0) && (lda % 16 == 0);
-    g.b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
+    const bool b_vec = ((uintptr_t)B % 16 == 0) && (ldb % 16 == 0);
     g.a_blocks = ceil_div(m * (lda4 / 16), 256);
     g.b_tiles_x = ceil_div(n, CT);
     const int64_t blocks = g.a_blocks + (n > 0 ? g.b_tiles_x * ceil_div(2 * ldbt4, CT) : 0);
     if (blocks > INT32_MAX) return fail(QMM_EUNSUPPORTED, "FP4 conversion grid too large");
-    pack_fp4_both_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(g);
+    if (b_vec)
+        pack_fp4_both_kernel<true><<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(g);
+    else
+        pack_fp4_both_kernel<false><<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(g);
     return check_launch("pack_fp4_both");
 }
 

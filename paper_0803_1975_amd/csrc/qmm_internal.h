@@ -107,6 +107,17 @@ qmm_status launch_gemm_int8_small(const qmm_plan &pl, int64_t m, int64_t n, int6
 // Longest operand data (bytes from the first element to one past the last) that
 // kernels address with 32-bit offsets, with room for their 20-byte load windows.
 constexpr int64_t kRawSpan = (int64_t)UINT32_MAX - 63;
+
+// Autotuner cost fits: (fixed, per_stage) for each of the four batched INT8 tile
+// shapes, cached per (GPU architecture, encoding, shape bucket).
+constexpr int kTuneCosts = 8;
+uint32_t tune_enc(uint32_t p);                     // 1: FP4 codes (p <= 8), 0: centred int8
+uint32_t tune_bucket(int64_t m, int64_t n);        // max(m, n) <= 128, <= 512, larger
+void tune_cache_put(const std::string &arch, uint32_t enc, uint32_t bucket, const double *costs);
+// The entry of this architecture and encoding with the nearest bucket, if any.
+bool tune_cache_lookup(const std::string &arch, uint32_t enc, uint32_t bucket, double *costs);
+qmm_status tune_cache_load_env_once();             // QMM_TUNE_CACHE, read once per process
+qmm_status tune_cache_save_env();                  // QMM_TUNE_CACHE, if set
 // Largest m n k that qmm_gemm_mod_p runs on the one-launch INT8 kernel.
 constexpr double kSmallInt8MaxMacs = 4294967296.0;  // 2^32: one launch measured faster up to 1536^3
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,

@@ -44,7 +44,8 @@ EXPORTS = [
     "qmm_gemm_right_packed", "qmm_batched_tune", "qmm_batched_set_costs", "qmm_count_nonresidues",
     "qmm_pack_fp4_rows", "qmm_pack_fp4_cols", "qmm_gemm_fp4", "qmm_pack_fp4",
     "qmm_gemm_packed_compress", "qmm_pack_left", "qmm_pack_full_right", "qmm_gemm_left_packed",
-    "qmm_gemm_full_packed", "qmm_operand_ld", "qmm_gemm_mod_p_noalloc",
+    "qmm_gemm_full_packed", "qmm_operand_ld", "qmm_gemm_mod_p_noalloc", "qmm_batched_tune_workspace_size",
+    "qmm_tune_cache_put", "qmm_tune_cache_get", "qmm_tune_cache_load", "qmm_tune_cache_save", "qmm_tune_cache_clear",
 ]
 
 
@@ -106,7 +107,13 @@ def lib():
             "qmm_gemm_mod_p_batched": [vp, vp],
             "qmm_batched_plan": [vp, i64, P],
             "qmm_batched_destroy": [vp],
-            "qmm_batched_tune": [vp, ctypes.POINTER(ctypes.c_double)],
+            "qmm_batched_tune": [u32, i64, i64, vp, sz, vp, ctypes.POINTER(ctypes.c_double)],
+            "qmm_batched_tune_workspace_size": [i64, i64, ctypes.POINTER(sz)],
+            "qmm_tune_cache_put": [ctypes.c_char_p, u32, i64, i64, ctypes.POINTER(ctypes.c_double)],
+            "qmm_tune_cache_get": [ctypes.c_char_p, u32, i64, i64, ctypes.POINTER(ctypes.c_double)],
+            "qmm_tune_cache_load": [ctypes.c_char_p],
+            "qmm_tune_cache_save": [ctypes.c_char_p],
+            "qmm_tune_cache_clear": [],
             "qmm_batched_set_costs": [ctypes.POINTER(ctypes.c_double)],
             "qmm_count_nonresidues": [u32, i64, i64, vp, i64, vp, vp],
             "qmm_pack_fp4_rows": [P, i64, i64, vp, i64, vp, i64, vp],
@@ -508,11 +515,51 @@ def batched_create(problems, flags=0) -> Batch:
     return Batch(h, len(problems), [problems])
 
 
-def batched_tune(stream=None):
-    """Calibrate the batched autotuner on this GPU; returns the 8 fitted costs."""
+def batched_tune_workspace_size(m=256, n=256) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().qmm_batched_tune_workspace_size(m, n, ctypes.byref(out)), "qmm_batched_tune_workspace_size")
+    return out.value
+
+
+def batched_tune(p=7, m=256, n=256, ws=None, stream=None, device="cuda"):
+    """Calibrate the batched autotuner on this GPU with m x n products at prime p;
+    returns the 8 fitted costs.  ws: a device uint8 tensor of at least
+    batched_tune_workspace_size(m, n) bytes (allocated here when None)."""
+    import torch
+    if ws is None:
+        ws = _new(torch.empty(batched_tune_workspace_size(m, n), dtype=torch.uint8, device=device), stream)
     out = (ctypes.c_double * N_BATCH_COSTS)()
-    _check(lib().qmm_batched_tune(_stream(stream), out), "qmm_batched_tune")
+    _check(lib().qmm_batched_tune(p, m, n, _ptr(ws), ws.numel(), _stream(stream), out), "qmm_batched_tune")
     return list(out)
+
+
+def tune_cache_put(arch, p, m, n, costs):
+    if len(costs) != N_BATCH_COSTS:
+        raise ValueError(f"expected {N_BATCH_COSTS} costs, got {len(costs)}")
+    arr = (ctypes.c_double * N_BATCH_COSTS)(*costs)
+    _check(lib().qmm_tune_cache_put(arch.encode(), p, m, n, arr), "qmm_tune_cache_put")
+
+
+def tune_cache_get(arch, p, m, n):
+    """The cached costs for (arch, encoding of p, nearest shape bucket), or None."""
+    arr = (ctypes.c_double * N_BATCH_COSTS)()
+    st = lib().qmm_tune_cache_get(arch.encode(), p, m, n, arr)
+    if st == EVALUE:
+        return None
+    _check(st, "qmm_tune_cache_get")
+    return list(arr)
+
+
+def tune_cache_load(path):
+    _check(lib().qmm_tune_cache_load(os.fsencode(path)), "qmm_tune_cache_load")
+
+
+def tune_cache_save(path):
+    _check(lib().qmm_tune_cache_save(os.fsencode(path)), "qmm_tune_cache_save")
+
+
+def tune_cache_clear():
+    _check(lib().qmm_tune_cache_clear(), "qmm_tune_cache_clear")
 
 
 def batched_set_costs(costs):

@@ -132,6 +132,55 @@ def test_autotuner_calibration_and_choices(torch):
         batch.destroy()
 
 
+def test_tune_cache_file_gives_the_freshly_tuned_choices(torch, tmp_path, monkeypatch):
+    # Calibrate both encodings into a cache file (QMM_TUNE_CACHE), build a batch
+    # with the fresh fits; then forget them (empty cache, skewed defaults that would
+    # pick other tiles), load the file, and build the batch again: the same tiles,
+    # and both batches exact.
+    path = str(tmp_path / "tune.json")
+    monkeypatch.setenv("QMM_TUNE_CACHE", path)
+    qmm.tune_cache_clear()
+    ws = torch.empty(qmm.batched_tune_workspace_size(256, 256), dtype=torch.uint8, device="cuda")
+    fits = {p: qmm.batched_tune(p, 256, 256, ws=ws) for p in (7, 101)}
+    note("fits", fits)
+    import json
+    doc = json.load(open(path))
+    assert {(e["enc"], e["bucket"]) for e in doc["entries"]} >= {("fp4", "le512"), ("int8", "le512")}
+    arch = doc["entries"][0]["arch"]
+    assert arch.startswith("gfx")
+    assert qmm.tune_cache_get(arch, 7, 256, 256) == fits[7] and qmm.tune_cache_get(arch, 101, 300, 300) == fits[101]
+    shapes = [(7, 32, 512, 256), (7, 512, 32, 256), (101, 256, 256, 256), (101, 500, 40, 1000), (3, 400, 400, 128),
+              (13, 64, 480, 64)]
+    host, dev = make_problems(torch, shapes, 21)
+
+    def build_and_run():
+        for _, _, dC, _ in dev:
+            dC.fill_(255)
+        batch = qmm.batched_create(dev)
+        try:
+            tiles = [batch.plan(i).tile for i in range(len(shapes))]
+            batch.run()
+            torch.cuda.synchronize()
+            check_all(host, dev)
+            return tiles
+        finally:
+            batch.destroy()
+
+    fresh = build_and_run()
+    qmm.tune_cache_clear()
+    skew = [0.0, 1.0, 50.0, 9.0, 50.0, 9.0, 50.0, 9.0]   # every product on 64 x 64 tiles
+    qmm.batched_set_costs(skew)
+    try:
+        assert build_and_run() == [0] * len(shapes)
+        qmm.tune_cache_load(path)
+        cached = build_and_run()
+    finally:
+        qmm.batched_set_costs(fits[101])
+        qmm.tune_cache_clear()
+    note("tiles", fresh, cached)
+    assert cached == fresh
+
+
 def test_measuring_autotuner_keeps_a_correct_fastest_candidate(torch):
     shapes = synth.batched_shapes(count=200, seed=11)
     host, dev = make_problems(torch, shapes, 11)

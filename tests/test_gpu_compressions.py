@@ -154,6 +154,41 @@ def test_degenerate_shapes_and_guard_bytes(torch, path):
     assert (host(C) == 0).all()
 
 
+# The word products store C through LDS as whole dwords when C and its leading
+# dimension are 4-byte aligned and a wavefront's block of residues fits the staging
+# buffers (E = residues per word up to 17 for doubles, 8 for floats), and byte by
+# byte otherwise.  Each case runs both: an aligned view with a ragged right edge
+# (ldc = 260, n = 257) and a view one byte in; E spans 1 to 52.
+EPI_CASES = [(qmm.PATH_FP64_QADIC, 7, 70), (qmm.PATH_FP64_QADIC, 2, 7), (qmm.PATH_FP64_QADIC, 3, 3000),
+             (qmm.PATH_FP32_QADIC, 7, 300),
+             (qmm.PATH_FP64_REDQ, 7, 70), (qmm.PATH_FP64_REDQ, 3, 3), (qmm.PATH_FP64_REDQ, 2, 7),
+             (qmm.PATH_FP64_REDQ, 2, 3), (qmm.PATH_FP64_LEFT, 3, 20), (qmm.PATH_FP64_LEFT, 2, 1),
+             (qmm.PATH_FP64_FULL, 7, 50), (qmm.PATH_FP64_FULL, 3, 3), (qmm.PATH_FP64_FULL, 2, 7),
+             (qmm.PATH_FP64_FULL, 2, 1), (qmm.PATH_FP32_REDQ, 2, 7), (qmm.PATH_FP32_REDQ, 3, 3),
+             (qmm.PATH_FP32_LEFT, 2, 3), (qmm.PATH_FP32_FULL, 2, 1), (qmm.PATH_FP32_FULL, 7, 50)]
+
+
+@pytest.mark.parametrize("path,p,k", EPI_CASES)
+def test_dword_epilogue_and_byte_fallback(torch, path, p, k):
+    m, n = 300, 257
+    pl = qmm.choose_Qd(p, m, n, k, path=path)
+    note("epilogue", pl, k)
+    rng = np.random.default_rng(p * 100 + k + path)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    for c0, width in ((0, 260), (1, 261)):
+        big = torch.full((m + 2, width), 0xAB, dtype=torch.uint8, device="cuda")
+        C = big[1:m + 1, c0:c0 + n]
+        qmm.gemm_mod_p(dA, dB, p, plan=pl, C=C)
+        out = host(big)
+        np.testing.assert_array_equal(out[1:m + 1, c0:c0 + n], want, err_msg=f"view at column {c0}")
+        mask = np.ones_like(out, dtype=bool)
+        mask[1:m + 1, c0:c0 + n] = False
+        assert (out[mask] == 0xAB).all(), f"view at column {c0}: bytes outside C written"
+
+
 # --- ReduceAndCompress ------------------------------------------------------------
 def compress_case(torch, p, m, n, k, path=qmm.PATH_FP64_QADIC, flags=0):
     pl = qmm.choose_Qd(p, m, n, k, path=path, flags=flags)

@@ -207,6 +207,32 @@ def test_worst_case_all_p_minus_one(torch, path, p, k):
     assert (C == (k * (p - 1) ** 2) % p).all(), (plan, np.unique(C))
 
 
+# Blocked Q-adic plans with t <= 15 sum the digits of finished blocks in 16-bit
+# fields and reduce them mod p every F = floor((2^16 - p) / (Q - 1)) blocks.  The
+# k below put the block count just under, at and past a multiple of F (p = 5 at
+# t = 13: F = 8, blocks of 448), and run several folds (FP32 p = 7 and 11, t = 12:
+# F = 16, 53 and 157 blocks; FP64 p = 3, t = 10: F = 64, 417 blocks).
+FOLD_CASES = [(qmm.PATH_FP64_QADIC, 5, 3584), (qmm.PATH_FP64_QADIC, 5, 3585), (qmm.PATH_FP64_QADIC, 5, 4032),
+              (qmm.PATH_FP64_QADIC, 5, 20000), (qmm.PATH_FP64_QADIC, 3, 100000), (qmm.PATH_FP32_QADIC, 7, 5000),
+              (qmm.PATH_FP32_QADIC, 11, 5000)]
+
+
+@pytest.mark.parametrize("path,p,k", FOLD_CASES)
+def test_blocked_digit_sums_across_folds(torch, path, p, k):
+    plan = qmm.choose_Qd(p, 48, 40, k, path=path)
+    assert plan.k_block < k and plan.t <= 15, plan
+    note("folds", plan, k)
+    A = torch.full((48, k), p - 1, dtype=torch.uint8, device="cuda")
+    B = torch.full((k, 40), p - 1, dtype=torch.uint8, device="cuda")
+    C = host(qmm.gemm_mod_p(A, B, p, plan=plan))
+    assert (C == (k * (p - 1) ** 2) % p).all(), (plan, np.unique(C))
+    rng = np.random.default_rng(k + p)
+    A = rng.integers(0, p, (48, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, 40), dtype=np.uint8)
+    got = host(qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan))
+    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+
+
 def test_int8_blocked_accumulation(torch):
     # centred residue 125 of p = 251: products 15625 overflow int32 after 137438 terms
     p, k = 251, 140000
