@@ -178,7 +178,9 @@ qmm_status qmm_extract(const qmm_plan *plan, int64_t m, int64_t n, const void *T
 qmm_status qmm_redq(const qmm_plan *plan, int64_t m, int64_t n, const void *CC, int64_t ldcc,
                     uint8_t *C, int64_t ldc, void *stream);
 
-/* Device workspace that qmm_gemm_mod_p needs for this plan and shape. */
+/* Device workspace that qmm_gemm_mod_p needs for this plan and shape (INT8:
+ * centred B transposed, plus, when k is not a multiple of 16, A centred into
+ * aligned rows). */
 qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
                                    size_t *bytes);
 

@@ -78,8 +78,14 @@ Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
         L.off_b = align_up((size_t)words_for(m, pl.d) * kk * word_bytes(pl));
         L.bytes = L.off_b + align_up((size_t)kk * L.ld_b * word_bytes(pl));
     } else if (pl.path == QMM_PATH_INT8) {
+        // Bt, then (k not a multiple of 16) A centred into rows of the same length
         L.ld_b = int8_bt_ld(kk);
         L.bytes = align_up((size_t)n * L.ld_b);
+        if (kk % 16 != 0) {
+            L.ld_a = L.ld_b;
+            L.off_b = L.bytes;
+            L.bytes += align_up((size_t)m * L.ld_a);
+        }
     } else if (pl.path == QMM_PATH_FP4) {
         L.ld_a = L.ld_b = fp4_ld(kk);
         L.off_b = align_up((size_t)m * L.ld_a);
@@ -250,6 +256,12 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
     if (pl.path == QMM_PATH_INT8) {
         int8_t *Bt = (int8_t *)w;
         if ((st = launch_centre_transpose(pl, k, n, B, ldb, Bt, L.ld_b, stream)) != QMM_OK) return st;
+        if (L.ld_a > 0) {
+            // rows of A that cannot be whole 16-byte loads: centre them into aligned rows first
+            int8_t *Ac = (int8_t *)(w + L.off_b);
+            if ((st = launch_centre_rows(pl, m, k, A, lda, Ac, L.ld_a, stream)) != QMM_OK) return st;
+            return launch_gemm_int8_centred_a(pl, m, n, k, Ac, L.ld_a, Bt, L.ld_b, C, ldc, stream);
+        }
         return launch_gemm_int8(pl, m, n, k, A, lda, Bt, L.ld_b, C, ldc, stream);
     }
     if (pl.path == QMM_PATH_FP4) {

@@ -153,36 +153,52 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
                 for (int h = 0; h < RES_W; ++h) res[mi][ni][h] = 0;
     }
 
-    // Staging: A row ra_r, elements ra_k..ra_k+7; B row rb_k, columns rb_c..rb_c+7.
-    const int ra_r = tid >> 1, ra_k = (tid & 1) * 8;
-    const int rb_k = tid >> 4, rb_c = (tid & 15) * 8;
-    const int64_t a_row = row0 + ra_r;
-    const bool a_row_ok = a_row < g.m;
-    const AT *__restrict__ Ap = (const AT *)g.A + (a_row_ok ? a_row : 0) * g.lda;
+    // Staging, in pairs of elements: the A stage (BM rows of KT words) and the B stage
+    // (KT rows of BN words) are each cut into pairs p = tid + NT i (i < 4) in row-major
+    // order, so the lanes of one load or store instruction cover consecutive pairs --
+    // whole 128-byte rows of A (8 lanes a row) and 1 KB rows of B (64 lanes) -- for
+    // coalesced loads and LDS stores on distinct banks (A rows are padded by one word).
+    // A: rows ar0 + 32 i, elements ak, ak + 1; B: k-rows bk0 + 4 i, columns bc, bc + 1.
+    static_assert(BM * KT == 8 * NT && KT * BN == 8 * NT, "four pairs of each operand per thread");
+    const int ar0 = tid >> 3, ak = 2 * (tid & 7);
+    const int bk0 = tid >> 6, bc = 2 * (tid & 63);
+    const int64_t a_row = row0 + ar0;
+    const AT *__restrict__ Ap = (const AT *)g.A + a_row * g.lda;  // row ar0 + 32 i at Ap + 32 i lda
     const BT *__restrict__ Bp = (const BT *)g.B;
     W ra[8], rb[8];
 
     auto load_stage = [&](int kt) {
         const int64_t k0 = (int64_t)kt * KT;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t kk = k0 + ra_k + e;
-            ra[e] = (a_row_ok && kk < g.kdim) ? (W)Ap[kk] : (W)0;
-        }
-        const int64_t gk = k0 + rb_k;
-        const bool krow_ok = gk < g.kdim;
-        const BT *brow = Bp + (krow_ok ? gk : 0) * g.ldb;
+        for (int i = 0; i < 4; ++i) {
+            const bool row_ok = a_row + 32 * i < g.m;
+            const AT *arow = Ap + (row_ok ? (int64_t)(32 * i) * g.lda : -a_row * g.lda);  // row 0 when past m
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t cc = col0 + rb_c + e;
-            rb[e] = (krow_ok && cc < g.n) ? (W)brow[cc] : (W)0;
+            for (int e = 0; e < 2; ++e) {
+                const int64_t kk = k0 + ak + e;
+                ra[2 * i + e] = (row_ok && kk < g.kdim) ? (W)arow[kk] : (W)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t gk = k0 + bk0 + 4 * i;
+            const bool krow_ok = gk < g.kdim;
+            const BT *brow = Bp + (krow_ok ? gk : 0) * g.ldb;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int64_t cc = col0 + bc + e;
+                rb[2 * i + e] = (krow_ok && cc < g.n) ? (W)brow[cc] : (W)0;
+            }
         }
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) sA[buf][ra_r][ra_k + e] = ra[e];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) sB[buf][rb_k][rb_c + e] = rb[e];
+        for (int i = 0; i < 4; ++i) {
+            sA[buf][ar0 + 32 * i][ak] = ra[2 * i];
+            sA[buf][ar0 + 32 * i][ak + 1] = ra[2 * i + 1];
+            sB[buf][bk0 + 4 * i][bc] = rb[2 * i];
+            sB[buf][bk0 + 4 * i][bc + 1] = rb[2 * i + 1];
+        }
     };
     // Digit d of one accumulated word (t <= 31 when blocked, so it fits 32 bits).
     auto digit32 = [&](W a) -> uint32_t {

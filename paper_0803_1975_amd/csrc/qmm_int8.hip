@@ -748,6 +748,38 @@ int64_t int8_bt_ld(int64_t k) {
     return r % 2048 == 0 ? r + kBtAlign : r;
 }
 
+namespace {
+// Ac[i][16 s .. 16 s + 15] = centred(A[i][16 s .. 16 s + 15]), zero past k: one
+// thread per 16-byte segment of Ac, read as a dword-aligned window of A (rows of A
+// may start anywhere) and stored as one 16-byte store.
+__global__ __launch_bounds__(256) void centre_rows_kernel(int64_t m, int64_t k, const uint8_t *__restrict__ A,
+                                                           int64_t lda, int8_t *__restrict__ Ac, int64_t ldac,
+                                                           uint32_t add_h, uint32_t neg_p) {
+    const int64_t segs = ldac / 16;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= m * segs) return;
+    const int64_t r = idx / segs, s = idx - r * segs;
+    uint32_t w[5], o[4] = {0, 0, 0, 0};
+    int32_t meta = 0;
+    const int64_t c0 = 16 * s;
+    if (c0 < k) raw_issue_ptr(w, meta, A + r * lda + c0, k - c0, A + (m - 1) * lda + k);
+    if (meta != 0) raw_finish(w, meta, o);
+    *(uint4 *)(Ac + r * ldac + c0) = make_uint4(centre4(o[0], add_h, neg_p), centre4(o[1], add_h, neg_p),
+                                               centre4(o[2], add_h, neg_p), centre4(o[3], add_h, neg_p));
+}
+}  // namespace
+
+qmm_status launch_centre_rows(const qmm_plan &pl, int64_t m, int64_t k, const uint8_t *A, int64_t lda, int8_t *Ac,
+                              int64_t ldac, void *stream) {
+    if (m == 0) return QMM_OK;
+    uint32_t add_h, neg_p;
+    centre_consts(pl.p, add_h, neg_p);
+    const int64_t blocks = ceil_div(m * (ldac / 16), 256);
+    if (blocks > INT32_MAX) return fail(QMM_EUNSUPPORTED, "centre_rows grid too large");
+    centre_rows_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(m, k, A, lda, Ac, ldac, add_h, neg_p);
+    return check_launch("centre_rows");
+}
+
 qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, const uint8_t *B, int64_t ldb,
                                    int8_t *Bt, int64_t ldbt, void *stream) {
     if (n == 0) return QMM_OK;
@@ -900,8 +932,28 @@ qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, 
     return run_fp4<128, 128, 64, 2, 2>(g, s);
 }
 
+namespace {
+qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
+                          bool a_centred, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream);
+}  // namespace
+
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
                             const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream) {
+    return gemm_int8_impl(pl, m, n, k, A, lda, false, Bt, ldbt, C, ldc, stream);
+}
+
+// Ac holds centred rows zero padded to ldac (a multiple of 128, at least k), so the
+// product may run over k rounded up to 16: the padding adds zero terms.  With the
+// centring constants zero, centre4 is the identity.
+qmm_status launch_gemm_int8_centred_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const int8_t *Ac,
+                                      int64_t ldac, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc,
+                                      void *stream) {
+    return gemm_int8_impl(pl, m, n, ceil_div(k, 16) * 16, (const uint8_t *)Ac, ldac, true, Bt, ldbt, C, ldc, stream);
+}
+
+namespace {
+qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
+                          bool a_centred, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream) {
     if (m == 0 || n == 0) return QMM_OK;
     Int8Args g{};
     g.m = m;
@@ -916,6 +968,7 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
     const bool blocked = pl.k_block < k;
     g.p = pl.p;
     centre_consts(pl.p, g.add_h, g.neg_p);
+    if (a_centred) g.add_h = g.neg_p = 0;  // centre4 is then the identity
     g.magic = mod_magic(pl.p);
     g.off = pl.p * ((1u << 31) / pl.p);
     g.magic32 = (uint32_t)((1ull << 32) / pl.p);
@@ -934,5 +987,6 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
     g.kb_tiles = blocked ? (int32_t)(pl.k_block / 64) : 0;
     return run_int8<128, 128, 64, 2, 2>(g, blocked, s);
 }
+}  // namespace
 
 }  // namespace qmm

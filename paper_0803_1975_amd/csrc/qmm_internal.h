@@ -123,6 +123,14 @@ constexpr double kSmallInt8MaxMacs = 4294967296.0;  // 2^32: one launch measured
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
                             uint8_t *C, int64_t ldc, void *stream);
+// INT8 with k not a multiple of 16: A is first centred into Ac (m x ldac int8,
+// ldac = int8_bt_ld(k), zero past k), so the product reads it with aligned 16-byte
+// loads and centres nothing (launch_gemm_int8_centred_a).
+qmm_status launch_centre_rows(const qmm_plan &pl, int64_t m, int64_t k, const uint8_t *A, int64_t lda, int8_t *Ac,
+                              int64_t ldac, void *stream);
+qmm_status launch_gemm_int8_centred_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const int8_t *Ac,
+                                      int64_t ldac, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc,
+                                      void *stream);
 int64_t int8_bt_ld(int64_t k);
 int64_t fp4_ld(int64_t k);
 void fp4_lut(uint32_t p, uint32_t &lo, uint32_t &hi);  // e2m1 codes of the residues 0..7, as bytes
