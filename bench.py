@@ -388,11 +388,14 @@ def run_batched(args, torch, qmm):
         del calls
 
     chosen = results["chosen"]
+    # the value is the median replay (each between its own pair of events); the
+    # roofline's average launch comes from the loop of back-to-back replays
+    med = chosen["median_ms_per_step"]
     ach = io_bytes / (chosen["ms_per_step"] * 1e-3) / 1e9
     out = {
         "metric": "mod-p GMAC/s (m*n*k / time), bit-exact; chosen path vs plain FP64 Q-adic; % MFMA peak",
-        "value": chosen["gmacs"], "unit": "mod-p GMAC/s", "n_gpus": 1, "steps": chosen["steps"],
-        "warmup": args.warmup, "ms_per_step": chosen["ms_per_step"], "median_ms_per_step": chosen["median_ms_per_step"],
+        "value": macs / (med * 1e-3) / 1e9, "unit": "mod-p GMAC/s", "n_gpus": 1, "steps": chosen["steps"],
+        "warmup": args.warmup, "ms_per_step": med, "mean_ms_per_step": chosen["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
         "config": {"workload": "batched: 2000 products, p in {2,3,5,7,11,13,31,101}, m,n,k uniform in [16,512], "
                                "seed 4; one HIP graph replay per step (pack kernel, then one persistent "
@@ -404,7 +407,7 @@ def run_batched(args, torch, qmm):
                      "op": "residue bytes read and written (A, B, C of every product) per replay",
                      "avg_launch_ms": chosen["ms_per_step"]},
         "paths": results,
-        "speedup_vs_plain_fp64_qadic": (chosen["gmacs"] / results["fp64_qadic_per_product"]["gmacs"]
+        "speedup_vs_plain_fp64_qadic": (macs / (med * 1e-3) / 1e9 / results["fp64_qadic_per_product"]["gmacs"]
                                         if "fp64_qadic_per_product" in results else None),
     }
     if not args.no_cpu:

@@ -105,7 +105,7 @@ typedef struct {
     uint32_t regime;   /* qmm_regime */
     uint32_t g;        /* products per rounding assumed by the offset regime (1 or 4) */
     uint32_t tile;     /* kernel tile variant: 0 = chosen from the shape (128 x 128 below
-                          192 tiles of 256 x 256; above, 2 for INT8 and 3 for FP4);
+                          192 tiles of 256 x 256; above, 3);
                           INT8 and FP4: 1 = 128 x 128 output tiles (4 wavefronts),
                           2 = 256 x 256 (8 wavefronts of 128 x 64),
                           3 = 256 x 256 (16 wavefronts of 64 x 64); other values are EINVAL */

@@ -824,12 +824,15 @@ qmm_status run_fp4(const Int8Args &g, hipStream_t s) {
 }  // namespace
 
 int int8_tile_for(int64_t m, int64_t n, bool fp4) {
-    // 256 x 256 tiles once they (nearly) fill the 256 CUs, 128 x 128 below that.
-    // Measured on the same GPU at 4096^2 and 8192^2: int8 products run 3-6 % faster
-    // with 8 wavefronts of 128 x 64 (fewer LDS fragment reads per MFMA), FP4
-    // products 2-6 % faster with 16 wavefronts of 64 x 64.
+    // 256 x 256 tiles once they (nearly) fill the 256 CUs, 128 x 128 below that;
+    // 16 wavefronts of 64 x 64 (four per SIMD, so one wavefront's LDS reads and
+    // barrier waits hide behind the others' MFMAs).  Measured interleaved on one
+    // GPU against 8 wavefronts of 128 x 64 (fewer LDS fragment reads per MFMA):
+    // equal or faster for int8 at 4096^3, 8192^3, 16384^3 and a blocked p = 251
+    // product (up to 13 %), and 2-6 % faster for FP4.
+    (void)fp4;
     if (ceil_div(m, 256) * ceil_div(n, 256) < 192) return 1;
-    return fp4 ? 3 : 2;
+    return 3;
 }
 
 // Packed FP4 rows: ceil(k/2) bytes rounded up to 128, plus one 128-byte line at
