@@ -99,6 +99,7 @@ struct GemmArgs {
     double inv_qd, inv_q, q; // 2^-td, 2^-t, 2^t (exact-regime digit)
     int32_t small_digit;     // t <= 31: digits fit 32 bits
     int32_t lds_epi;         // C and ldc 4-byte aligned and 4 x 512 E bytes fit the staging buffers
+    int32_t c_vec;           // C and ldc 4-byte aligned
 };
 
 // Output tile of this workgroup.  Workgroups are dealt round-robin to the 8 XCDs;
@@ -394,6 +395,71 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
             return;
         }
     }
+    if constexpr (EPI == EPI_REDQ) {
+        const int dq1 = (int)g.dq + 1, dt1 = (int)g.dth + 1;
+        const bool whole = (row0 + BM) * dq1 <= g.m_out && (col0 + BN) * dt1 <= g.n_out;
+        if (g.c_vec && whole && g.dth == 0) {
+            // Left compression, whole tile: output row R (dq+1) + i of word row R holds
+            // residue i of each word, so for each i the four registers of a lane (four
+            // word rows) and the four lanes of a quad (four columns) transpose into a
+            // dword of one output row per lane, as for the Q-adic words.
+            const int j = lane & 3;
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) {
+                    const int64_t wrow = row0 + wm * 64 + mi * 16 + MM::row(lane, j);
+                    uint8_t *dst = g.C + wrow * dq1 * g.ldc + col0 + wn * 64 + ni * 16 + (lane & 15) - j;
+                    for (int32_t i = 0; i < dq1; ++i) {
+                        uint32_t v = 0;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) v |= redq_value(exact_word_bits(acc[mi][ni][r]), i, 0) << (8 * r);
+                        *(uint32_t *)(dst + (int64_t)i * g.ldc) = quad_transpose_bytes(v, j);
+                    }
+                }
+            return;
+        }
+        if (g.c_vec && whole && (dt1 == 2 || dt1 == 4)) {
+            // Right or full compression with 2 or 4 residues per word along a row, whole
+            // tile: residues (i, 0 .. dt1-1) of a word are consecutive bytes of output row
+            // (dq+1) R + i, stored as one 2- or 4-byte store; the lanes of a row write
+            // consecutive runs.
+            auto store_words = [&](auto dt_c, auto one_row_c) __attribute__((always_inline)) {
+                constexpr int DT = decltype(dt_c)::value;
+                constexpr bool ONE_ROW = decltype(one_row_c)::value;  // right compression: dq = 0
+                const uint32_t qm = (uint32_t)g.qmask;
+                const int64_t rs = (int64_t)dq1 * g.ldc;
+                uint8_t *base = g.C + (row0 + wm * 64 + MM::row(lane, 0)) * rs + (col0 + wn * 64 + (lane & 15)) * DT;
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const uint64_t w = exact_word_bits(acc[mi][ni][r]);
+                            uint8_t *dst = base + (int64_t)(mi * 16 + MM::row(lane, r) - MM::row(lane, 0)) * rs + ni * 16 * DT;
+                            for (int32_t i = 0; i < (ONE_ROW ? 1 : dq1); ++i) {
+                                uint32_t v = 0;
+#pragma unroll
+                                for (int jj = 0; jj < DT; ++jj)
+                                    v |= mod_u32_m32(bit_field(w, g.t * (uint32_t)(i + jj * dq1), qm), g.p, g.m32) << (8 * jj);
+                                if constexpr (DT == 2) *(uint16_t *)(dst + (int64_t)i * g.ldc) = (uint16_t)v;
+                                else *(uint32_t *)(dst + (int64_t)i * g.ldc) = v;
+                            }
+                        }
+            };
+            // dt1 >= 2 residues of t bits share a word of at most 53 bits: t <= 26, the
+            // digits fit 32 bits.
+            if (dq1 == 1) {
+                if (dt1 == 2) store_words(std::integral_constant<int, 2>{}, std::true_type{});
+                else store_words(std::integral_constant<int, 4>{}, std::true_type{});
+            } else {
+                if (dt1 == 2) store_words(std::integral_constant<int, 2>{}, std::false_type{});
+                else store_words(std::integral_constant<int, 4>{}, std::false_type{});
+            }
+            return;
+        }
+    }
     if (EPI != EPI_QADIC && g.lds_epi) {
         // Coalesced stores: one 16 x 16 MFMA block of words at a time, each wavefront
         // lays its words' residues out in LDS as the bytes of C they become (a block
@@ -527,7 +593,8 @@ void common_args(GemmArgs &g, const qmm_plan &pl) {
 template <typename W>
 void set_lds_epi(GemmArgs &g, int64_t E) {
     const size_t staging = sizeof(W) * 2 * BM * (KT + APAD);
-    g.lds_epi = ((uintptr_t)g.C % 4 == 0) && (g.ldc % 4 == 0) && (size_t)(4 * 512 * E) <= staging;
+    g.c_vec = ((uintptr_t)g.C % 4 == 0) && (g.ldc % 4 == 0);
+    g.lds_epi = g.c_vec && (size_t)(4 * 512 * E) <= staging;
 }
 
 dim3 grid_for(GemmArgs &g) {

@@ -189,6 +189,45 @@ def test_dword_epilogue_and_byte_fallback(torch, path, p, k):
         assert (out[mask] == 0xAB).all(), f"view at column {c0}: bytes outside C written"
 
 
+# Whole tiles of left compression (one residue per word along a row) store each
+# output row's residues as dwords after a quad transpose; whole tiles of right or full
+# compression with 2 or 4 residues along a row store each word's run of residues as
+# one 2- or 4-byte store.  With m = 300 and n = 520 the first tile (128 x 128 words)
+# is whole for up to 2 residues down and 4 across, the others take the general
+# stores.  Each case names the (dq+1, dth+1) shape it is meant to reach.
+DIRECT_CASES = [(qmm.PATH_FP64_REDQ, 31, 500, 1, 2), (qmm.PATH_FP64_REDQ, 7, 70, 1, 4),
+                (qmm.PATH_FP64_FULL, 7, 50, 2, 2), (qmm.PATH_FP64_LEFT, 31, 500, 2, 1),
+                (qmm.PATH_FP32_REDQ, 3, 256, 1, 2), (qmm.PATH_FP32_LEFT, 3, 256, 2, 1),
+                (qmm.PATH_FP64_REDQ, 3, 256, 1, 4), (qmm.PATH_FP64_FULL, 3, 256, 2, 2)]
+
+
+@pytest.mark.parametrize("path,p,k,dq1,dt1", DIRECT_CASES)
+def test_direct_word_stores(torch, path, p, k, dq1, dt1):
+    m, n = 300, 520
+    pl = qmm.choose_Qd(p, m, n, k, path=path)
+    if path in (qmm.PATH_FP64_REDQ, qmm.PATH_FP32_REDQ):
+        shape = (1, pl.d + 1)
+    elif path in (qmm.PATH_FP64_LEFT, qmm.PATH_FP32_LEFT):
+        shape = (pl.d + 1, 1)
+    else:
+        shape = (pl.d + 1, pl.d2 + 1)
+    assert shape == (dq1, dt1), pl
+    note("direct stores", pl, k)
+    rng = np.random.default_rng(p * 7 + k + 31 * path)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    big = torch.full((m + 2, 528), 0xAB, dtype=torch.uint8, device="cuda")
+    C = big[1:m + 1, 4:4 + n]
+    qmm.gemm_mod_p(dA, dB, p, plan=pl, C=C)
+    out = host(big)
+    np.testing.assert_array_equal(out[1:m + 1, 4:4 + n], want)
+    mask = np.ones_like(out, dtype=bool)
+    mask[1:m + 1, 4:4 + n] = False
+    assert (out[mask] == 0xAB).all(), "bytes outside C written"
+
+
 # --- ReduceAndCompress ------------------------------------------------------------
 def compress_case(torch, p, m, n, k, path=qmm.PATH_FP64_QADIC, flags=0):
     pl = qmm.choose_Qd(p, m, n, k, path=path, flags=flags)
