@@ -81,7 +81,7 @@ Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
         // Bt, then (k not a multiple of 16) A centred into rows of the same length
         L.ld_b = int8_bt_ld(kk);
         L.bytes = align_up((size_t)n * L.ld_b);
-        if (kk % 16 != 0) {
+        if (int8_centres_a(pl, m, n, kk)) {
             L.ld_a = L.ld_b;
             L.off_b = L.bytes;
             L.bytes += align_up((size_t)m * L.ld_a);

@@ -566,6 +566,161 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
             }
 }
 
+// Both operands as centred int8 rows (A as Ac from the centring pass, B as Bt), each
+// row zero padded to its leading dimension (a multiple of 128 bytes, at least k), so
+// every 128-byte K stage of a row is in bounds.  256 x 256 output tile, 16
+// wavefronts of 64 x 64 (2 x 2 blocks of i32_32x32x32_i8, four wavefronts per SIMD).
+// The stages go from HBM straight into LDS (global_load_lds_dwordx4: no staging
+// registers, no LDS store instructions, no VALU), two buffers of 64 KB.
+// LDS layout of an operand's stage: 256 rows of 128 bytes, no padding; 16-byte chunk
+// c of row r sits at position c ^ swz(r), swz(r) = (r % 8) ^ ((r / 8) % 2).  A
+// fragment read (lane l: row base + l % 32, chunk 2 ks + l / 32) then touches 8
+// distinct positions on any 8 consecutive rows and, on 16 consecutive rows, distinct
+// positions among the rows of each parity, so it is free of bank conflicts whether
+// the LDS serves 8 or 16 lanes of a 16-byte read per cycle.  A direct load writes
+// 1 KB (8 rows) per instruction, lane j at bytes 16 j, so lane j reads chunk
+// (j % 8) ^ swz(its row) of row j / 8 of the block.
+// Schedule: stage kt computes from buffer kt % 2.  The fragments of k-step ks + 1
+// are read during k-step ks's MFMAs; the last k-step reads the next stage's first
+// fragments from the other buffer.  One barrier per stage, after the MFMAs of the
+// second-to-last k-step, preceded by a wait for this wavefront's direct loads (the
+// next stage's, issued a stage earlier) and its LDS reads: after it, the next stage
+// is complete in LDS and every read of this stage's buffer is done, so the last
+// k-step issues the loads of stage kt + 2 into this buffer.  The MFMAs after a
+// barrier never wait on LDS: their fragments are already in registers.
+template <bool BLOCKED>
+__global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
+    constexpr int BM = 256, BN = 256, KT = 128, KS = KT / 32, WGN = 4, WT = 64, F = 2;
+    constexpr int STAGE = BM * KT;
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2][2][STAGE];  // [buffer][A, B]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    int tm, tn;
+    tile_coords<BM, BN>(g.m, g.n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+
+    // Direct loads: wavefront w fills blocks q = 2 w + i (i < 2, rows 8 q .. 8 q + 7)
+    // of each operand's stage.  Rows past m (n) read row m - 1 (n - 1); they only
+    // reach outputs that are not stored.
+    const int8_t *a_src[2], *b_src[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int q = 2 * wave + i, r = 8 * q + (lane >> 3);
+        const int chunk = (lane & 7) ^ (r & 7) ^ ((r >> 3) & 1);
+        const int64_t ar = min(row0 + r, g.m - 1), br = min(col0 + r, g.n - 1);
+        a_src[i] = (const int8_t *)g.A + ar * g.lda + 16 * chunk;
+        b_src[i] = g.Bt + br * g.ldbt + 16 * chunk;
+    }
+    auto issue = [&](int kt, int b) {
+        const int64_t k0 = (int64_t)kt * KT;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            __builtin_amdgcn_global_load_lds((const void *)(a_src[i] + k0),
+                                             (__attribute__((address_space(3))) void *)&lds[b][0][(2 * wave + i) * 1024],
+                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(b_src[i] + k0),
+                                             (__attribute__((address_space(3))) void *)&lds[b][1][(2 * wave + i) * 1024],
+                                             16, 0, 0);
+        }
+    };
+
+    ix16 acc[F][F];
+#pragma unroll
+    for (int mi = 0; mi < F; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < F; ++ni) acc[mi][ni] = ix16{};
+
+    // Fragment rows are 32 x + l % 32, so swz(row) = (l % 8) ^ ((l / 8) % 2), and the
+    // chunk 2 ks + l / 32 sits at position (2 ks) ^ (l / 32) ^ swz.
+    const int swz = (lane & 7) ^ ((lane >> 3) & 1) ^ (lane >> 5);
+    const int a_row = (wm * WT + (lane & 31)) * KT, b_row = (wn * WT + (lane & 31)) * KT;
+    ix4 af[2][F], bf[2][F];
+    auto read_frags = [&](int b, int ks, int slot) {
+        const int co = 16 * ((2 * ks) ^ swz);
+#pragma unroll
+        for (int ni = 0; ni < F; ++ni) bf[slot][ni] = *(const ix4 *)&lds[b][1][b_row + ni * 32 * KT + co];
+#pragma unroll
+        for (int mi = 0; mi < F; ++mi) af[slot][mi] = *(const ix4 *)&lds[b][0][a_row + mi * 32 * KT + co];
+    };
+
+    const int ntiles = (int)ceil_div(g.k, KT);
+    issue(0, 0);
+    if (ntiles > 1) issue(1, 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    read_frags(0, 0, 0);
+    for (int kt = 0; kt < ntiles; ++kt) {
+        const int buf = kt & 1;
+        const bool more = kt + 1 < ntiles;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int cur = ks & 1;
+            if (ks == KS - 1 && kt + 2 < ntiles) issue(kt + 2, buf);
+            // on the last stage the other buffer's reads are not used
+            read_frags(ks + 1 < KS ? buf : buf ^ 1, (ks + 1) % KS, cur ^ 1);
+#pragma unroll
+            for (int mi = 0; mi < F; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < F; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int x = 0; x < 2 * F; ++x) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            if (ks == KS - 2 && more) {
+                asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+                __syncthreads();
+            }
+        }
+        if constexpr (BLOCKED) {
+            if ((kt + 1) % g.kb_tiles == 0 && more) {
+#pragma unroll
+                for (int mi = 0; mi < F; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < F; ++ni)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            acc[mi][ni][r] = (int)mod_u32_m32((uint32_t)acc[mi][ni][r] + g.off, g.p, g.magic32);
+            }
+        }
+    }
+
+    if (g.c_vec && row0 + BM <= g.m && col0 + BN <= g.n) {
+        // Whole tile: registers 4q .. 4q+3 of lane l are rows R .. R+3 of column l % 32
+        // (R = 8q + 4 (l / 32)); packed into a dword and transposed across the lane's
+        // quad, they become 4 consecutive bytes of row R + (l % 4), one dword store.
+        const int j = lane & 3;
+        uint8_t *cbase = g.C + (row0 + wm * WT + 4 * (lane >> 5) + j) * g.ldc + col0 + wn * WT + (lane & 31) - j;
+#pragma unroll
+        for (int mi = 0; mi < F; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < F; ++ni)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        w |= mod_u32_m32((uint32_t)acc[mi][ni][4 * q + i] + g.off, g.p, g.magic32) << (8 * i);
+                    w = quad_transpose_bytes(w, j);
+                    *(uint32_t *)(cbase + (int64_t)(mi * 32 + 8 * q) * g.ldc + ni * 32) = w;
+                }
+        return;
+    }
+#pragma unroll
+    for (int mi = 0; mi < F; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < F; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + wm * WT + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t col = col0 + wn * WT + ni * 32 + (lane & 31);
+                if (row < g.m && col < g.n)
+                    g.C[row * g.ldc + col] = (uint8_t)mod_i32_magic((int32_t)acc[mi][ni][r], g.p, g.magic, g.off);
+            }
+}
+
 qmm_status check_launch(const char *what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(QMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -823,16 +978,31 @@ qmm_status run_fp4(const Int8Args &g, hipStream_t s) {
 }
 }  // namespace
 
+// The direct-load tile reads A's rows as they are when every residue is already an
+// int8 (p <= 128), the int32 sums stay in range with A in [0, p-1] instead of
+// centred (a block of k_block terms of at most (p-1) floor(p/2) each, plus the
+// residue carried from the block before), and whole 128-byte stages of every row
+// lie inside the row (k a multiple of 128, rows 16-byte aligned).
+bool int8_raw_a_ok(const qmm_plan &pl, int64_t k) {
+    const int64_t kb = pl.k_block < k ? pl.k_block : k;
+    return pl.p <= 128 && k % 128 == 0 &&
+           (__int128)kb * (pl.p - 1) * (pl.p / 2) + (pl.p - 1) <= (((__int128)1 << 31) - 1);
+}
+
+bool int8_centres_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
+    const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n, false);
+    return k % 16 != 0 || (tile == 4 && !int8_raw_a_ok(pl, k));
+}
+
 int int8_tile_for(int64_t m, int64_t n, bool fp4) {
-    // 256 x 256 tiles once they (nearly) fill the 256 CUs, 128 x 128 below that;
-    // 16 wavefronts of 64 x 64 (four per SIMD, so one wavefront's LDS reads and
-    // barrier waits hide behind the others' MFMAs).  Measured interleaved on one
-    // GPU against 8 wavefronts of 128 x 64 (fewer LDS fragment reads per MFMA):
-    // equal or faster for int8 at 4096^3, 8192^3, 16384^3 and a blocked p = 251
-    // product (up to 13 %), and 2-6 % faster for FP4.
-    (void)fp4;
+    // 256 x 256 tiles once they (nearly) fill the 256 CUs, 128 x 128 below that.
+    // INT8: the direct-load tile (16 wavefronts of 64 x 64, both operands straight
+    // from HBM into LDS, one barrier per K stage); the product kernels fall back to
+    // tile 3 where A's rows cannot be read whole.  FP4: 16 wavefronts of 64 x 64
+    // with register-staged loads (measured interleaved on one GPU against 8
+    // wavefronts of 128 x 64: 2-6 % faster).
     if (ceil_div(m, 256) * ceil_div(n, 256) < 192) return 1;
-    return 3;
+    return fp4 ? 3 : 4;
 }
 
 // Packed FP4 rows: ceil(k/2) bytes rounded up to 128, plus one 128-byte line at
@@ -978,7 +1148,22 @@ qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     g.c_vec = ((uintptr_t)C % 4 == 0) && (ldc % 4 == 0);
     g.a_vec = ((uintptr_t)A % 16 == 0) && (lda % 16 == 0);
     hipStream_t s = (hipStream_t)stream;
-    const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n, false);
+    // the direct-load tile reads A as int8 rows: centred (Ac, padded to whole
+    // stages) or, where int8_raw_a_ok, the residues themselves; otherwise tile 3
+    // runs instead
+    const bool direct_a = a_centred ? lda % 128 == 0 : (int8_raw_a_ok(pl, k) && lda % 16 == 0);
+    const bool direct = direct_a && ldbt % 128 == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)Bt % 16 == 0;
+    int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n, false);
+    if (tile == 4 && !direct) tile = 3;  // same 256 x 256 tile, register-staged loads
+    if (tile == 4) {
+        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
+        const dim3 grid((unsigned)(ceil_div(m, 256) * ceil_div(n, 256)));
+        if (blocked)
+            gemm_int8_direct_kernel<true><<<grid, 1024, 0, s>>>(g);
+        else
+            gemm_int8_direct_kernel<false><<<grid, 1024, 0, s>>>(g);
+        return check_launch("gemm_int8_direct");
+    }
     if (tile == 2) {
         g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
         return run_int8<256, 256, 128, 2, 4>(g, blocked, s);

@@ -144,5 +144,8 @@ qmm_status launch_pack_fp4_both(const qmm_plan &pl, int64_t m, int64_t n, int64_
 qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A4, int64_t lda4,
                            const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc, void *stream);
 int int8_tile_for(int64_t m, int64_t n, bool fp4);
+// Whether qmm_gemm_mod_p's INT8 product centres A into aligned rows first (k not a
+// multiple of 16, or the direct-load tile 4, which reads both operands as rows).
+bool int8_centres_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k);
 
 }  // namespace qmm

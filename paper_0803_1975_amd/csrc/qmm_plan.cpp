@@ -389,7 +389,7 @@ extern "C" qmm_status qmm_validate_plan(const qmm_plan *pl, int64_t m, int64_t n
         const int64_t kb = pl->k_block;
         if (kb < 1) return fail(QMM_EBOUND, "k_block < 1");
         if (kb < kk && kb % kInt8KT) return fail(QMM_EBOUND, "INT8 k_block must be a multiple of 128");
-        if (pl->tile > 3) return fail(QMM_EINVAL, "INT8 tile must be 0 (auto) or 1..3");
+        if (pl->tile > 4) return fail(QMM_EINVAL, "INT8 tile must be 0 (auto) or 1..4");
         if ((__int128)kb * h * h + (pl->p - 1) > (((__int128)1 << 31) - 1))
             return fail(QMM_EBOUND, "INT8 k_block overflows int32");
         return QMM_OK;

@@ -82,7 +82,7 @@ def test_plans_that_break_the_bounds_are_refused():
     big = qmm.Plan.from_buffer_copy(i8)
     big.k_block = 200000
     assert qmm.validate_plan(big, 4, 4, 200000) == qmm.EBOUND
-    for tile, want in ((0, qmm.OK), (3, qmm.OK), (4, qmm.EINVAL)):
+    for tile, want in ((0, qmm.OK), (3, qmm.OK), (4, qmm.OK), (5, qmm.EINVAL)):
         tiled = qmm.Plan.from_buffer_copy(i8)
         tiled.tile = tile
         assert qmm.validate_plan(tiled, 4, 4, 200000) == want, tile

@@ -32,6 +32,7 @@ COMMON = [
     (qmm.PATH_FP64_REDQ, 0, 0), (qmm.PATH_FP64_LEFT, 0, 0), (qmm.PATH_FP64_FULL, 0, 0),
     (qmm.PATH_FP32_QADIC, 0, 0),
     (qmm.PATH_INT8, 0, 0), (qmm.PATH_INT8, 0, 1), (qmm.PATH_INT8, 0, 2), (qmm.PATH_INT8, 0, 3),
+    (qmm.PATH_INT8, 0, 4),
     (qmm.PATH_AUTO, 0, 0),
 ]
 SMALL_P = [  # p <= 8 (FP4 codes) and short enough k for every FP32 form

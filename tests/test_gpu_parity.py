@@ -249,7 +249,7 @@ def test_int8_blocked_accumulation(torch):
     want = ref.modmul(A, B, p)
     np.testing.assert_array_equal(got, want)
     dA, dB = dev(torch, A), dev(torch, B)
-    for tile in (1, 2, 3):
+    for tile in (1, 2, 3, 4):
         plan = qmm.choose_Qd(p, 20, 9, k, path=qmm.PATH_INT8)
         plan.tile = tile
         np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=plan)), want, err_msg=f"tile {tile}")
@@ -324,8 +324,7 @@ def test_strided_operands(torch):
         assert int(Cbig[:, :10].max()) == 0 and int(Cbig[:, 170:].max()) == 0
 
 
-@pytest.mark.parametrize("path", (qmm.PATH_INT8, qmm.PATH_FP4))
-@pytest.mark.parametrize("tile", (1, 2, 3))
+@pytest.mark.parametrize("path,tile", [(qmm.PATH_INT8, t) for t in (1, 2, 3, 4)] + [(qmm.PATH_FP4, t) for t in (1, 2, 3)])
 @pytest.mark.parametrize("col0", (4, 3))
 def test_output_views_for_every_tile(torch, path, tile, col0):
     # C is a view into a larger zeroed buffer: at a 4-byte aligned column offset with
@@ -432,7 +431,7 @@ def test_int8_stages_match_one_call_and_oracle(torch, p, m, n, k):
     plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
     one = qmm.gemm_mod_p(dA, dB, p, plan=plan)
     Bt = qmm.pack_centred_cols(plan, dB)
-    for tile in (1, 2, 3):
+    for tile in (1, 2, 3, 4):
         plan.tile = tile
         assert torch.equal(qmm.gemm_centred(plan, dA, Bt, n), one)
     if m * n * k <= 2 ** 28:
@@ -589,6 +588,35 @@ def test_small_int8_one_launch_matches_staged_calls_and_oracle(torch, p, m, n, k
     np.testing.assert_array_equal(host(staged), want)
 
 
+# The direct-load INT8 tile (4) reads A's rows whole, as int8: the residues
+# themselves when p <= 128, k is a multiple of 128 and the int32 sums stay in range
+# with A uncentred, A's centred copy otherwise (qmm_gemm_mod_p), and tile 3's kernel
+# where neither is possible (qmm_gemm_centred on rows it cannot read whole).  Output
+# 300 x 520: two rows of 256 x 256 tiles, both ragged.
+@pytest.mark.parametrize("p,k,k_block", [(101, 1024, 0), (101, 1024, 256), (127, 640, 0), (2, 384, 0),
+                                         (251, 1024, 0), (251, 1024, 384), (101, 1000, 0), (13, 200, 0)])
+def test_int8_direct_tile_on_raw_and_centred_rows(torch, p, k, k_block):
+    m, n = 300, 520
+    rng = np.random.default_rng(p + k + k_block)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    want = ref.modmul(A, B, p)
+    dA, dB = dev(torch, A), dev(torch, B)
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    if k_block:
+        plan.k_block = k_block
+    plan.tile = 4
+    note("int8 direct", plan, k)
+    np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dB, p, plan=plan)), want)
+    Bt = qmm.pack_centred_cols(plan, dB)
+    np.testing.assert_array_equal(host(qmm.gemm_centred(plan, dA, Bt, n)), want)
+    # A as a view whose rows start 3 bytes in: read whole only after centring
+    big = torch.zeros((m, k + 8), dtype=torch.uint8, device="cuda")
+    big[:, 3:3 + k] = dA
+    np.testing.assert_array_equal(host(qmm.gemm_mod_p(big[:, 3:3 + k], dB, p, plan=plan)), want)
+    np.testing.assert_array_equal(host(qmm.gemm_centred(plan, big[:, 3:3 + k], Bt, n)), want)
+
+
 @pytest.mark.parametrize("k", (1001, 4097, 2049))
 def test_int8_unaligned_rows_on_every_tile(torch, k):
     # k odd: rows of A start at every byte offset within a dword, so the product
@@ -603,7 +631,7 @@ def test_int8_unaligned_rows_on_every_tile(torch, k):
     dA, dB = dev(torch, A), dev(torch, B)
     plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
     Bt = qmm.pack_centred_cols(plan, dB)
-    for tile in (1, 2, 3):
+    for tile in (1, 2, 3, 4):
         for k_block in ((plan.k_block, 512) if k == 4097 else (plan.k_block,)):
             plan.tile, plan.k_block = tile, k_block
             note("int8 unaligned", k, "tile", tile, "k_block", k_block)
