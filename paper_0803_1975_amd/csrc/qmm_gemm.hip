@@ -238,55 +238,125 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
                     res[mi][ni][h] = mod_u32_m32(v & 0xffffu, g.p, g.m32) | mod_u32_m32(v >> 16, g.p, g.m32) << 16;
                 }
     };
-    // The four k-steps of one LDS stage.
-    auto mma_stage = [&](int buf) {
-#pragma unroll
-        for (int ks = 0; ks < KT / 4; ++ks) {
-            W af[4], bf[4];
-#pragma unroll
-            for (int mi = 0; mi < 4; ++mi) af[mi] = sA[buf][wm * 64 + mi * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
-#pragma unroll
-            for (int ni = 0; ni < 4; ++ni) bf[ni] = sB[buf][ks * 4 + (lane >> 4)][wn * 64 + ni * 16 + (lane & 15)];
-#pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < 4; ++ni) {
-                    acc[mi][ni] = MM::mma(af[mi], bf[ni], acc[mi][ni]);
-                }
-        }
-    };
+    // Doubles take the schedule below; floats, whose MFMAs take half as long, keep
+    // the plain double-buffered one (measured: the one-barrier schedule raises the
+    // FP64 products 1.5-2 points of peak and costs the FP32 ones registers and a
+    // wavefront per SIMD).
+    if constexpr (sizeof(W) == 8) {
+        // One barrier per K stage, and none between a barrier and the MFMAs after it:
+        // stage kt computes from LDS buffer kt % 2; the registers loaded during stage
+        // kt - 1 (stage kt + 1's words) are stored into the other buffer after the first
+        // k-step, and stage kt + 2's loads are issued into the freed registers.  The
+        // barrier follows the second-to-last k-step; the last k-step's MFMAs run while
+        // the next stage's first fragments are read.  So every read of a buffer precedes
+        // (in each wavefront) the barrier before its next overwrite, and every store
+        // precedes the barrier before its first read.
+        constexpr int KS = KT / 4;
+        W af[2][4], bf[2][4];
+        auto read_frags = [&](int b, int ks, int slot) {
+    #pragma unroll
+            for (int mi = 0; mi < 4; ++mi) af[slot][mi] = sA[b][wm * 64 + mi * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+    #pragma unroll
+            for (int ni = 0; ni < 4; ++ni) bf[slot][ni] = sB[b][ks * 4 + (lane >> 4)][wn * 64 + ni * 16 + (lane & 15)];
+        };
 
-    const int ntiles = (int)ceil_div(g.kdim, KT);
-    load_stage(0);
-    store_stage(0);
-    __syncthreads();
-    int blk_left = g.kb_tiles;      // stages left in the current block (blocked plans)
-    int fold_left = g.fold_blocks;  // blocks before the next fold (BLK_SUM16)
-    for (int kt = 0; kt < ntiles; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < ntiles) load_stage(kt + 1);
-        mma_stage(buf);
-        if constexpr (BLOCKED) {
-            if (--blk_left == 0 && kt + 1 < ntiles) {
-                blk_left = g.kb_tiles;
-                reduce_block();
-#pragma unroll
+        const int ntiles = (int)ceil_div(g.kdim, KT);
+        load_stage(0);
+        store_stage(0);
+        if (ntiles > 1) load_stage(1);
+        __syncthreads();
+        read_frags(0, 0, 0);
+        int blk_left = g.kb_tiles;      // stages left in the current block (blocked plans)
+        int fold_left = g.fold_blocks;  // blocks before the next fold (BLK_SUM16)
+        for (int kt = 0; kt < ntiles; ++kt) {
+            const int buf = kt & 1;
+            const bool more = kt + 1 < ntiles;
+    #pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int cur = ks & 1;
+                // the next k-step's fragments (on the last k-step: the next stage's first,
+                // read unconditionally; on the last stage they are not used)
+                read_frags(ks + 1 < KS ? buf : buf ^ 1, (ks + 1) % KS, cur ^ 1);
+    #pragma unroll
                 for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = acc_t{start, start, start, start};
-                if constexpr (BLK == BLK_SUM16) {
-                    if (--fold_left == 0) {
-                        fold_left = g.fold_blocks;
-                        fold();
+    #pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = MM::mma(af[cur][mi], bf[cur][ni], acc[mi][ni]);
+                if (ks == 0 && more) {
+                    store_stage(buf ^ 1);
+                    if (kt + 2 < ntiles) load_stage(kt + 2);
+                }
+                if (ks == KS - 2 && more) __syncthreads();
+            }
+            if constexpr (BLOCKED) {
+                if (--blk_left == 0 && more) {
+                    blk_left = g.kb_tiles;
+                    reduce_block();
+    #pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+    #pragma unroll
+                        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = acc_t{start, start, start, start};
+                    if constexpr (BLK == BLK_SUM16) {
+                        if (--fold_left == 0) {
+                            fold_left = g.fold_blocks;
+                            fold();
+                        }
                     }
                 }
             }
         }
-        if (kt + 1 < ntiles) {
-            store_stage(buf ^ 1);
-            __syncthreads();
+    } else {
+        // The four k-steps of one LDS stage.
+        auto mma_stage = [&](int buf) {
+    #pragma unroll
+            for (int ks = 0; ks < KT / 4; ++ks) {
+                W af[4], bf[4];
+    #pragma unroll
+                for (int mi = 0; mi < 4; ++mi) af[mi] = sA[buf][wm * 64 + mi * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+    #pragma unroll
+                for (int ni = 0; ni < 4; ++ni) bf[ni] = sB[buf][ks * 4 + (lane >> 4)][wn * 64 + ni * 16 + (lane & 15)];
+    #pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+    #pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) {
+                        acc[mi][ni] = MM::mma(af[mi], bf[ni], acc[mi][ni]);
+                    }
+            }
+        };
+
+        const int ntiles = (int)ceil_div(g.kdim, KT);
+        load_stage(0);
+        store_stage(0);
+        __syncthreads();
+        int blk_left = g.kb_tiles;      // stages left in the current block (blocked plans)
+        int fold_left = g.fold_blocks;  // blocks before the next fold (BLK_SUM16)
+        for (int kt = 0; kt < ntiles; ++kt) {
+            const int buf = kt & 1;
+            if (kt + 1 < ntiles) load_stage(kt + 1);
+            mma_stage(buf);
+            if constexpr (BLOCKED) {
+                if (--blk_left == 0 && kt + 1 < ntiles) {
+                    blk_left = g.kb_tiles;
+                    reduce_block();
+    #pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+    #pragma unroll
+                        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = acc_t{start, start, start, start};
+                    if constexpr (BLK == BLK_SUM16) {
+                        if (--fold_left == 0) {
+                            fold_left = g.fold_blocks;
+                            fold();
+                        }
+                    }
+                }
+            }
+            if (kt + 1 < ntiles) {
+                store_stage(buf ^ 1);
+                __syncthreads();
+            }
         }
+
     }
+    __syncthreads();  // the epilogue may reuse the staging buffers
 
     // Epilogue.
     // Digit d of the accumulated word at (mi, ni, r), reduced mod p.
