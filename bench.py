@@ -307,12 +307,15 @@ def run_batched(args, torch, qmm):
     macs = float(sum(m * n * k for _, m, n, k in shapes))
     io_bytes = float(sum(m * k + k * n + m * n for _, m, n, k in shapes))
     log(f"[bench] batched: {len(shapes)} products, {macs:.3e} MAC, {io_bytes / 1e6:.1f} MB of residues")
-    try:
-        costs = qmm.batched_tune()
-        log(f"[bench] autotuner costs {['%.3f' % c for c in costs]}")
-    except qmm.QmmError as e:
-        costs = None
-        log(f"[bench] autotuner calibration failed ({e}); keeping the analytic prior")
+    if args.batch_flags is None:
+        try:
+            costs = qmm.batched_tune()
+            log(f"[bench] autotuner costs {['%.3f' % c for c in costs]}")
+        except qmm.QmmError as e:
+            costs = None
+            log(f"[bench] autotuner calibration failed ({e}); keeping the analytic prior")
+    else:
+        log(f"[bench] batch flags fixed to {args.batch_flags:#x}: no calibration, no measuring stage")
 
     def time_fn(fn, steps, warmup):
         for _ in range(warmup):
@@ -340,7 +343,7 @@ def run_batched(args, torch, qmm):
     results = {}
     ref_out = None
     # chosen: the autotuner's cost model, then its measuring stage on this batch
-    batched_variants = [("chosen", qmm.BATCH_MEASURE)]
+    batched_variants = [("chosen", qmm.BATCH_MEASURE if args.batch_flags is None else args.batch_flags)]
     if args.paths == "all":
         batched_variants += [("raw_int8_no_pack", qmm.BATCH_RAW), ("fp64_qadic_batched", qmm.BATCH_FORCE_FP64)]
     for name, flags in batched_variants:
@@ -633,6 +636,9 @@ def main():
     ap.add_argument("--paths", default="all", help="'all', or 'headline' (time only the headline path)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-flags", type=lambda x: int(x, 0), default=None,
+                    help="batched workload: build the timed batch with these qmm_batched_create flags instead "
+                         "of calibrating and measuring (for counter runs on one fixed kernel)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes three times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
