@@ -104,11 +104,18 @@ typedef struct {
     uint32_t path;     /* qmm_path; never QMM_PATH_AUTO in a returned plan */
     uint32_t regime;   /* qmm_regime */
     uint32_t g;        /* products per rounding assumed by the offset regime (1 or 4) */
-    uint32_t tile;     /* kernel tile variant: 0 = chosen from the shape (128 x 128 below
-                          192 tiles of 256 x 256; above, 3);
+    uint32_t tile;     /* kernel tile variant: 0 = chosen from the shape (1 below 192 tiles
+                          of 256 x 256; above, 4 for INT8 and 3 for FP4);
                           INT8 and FP4: 1 = 128 x 128 output tiles (4 wavefronts),
                           2 = 256 x 256 (8 wavefronts of 128 x 64),
-                          3 = 256 x 256 (16 wavefronts of 64 x 64); other values are EINVAL */
+                          3 = 256 x 256 (16 wavefronts of 64 x 64);
+                          INT8 only: 4 = 256 x 256, 16 wavefronts of 64 x 64 with both
+                          operands loaded straight into on-chip memory, which reads A's
+                          rows whole as int8 (residues of p <= 128 when k is a multiple
+                          of 128 and the uncentred sums fit int32, else a centred copy
+                          qmm_gemm_mod_p makes); where it cannot (qmm_gemm_centred on
+                          rows not 16-byte aligned) tile 3 runs instead;
+                          other values are EINVAL */
     uint32_t d2;       /* FULL paths: degree in Theta = Q^(d+1), d2+1 columns of B per word
                           (d+1 rows of A per word); 0 on every other path */
 } qmm_plan;
@@ -179,8 +186,9 @@ qmm_status qmm_redq(const qmm_plan *plan, int64_t m, int64_t n, const void *CC, 
                     uint8_t *C, int64_t ldc, void *stream);
 
 /* Device workspace that qmm_gemm_mod_p needs for this plan and shape (INT8:
- * centred B transposed, plus, when k is not a multiple of 16, A centred into
- * aligned rows). */
+ * centred B transposed, plus A centred into aligned rows when k is not a multiple
+ * of 16, or when the product runs on tile 4 and A's residues cannot be read as
+ * they are: p > 128, k not a multiple of 128, or uncentred sums past int32). */
 qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
                                    size_t *bytes);
 
