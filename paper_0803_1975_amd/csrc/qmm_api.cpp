@@ -33,6 +33,7 @@ struct Layout {
     size_t bytes = 0;
     size_t off_b = 0;  // second buffer offset
     int64_t ld_a = 0, ld_b = 0;
+    size_t off_tail = 0, tail = 0;  // INT8 / FP4: partial outputs of a split-K strip
 };
 
 // Small unblocked FP64 Q-adic products run in one launch that packs in LDS.
@@ -90,6 +91,13 @@ Layout workspace_layout(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
         L.ld_a = L.ld_b = fp4_ld(kk);
         L.off_b = align_up((size_t)m * L.ld_a);
         L.bytes = L.off_b + align_up((size_t)n * L.ld_b);
+    }
+    if (pl.path == QMM_PATH_INT8 || pl.path == QMM_PATH_FP4) {
+        L.tail = lowp_tail_bytes(pl, m, n, k);
+        if (L.tail > 0) {
+            L.off_tail = L.bytes;
+            L.bytes += align_up(L.tail);
+        }
     }
     return L;
 }
@@ -260,14 +268,15 @@ extern "C" qmm_status qmm_gemm_mod_p(const qmm_plan *plan, int64_t m, int64_t n,
             // rows of A that cannot be whole 16-byte loads: centre them into aligned rows first
             int8_t *Ac = (int8_t *)(w + L.off_b);
             if ((st = launch_centre_rows(pl, m, k, A, lda, Ac, L.ld_a, stream)) != QMM_OK) return st;
-            return launch_gemm_int8_centred_a(pl, m, n, k, Ac, L.ld_a, Bt, L.ld_b, C, ldc, stream);
+            return launch_gemm_int8_centred_a(pl, m, n, k, Ac, L.ld_a, Bt, L.ld_b, C, ldc, stream, w + L.off_tail,
+                                              L.tail);
         }
-        return launch_gemm_int8(pl, m, n, k, A, lda, Bt, L.ld_b, C, ldc, stream);
+        return launch_gemm_int8(pl, m, n, k, A, lda, Bt, L.ld_b, C, ldc, stream, w + L.off_tail, L.tail);
     }
     if (pl.path == QMM_PATH_FP4) {
         uint8_t *A4 = w, *Bt4 = w + L.off_b;
         if ((st = launch_pack_fp4_both(pl, m, n, k, A, lda, B, ldb, A4, L.ld_a, Bt4, L.ld_b, stream)) != QMM_OK) return st;
-        return launch_gemm_fp4(pl, m, n, k, A4, L.ld_a, Bt4, L.ld_b, C, ldc, stream);
+        return launch_gemm_fp4(pl, m, n, k, A4, L.ld_a, Bt4, L.ld_b, C, ldc, stream, w + L.off_tail, L.tail);
     }
     return fail(QMM_EINVAL, "unknown path");
 }

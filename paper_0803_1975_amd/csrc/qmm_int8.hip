@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "qmm_device.h"
@@ -337,6 +338,8 @@ struct Int8Args {
     uint32_t magic32;  // floor(2^32 / p)
     bool a_vec;        // A rows 16-byte aligned: vector loads allowed
     bool c_vec;        // C and ldc 4-byte aligned: whole tiles are stored as dwords
+    int64_t kc;           // split K (gridDim.y > 1): bytes of k per chunk
+    int64_t part_stride;  // split K: bytes between the chunks' partial outputs
 };
 
 // BM x BN output tile, WGM x WGN wavefronts, K stage of KT bytes.  Each wavefront
@@ -369,6 +372,15 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
     __shared__ __attribute__((aligned(16))) uint8_t sA[2][BM * PITCH];
     __shared__ __attribute__((aligned(16))) uint8_t sB[2][BN * PITCH];
 
+    if (gridDim.y > 1) {
+        // one K chunk of a split product: its slice of A's and Bt's rows, and its own
+        // partial output (the residue of the chunk's sum), combined afterwards
+        const int64_t k0 = (int64_t)blockIdx.y * g.kc;
+        g.A += k0;
+        g.Bt += k0;
+        g.C += (int64_t)blockIdx.y * g.part_stride;
+        g.k = min(g.kc, g.k - k0);
+    }
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     int tm, tn;
@@ -950,8 +962,8 @@ qmm_status launch_centre_transpose(const qmm_plan &pl, int64_t k, int64_t n, con
 
 namespace {
 template <int BM, int BN, int KT, int WGM, int WGN>
-qmm_status run_int8(const Int8Args &g, bool blocked, hipStream_t s) {
-    const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)));
+qmm_status run_int8(const Int8Args &g, bool blocked, hipStream_t s, unsigned chunks = 1) {
+    const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)), chunks);
     const bool avec = g.a_vec && g.k % 16 == 0;
     if (blocked && avec)
         gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, true, false><<<grid, 64 * WGM * WGN, 0, s>>>(g);
@@ -971,8 +983,8 @@ qmm_status run_int8(const Int8Args &g, bool blocked, hipStream_t s) {
 // it is scheduled by the compiler into more registers than four wavefronts per
 // SIMD allow, and spills).
 template <int BM, int BN, int KT, int WGM, int WGN>
-qmm_status run_fp4(const Int8Args &g, hipStream_t s) {
-    const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)));
+qmm_status run_fp4(const Int8Args &g, hipStream_t s, unsigned chunks = 1) {
+    const dim3 grid((unsigned)(ceil_div(g.m, BM) * ceil_div(g.n, BN)), chunks);
     gemm_int8_kernel<BM, BN, KT, WGM, WGN, true, true, true><<<grid, 64 * WGM * WGN, 0, s>>>(g);
     return check_launch("gemm_fp4");
 }
@@ -1069,8 +1081,115 @@ qmm_status launch_pack_fp4_both(const qmm_plan &pl, int64_t m, int64_t n, int64_
     return check_launch("pack_fp4_both");
 }
 
+namespace {
+// Compute units of the current device, looked up once per device.
+int device_cus() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+        cache[dev] = c;
+    }
+    return cache[dev];
+}
+
+// Tile quantisation: when m or n is a little past a multiple of 256 (4097^2: 17 x 17
+// = 289 tiles of 256 x 256 on 256 CUs), the ragged last tile-row and tile-column make
+// a second round of tiles that takes as long as the first.  Then the block
+// [0, m0) x [0, n0) of whole 256 x 256 tiles runs on them in fewer rounds, and the two
+// edge strips -- rows [m0, m) of all of C, and columns [n0, n) of rows [0, m0) --
+// each run as a split-K product on 128 x 128 tiles: k cut into chunks of kc bytes
+// (multiples of 128), chunks chosen so that tiles times chunks make about one round
+// over the CUs (four chunk-tiles per CU measured no faster); each chunk's product
+// mod p goes to a partial output in the workspace, and a small kernel sums the
+// chunks mod p into C (a strip of one chunk is written to C directly).  kbytes:
+// bytes of k per row (INT8: k; FP4: packed).
+struct Strip {
+    int64_t rows = 0, cols = 0;
+    int64_t chunks = 1, kc = 0;
+    size_t off = 0;  // partial outputs in the workspace (chunks > 1)
+    size_t bytes() const { return chunks > 1 ? (size_t)chunks * (size_t)rows * (size_t)cols : 0; }
+};
+struct TailPlan {
+    bool split = false;
+    int64_t m0 = 0, n0 = 0;
+    Strip bottom, right;
+    size_t bytes = 0;
+};
+
+Strip strip_plan(int64_t rows, int64_t cols, int64_t kbytes, int64_t cus) {
+    Strip st;
+    st.rows = rows;
+    st.cols = cols;
+    if (rows == 0 || cols == 0) return st;
+    const int64_t tiles = ceil_div(rows, 128) * ceil_div(cols, 128);
+    const int64_t stages = ceil_div(kbytes, 128);
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(cus / tiles, stages));
+    st.kc = ceil_div(stages, want) * 128;
+    st.chunks = ceil_div(kbytes, st.kc);
+    return st;
+}
+
+TailPlan tail_plan(int64_t m, int64_t n, int64_t kbytes, int64_t cus) {
+    TailPlan t;
+    const int64_t tiles = ceil_div(m, 256) * ceil_div(n, 256);
+    const int64_t inner = (m / 256) * (n / 256);
+    if (inner == 0 || ceil_div(inner, cus) >= ceil_div(tiles, cus)) return t;
+    t.split = true;
+    t.m0 = m / 256 * 256;
+    t.n0 = n / 256 * 256;
+    t.bottom = strip_plan(m - t.m0, n, kbytes, cus);
+    t.right = strip_plan(t.m0, n - t.n0, kbytes, cus);
+    t.bottom.off = 0;
+    t.right.off = (t.bottom.bytes() + 255) / 256 * 256;
+    t.bytes = t.right.off + t.right.bytes();
+    return t;
+}
+
+// C = (sum of the chunks' partial residues) mod p, one output per thread.
+__global__ __launch_bounds__(256) void tail_combine_kernel(const uint8_t *__restrict__ part, int64_t stride,
+                                                           int32_t chunks, int64_t rows, int64_t n,
+                                                           uint8_t *__restrict__ C, int64_t ldc, uint32_t p,
+                                                           uint32_t magic32) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= rows * n) return;
+    uint32_t sum = 0;
+    for (int32_t c = 0; c < chunks; ++c) sum += part[c * stride + idx];
+    const int64_t r = idx / n;
+    C[r * ldc + (idx - r * n)] = (uint8_t)mod_u32_m32(sum, p, magic32);
+}
+
+// One edge strip: args `a` already describe the strip's A rows, Bt rows and C; run
+// it whole (one chunk) or as chunks into `part` and combine.
+template <typename Run>
+qmm_status run_strip(const Strip &st, Int8Args a, uint8_t *part, uint32_t p, hipStream_t s, Run run) {
+    if (st.rows == 0 || st.cols == 0) return QMM_OK;
+    a.m = st.rows;
+    a.n = st.cols;
+    if (st.chunks == 1) return run(a, 1u);
+    uint8_t *C = a.C;
+    const int64_t ldc = a.ldc;
+    a.C = part;
+    a.ldc = st.cols;
+    a.c_vec = st.cols % 4 == 0 && (uintptr_t)part % 4 == 0;
+    a.kc = st.kc;
+    a.part_stride = st.rows * st.cols;
+    qmm_status r = run(a, (unsigned)st.chunks);
+    if (r != QMM_OK) return r;
+    const int64_t blocks = ceil_div(st.rows * st.cols, 256);
+    tail_combine_kernel<<<(unsigned)blocks, 256, 0, s>>>(part, st.rows * st.cols, (int32_t)st.chunks, st.rows, st.cols,
+                                                         C, ldc, p, (uint32_t)((1ull << 32) / p));
+    return check_launch("tail_combine");
+}
+}  // namespace
+
 qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A4, int64_t lda4,
-                           const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc, void *stream) {
+                           const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc, void *stream,
+                           uint8_t *tail_ws, size_t tail_bytes) {
     if (m == 0 || n == 0) return QMM_OK;
     Int8Args g{};
     g.m = m;
@@ -1093,26 +1212,46 @@ qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, 
     const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n, true);
     // one K stage of KT packed bytes holds 2 KT values of k
     const int32_t never = INT32_MAX;
-    if (tile == 2) {
-        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 256) : never;
-        return run_fp4<256, 256, 128, 2, 4>(g, s);
-    }
-    if (tile == 3) {
-        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 256) : never;
-        return run_fp4<256, 256, 128, 4, 4>(g, s);
-    }
-    g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : never;
-    return run_fp4<128, 128, 64, 2, 2>(g, s);
+    auto small_tiles = [&](Int8Args a) {
+        a.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : never;
+        return run_fp4<128, 128, 64, 2, 2>(a, s);
+    };
+    auto big_tiles = [&](Int8Args a) {
+        a.kb_tiles = blocked ? (int32_t)(pl.k_block / 256) : never;
+        return tile == 2 ? run_fp4<256, 256, 128, 2, 4>(a, s) : run_fp4<256, 256, 128, 4, 4>(a, s);
+    };
+    if (tile != 2 && tile != 3) return small_tiles(g);
+    const TailPlan t = tail_plan(m, n, g.k, device_cus());
+    if (!t.split || tail_ws == nullptr || tail_bytes < t.bytes) return big_tiles(g);
+    // ragged edges past whole rounds of 256 x 256 tiles: split-K strips
+    Int8Args head = g;
+    head.m = t.m0;
+    head.n = t.n0;
+    qmm_status st = big_tiles(head);
+    auto run = [&](Int8Args a, unsigned chunks) {
+        a.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : never;
+        return run_fp4<128, 128, 64, 2, 2>(a, s, chunks);
+    };
+    Int8Args bottom = g, right = g;
+    bottom.A = A4 + t.m0 * lda4;
+    bottom.C = C + t.m0 * ldc;
+    right.Bt = (const int8_t *)(Bt4 + t.n0 * ldbt4);
+    right.C = C + t.n0;
+    if (st == QMM_OK) st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
+    if (st == QMM_OK) st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
+    return st;
 }
 
 namespace {
 qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
-                          bool a_centred, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream);
+                          bool a_centred, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream,
+                          uint8_t *tail_ws, size_t tail_bytes);
 }  // namespace
 
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
-                            const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream) {
-    return gemm_int8_impl(pl, m, n, k, A, lda, false, Bt, ldbt, C, ldc, stream);
+                            const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream,
+                            uint8_t *tail_ws, size_t tail_bytes) {
+    return gemm_int8_impl(pl, m, n, k, A, lda, false, Bt, ldbt, C, ldc, stream, tail_ws, tail_bytes);
 }
 
 // Ac holds centred rows zero padded to ldac (a multiple of 128, at least k), so the
@@ -1120,13 +1259,25 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
 // centring constants zero, centre4 is the identity.
 qmm_status launch_gemm_int8_centred_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const int8_t *Ac,
                                       int64_t ldac, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc,
-                                      void *stream) {
-    return gemm_int8_impl(pl, m, n, ceil_div(k, 16) * 16, (const uint8_t *)Ac, ldac, true, Bt, ldbt, C, ldc, stream);
+                                      void *stream, uint8_t *tail_ws, size_t tail_bytes) {
+    return gemm_int8_impl(pl, m, n, ceil_div(k, 16) * 16, (const uint8_t *)Ac, ldac, true, Bt, ldbt, C, ldc, stream,
+                          tail_ws, tail_bytes);
+}
+
+size_t lowp_tail_bytes(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
+    if (m == 0 || n == 0 || k == 0) return 0;
+    const bool fp4 = pl.path == QMM_PATH_FP4;
+    const int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n, fp4);
+    if (tile < 2 || tile > (fp4 ? 3 : 4)) return 0;
+    // the product's k in bytes per row: INT8 rounds up to 16 when A is centred first
+    const int64_t kbytes = fp4 ? ceil_div(ceil_div(k, 2), 16) * 16 : (k % 16 ? ceil_div(k, 16) * 16 : k);
+    return tail_plan(m, n, kbytes, device_cus()).bytes;
 }
 
 namespace {
 qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A, int64_t lda,
-                          bool a_centred, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream) {
+                          bool a_centred, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc, void *stream,
+                          uint8_t *tail_ws, size_t tail_bytes) {
     if (m == 0 || n == 0) return QMM_OK;
     Int8Args g{};
     g.m = m;
@@ -1155,25 +1306,41 @@ qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     const bool direct = direct_a && ldbt % 128 == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)Bt % 16 == 0;
     int tile = pl.tile ? (int)pl.tile : int8_tile_for(m, n, false);
     if (tile == 4 && !direct) tile = 3;  // same 256 x 256 tile, register-staged loads
-    if (tile == 4) {
-        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
-        const dim3 grid((unsigned)(ceil_div(m, 256) * ceil_div(n, 256)));
+    auto small_tiles = [&](Int8Args a) {
+        a.kb_tiles = blocked ? (int32_t)(pl.k_block / 64) : 0;
+        return run_int8<128, 128, 64, 2, 2>(a, blocked, s);
+    };
+    auto big_tiles = [&](Int8Args a) {
+        a.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
+        if (tile == 2) return run_int8<256, 256, 128, 2, 4>(a, blocked, s);
+        if (tile == 3) return run_int8<256, 256, 128, 4, 4>(a, blocked, s);
+        const dim3 grid((unsigned)(ceil_div(a.m, 256) * ceil_div(a.n, 256)));
         if (blocked)
-            gemm_int8_direct_kernel<true><<<grid, 1024, 0, s>>>(g);
+            gemm_int8_direct_kernel<true><<<grid, 1024, 0, s>>>(a);
         else
-            gemm_int8_direct_kernel<false><<<grid, 1024, 0, s>>>(g);
+            gemm_int8_direct_kernel<false><<<grid, 1024, 0, s>>>(a);
         return check_launch("gemm_int8_direct");
-    }
-    if (tile == 2) {
-        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
-        return run_int8<256, 256, 128, 2, 4>(g, blocked, s);
-    }
-    if (tile == 3) {
-        g.kb_tiles = blocked ? (int32_t)(pl.k_block / 128) : 0;
-        return run_int8<256, 256, 128, 4, 4>(g, blocked, s);
-    }
-    g.kb_tiles = blocked ? (int32_t)(pl.k_block / 64) : 0;
-    return run_int8<128, 128, 64, 2, 2>(g, blocked, s);
+    };
+    if (tile < 2 || tile > 4) return small_tiles(g);
+    const TailPlan t = tail_plan(m, n, k, device_cus());
+    if (!t.split || tail_ws == nullptr || tail_bytes < t.bytes) return big_tiles(g);
+    // ragged edges past whole rounds of 256 x 256 tiles: split-K strips
+    Int8Args head = g;
+    head.m = t.m0;
+    head.n = t.n0;
+    qmm_status st = big_tiles(head);
+    auto run = [&](Int8Args a, unsigned chunks) {
+        a.kb_tiles = blocked ? (int32_t)(pl.k_block / 64) : 0;
+        return run_int8<128, 128, 64, 2, 2>(a, blocked, s, chunks);
+    };
+    Int8Args bottom = g, right = g;
+    bottom.A = A + t.m0 * lda;
+    bottom.C = C + t.m0 * ldc;
+    right.Bt = Bt + t.n0 * ldbt;
+    right.C = C + t.n0;
+    if (st == QMM_OK) st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
+    if (st == QMM_OK) st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
+    return st;
 }
 }  // namespace
 

@@ -120,9 +120,12 @@ qmm_status tune_cache_load_env_once();             // QMM_TUNE_CACHE, read once 
 qmm_status tune_cache_save_env();                  // QMM_TUNE_CACHE, if set
 // Largest m n k that qmm_gemm_mod_p runs on the one-launch INT8 kernel.
 constexpr double kSmallInt8MaxMacs = 4294967296.0;  // 2^32: one launch measured faster up to 1536^3
+// tail_ws, tail_bytes: workspace for the split-K strip of a partial last round of
+// 256 x 256 tiles (lowp_tail_bytes); without it (nullptr) the product runs whole.
 qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
                             const uint8_t *A, int64_t lda, const int8_t *Bt, int64_t ldbt,
-                            uint8_t *C, int64_t ldc, void *stream);
+                            uint8_t *C, int64_t ldc, void *stream, uint8_t *tail_ws = nullptr,
+                            size_t tail_bytes = 0);
 // INT8 with k not a multiple of 16: A is first centred into Ac (m x ldac int8,
 // ldac = int8_bt_ld(k), zero past k), so the product reads it with aligned 16-byte
 // loads and centres nothing (launch_gemm_int8_centred_a).
@@ -130,7 +133,10 @@ qmm_status launch_centre_rows(const qmm_plan &pl, int64_t m, int64_t k, const ui
                               int64_t ldac, void *stream);
 qmm_status launch_gemm_int8_centred_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const int8_t *Ac,
                                       int64_t ldac, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc,
-                                      void *stream);
+                                      void *stream, uint8_t *tail_ws = nullptr, size_t tail_bytes = 0);
+// Bytes of the partial outputs qmm_gemm_mod_p's INT8 or FP4 product uses for the
+// rows of a partial last round of 256 x 256 tiles (0: no split).
+size_t lowp_tail_bytes(const qmm_plan &pl, int64_t m, int64_t n, int64_t k);
 int64_t int8_bt_ld(int64_t k);
 int64_t fp4_ld(int64_t k);
 void fp4_lut(uint32_t p, uint32_t &lo, uint32_t &hi);  // e2m1 codes of the residues 0..7, as bytes
@@ -142,7 +148,8 @@ qmm_status launch_pack_fp4_both(const qmm_plan &pl, int64_t m, int64_t n, int64_
                                 const uint8_t *B, int64_t ldb, uint8_t *A4, int64_t lda4, uint8_t *Bt4, int64_t ldbt4,
                                 void *stream);
 qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const uint8_t *A4, int64_t lda4,
-                           const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc, void *stream);
+                           const uint8_t *Bt4, int64_t ldbt4, uint8_t *C, int64_t ldc, void *stream,
+                           uint8_t *tail_ws = nullptr, size_t tail_bytes = 0);
 int int8_tile_for(int64_t m, int64_t n, bool fp4);
 // Whether qmm_gemm_mod_p's INT8 product centres A into aligned rows first (k not a
 // multiple of 16, or the direct-load tile 4, which reads both operands as rows).

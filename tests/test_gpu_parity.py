@@ -617,6 +617,29 @@ def test_int8_direct_tile_on_raw_and_centred_rows(torch, p, k, k_block):
     np.testing.assert_array_equal(host(qmm.gemm_centred(plan, big[:, 3:3 + k], Bt, n)), want)
 
 
+# A grid of 256 x 256 tiles just past whole rounds over the CUs (17 x 16 = 272 or
+# 17 x 17 = 289 tiles on 256 CUs) keeps the block of whole tiles on the large tiles
+# and runs the ragged edge strips (the last row, and the last column) as split-K
+# products on 128 x 128 tiles whose chunks are summed mod p.  Raw and centred A, a
+# blocked plan, the register-staged tile and FP4, one or both strips.
+@pytest.mark.parametrize("p,k,k_block,tile,path,n", [
+    (101, 1024, 0, 0, qmm.PATH_INT8, 4096), (101, 1000, 0, 0, qmm.PATH_INT8, 4097),
+    (251, 1024, 384, 0, qmm.PATH_INT8, 4097), (101, 1024, 0, 3, qmm.PATH_INT8, 4097),
+    (7, 700, 0, 0, qmm.PATH_FP4, 4096), (7, 3000, 0, 0, qmm.PATH_FP4, 4097)])
+def test_tail_of_a_partial_round_on_small_tiles(torch, p, k, k_block, tile, path, n):
+    m = 4097
+    rng = np.random.default_rng(p + k + tile + n)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    plan = qmm.choose_Qd(p, m, n, k, path=path)
+    if k_block:
+        plan.k_block = k_block
+    plan.tile = tile
+    note("tail split", plan, m, n, k)
+    got = host(qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan))
+    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+
+
 @pytest.mark.parametrize("k", (1001, 4097, 2049))
 def test_int8_unaligned_rows_on_every_tile(torch, k):
     # k odd: rows of A start at every byte offset within a dword, so the product
