@@ -188,7 +188,10 @@ qmm_status qmm_redq(const qmm_plan *plan, int64_t m, int64_t n, const void *CC, 
 /* Device workspace that qmm_gemm_mod_p needs for this plan and shape (INT8:
  * centred B transposed, plus A centred into aligned rows when k is not a multiple
  * of 16, or when the product runs on tile 4 and A's residues cannot be read as
- * they are: p > 128, k not a multiple of 128, or uncentred sums past int32). */
+ * they are: p > 128, k not a multiple of 128, or uncentred sums past int32; INT8
+ * and FP4: plus the partial outputs of the split-K edge strips when the grid of
+ * 256 x 256 tiles is just past whole rounds over the device's compute units, so
+ * the size can depend on the current device). */
 qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
                                    size_t *bytes);
 
