@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "qmm_device.h"
 #include "qmm_internal.h"
@@ -27,10 +28,17 @@ namespace {
 constexpr int kThreads = 256;
 
 // Grid for a rows x cols pass: enough x blocks to cover a row (at most 4096), and
-// as many rows per launch as keep the grid near 2^18 workgroups.
+// as many rows per launch as keep the grid near kPassBlocks workgroups; each
+// workgroup then strides over rows.  Workgroups of one output row each (2^18 of
+// them for the graph workload's operands) left these passes bound by launching
+// workgroups rather than by HBM.
+#ifndef QMM_PASS_BLOCKS
+#define QMM_PASS_BLOCKS 4096
+#endif
+constexpr int64_t kPassBlocks = QMM_PASS_BLOCKS;
 inline dim3 grid2(int64_t rows, int64_t cols) {
     const int64_t x = std::max<int64_t>(1, std::min<int64_t>(ceil_div(cols, kThreads), 4096));
-    const int64_t y = std::max<int64_t>(1, std::min<int64_t>({rows, (int64_t)65535, std::max<int64_t>(1, 262144 / x)}));
+    const int64_t y = std::max<int64_t>(1, std::min<int64_t>({rows, (int64_t)65535, std::max<int64_t>(1, kPassBlocks / x)}));
     return dim3((unsigned)x, (unsigned)y);
 }
 
@@ -74,6 +82,85 @@ __global__ __launch_bounds__(kThreads) void pack_cols_fwd_kernel(int64_t k, int6
                 w = (w << t) | (r < k ? (uint64_t)B[r * ldb + j] : 0ull);
             }
             CB[l * ldcb + j] = word_from_u64<W>(w);
+        }
+    }
+}
+
+// The same, four words per thread when rows of A are 4-byte aligned and d+1 <= 8:
+// the thread's 4 (d+1) residues are d+1 aligned dwords of the row (one load each,
+// consecutive threads on consecutive dwords), and its four words go out as one run.
+// Words whose residues run past k take the byte path.
+template <typename W, int D1>
+__global__ __launch_bounds__(kThreads) void pack_rows_rev4_kernel(int64_t m, int64_t k, int64_t nw,
+                                                                   const uint8_t *__restrict__ A, int64_t lda,
+                                                                   W *__restrict__ CA, int64_t ldca, uint32_t t) {
+    const int64_t groups = ceil_div(nw, 4);
+    QMM_FOR_ROWS(i, m) {
+        const uint8_t *a = A + i * lda;
+        W *ca = CA + i * ldca;
+        QMM_FOR_COLS(gi, groups) {
+            const int64_t l0 = 4 * gi, b0 = l0 * D1;
+            if (b0 + 4 * D1 <= k) {
+                uint32_t dw[D1];
+#pragma unroll
+                for (int q = 0; q < D1; ++q) dw[q] = *(const uint32_t *)(a + b0 + 4 * q);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    uint64_t v = 0;
+#pragma unroll
+                    for (int s2 = 0; s2 < D1; ++s2) {
+                        const int j = w * D1 + s2;
+                        v = (v << t) | ((dw[j >> 2] >> (8 * (j & 3))) & 0xffu);
+                    }
+                    if (l0 + w < nw) ca[l0 + w] = word_from_u64<W>(v);
+                }
+            } else {
+                for (int64_t l = l0; l < nw && l < l0 + 4; ++l) {
+                    uint64_t v = 0;
+                    for (int s2 = 0; s2 < D1; ++s2) {
+                        const int64_t c = l * D1 + s2;
+                        v = (v << t) | (c < k ? (uint64_t)a[c] : 0ull);
+                    }
+                    ca[l] = word_from_u64<W>(v);
+                }
+            }
+        }
+    }
+}
+
+// CompressColumns, four columns per thread when rows of B are 4-byte aligned: each
+// of the d+1 residue rows of a word row is one dword load for the four columns;
+// columns past n take byte loads.
+template <typename W>
+__global__ __launch_bounds__(kThreads) void pack_cols_fwd4_kernel(int64_t k, int64_t n, int64_t nw,
+                                                                   const uint8_t *__restrict__ B, int64_t ldb,
+                                                                   W *__restrict__ CB, int64_t ldcb,
+                                                                   uint32_t t, uint32_t d) {
+    const int64_t groups = ceil_div(n, 4);
+    QMM_FOR_ROWS(l, nw) {
+        const int64_t base = l * (d + 1);
+        W *cb = CB + l * ldcb;
+        QMM_FOR_COLS(gi, groups) {
+            const int64_t j0 = 4 * gi;
+            uint64_t v[4] = {0, 0, 0, 0};
+            const bool whole = j0 + 4 <= n;
+            for (int32_t s2 = (int32_t)d; s2 >= 0; --s2) {
+                const int64_t r = base + s2;
+                uint32_t x = 0;
+                if (r < k) {
+                    const uint8_t *row = B + r * ldb + j0;
+                    if (whole) {
+                        x = *(const uint32_t *)row;
+                    } else {
+                        for (int q = 0; j0 + q < n; ++q) x |= (uint32_t)row[q] << (8 * q);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (v[q] << t) | ((x >> (8 * q)) & 0xffu);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (j0 + q < n) cb[j0 + q] = word_from_u64<W>(v[q]);
         }
     }
 }
@@ -186,6 +273,28 @@ qmm_status launch_pack_rows_rev(const qmm_plan &pl, int64_t m, int64_t k, const 
     if (m * nw == 0) return QMM_OK;
     if (row_too_long(nw) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
+    const bool aligned = (uintptr_t)A % 4 == 0 && lda % 4 == 0;
+    if (aligned && pl.d + 1 <= 8) {
+        const dim3 grid = grid2(m, ceil_div(nw, 4));
+        auto go = [&](auto d1) {
+            constexpr int D1 = decltype(d1)::value;
+            if (pl.beta == 24)
+                pack_rows_rev4_kernel<float, D1><<<grid, kThreads, 0, s>>>(m, k, nw, A, lda, (float *)CA, ldca, pl.t);
+            else
+                pack_rows_rev4_kernel<double, D1><<<grid, kThreads, 0, s>>>(m, k, nw, A, lda, (double *)CA, ldca, pl.t);
+        };
+        switch (pl.d + 1) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        case 5: go(std::integral_constant<int, 5>{}); break;
+        case 6: go(std::integral_constant<int, 6>{}); break;
+        case 7: go(std::integral_constant<int, 7>{}); break;
+        default: go(std::integral_constant<int, 8>{}); break;
+        }
+        return check_launch("pack_rows_rev4");
+    }
     if (pl.beta == 24)
         pack_rows_rev_kernel<float><<<grid2(m, nw), kThreads, 0, s>>>(m, k, nw, A, lda, (float *)CA, ldca, pl.t, pl.d);
     else
@@ -199,6 +308,14 @@ qmm_status launch_pack_cols_fwd(const qmm_plan &pl, int64_t k, int64_t n, const 
     if (nw * n == 0) return QMM_OK;
     if (row_too_long(n) != QMM_OK) return QMM_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
+    if ((uintptr_t)B % 4 == 0 && ldb % 4 == 0) {
+        const dim3 grid = grid2(nw, ceil_div(n, 4));
+        if (pl.beta == 24)
+            pack_cols_fwd4_kernel<float><<<grid, kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CB, ldcb, pl.t, pl.d);
+        else
+            pack_cols_fwd4_kernel<double><<<grid, kThreads, 0, s>>>(k, n, nw, B, ldb, (double *)CB, ldcb, pl.t, pl.d);
+        return check_launch("pack_cols_fwd4");
+    }
     if (pl.beta == 24)
         pack_cols_fwd_kernel<float><<<grid2(nw, n), kThreads, 0, s>>>(k, n, nw, B, ldb, (float *)CB, ldcb, pl.t, pl.d);
     else
