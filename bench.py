@@ -230,6 +230,15 @@ class Stepper:
         for _ in range(warmup):
             self.convert()
             self.product()
+        # and at least 25 ms of steps, so short products run at the clock and cache
+        # state of a steady stream of launches before they are timed
+        import time as _time
+        torch.cuda.synchronize()
+        t0 = _time.perf_counter()
+        while _time.perf_counter() - t0 < 0.025:
+            self.convert()
+            self.product()
+            torch.cuda.synchronize()
 
         def step():
             self.convert()
