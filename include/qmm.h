@@ -109,7 +109,7 @@ typedef struct {
                           INT8 and FP4: 1 = 128 x 128 output tiles (4 wavefronts),
                           2 = 256 x 256 (8 wavefronts of 128 x 64),
                           3 = 256 x 256 (16 wavefronts of 64 x 64);
-                          INT8 only: 4 = 256 x 256, 16 wavefronts of 64 x 64 with both
+                          INT8 only: 4 = 256 x 256, 8 wavefronts of 128 x 64 with both
                           operands loaded straight into on-chip memory, which reads A's
                           rows whole as int8 (residues of p <= 128 when k is a multiple
                           of 128 and the uncentred sums fit int32, else a centred copy

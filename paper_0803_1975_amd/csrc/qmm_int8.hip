@@ -580,8 +580,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
 
 // Both operands as centred int8 rows (A as Ac from the centring pass, B as Bt), each
 // row zero padded to its leading dimension (a multiple of 128 bytes, at least k), so
-// every 128-byte K stage of a row is in bounds.  256 x 256 output tile, 16
-// wavefronts of 64 x 64 (2 x 2 blocks of i32_32x32x32_i8, four wavefronts per SIMD).
+// every 128-byte K stage of a row is in bounds.  256 x 256 output tile, WGM x WGN
+// wavefronts; the launch uses 2 x 4 wavefronts of 128 x 64 (4 x 2 blocks of
+// i32_32x32x32_i8, two wavefronts per SIMD: six fragment reads per eight MFMAs,
+// against four per four for 16 wavefronts of 64 x 64, which measured 4-6 % slower).
 // The stages go from HBM straight into LDS (global_load_lds_dwordx4: no staging
 // registers, no LDS store instructions, no VALU), two buffers of 64 KB.
 // LDS layout of an operand's stage: 256 rows of 128 bytes, no padding; 16-byte chunk
@@ -600,9 +602,11 @@ __global__ __launch_bounds__(64 * WGM * WGN, (BM * BN * 4 >= 256 * 256 * WGM * W
 // is complete in LDS and every read of this stage's buffer is done, so the last
 // k-step issues the loads of stage kt + 2 into this buffer.  The MFMAs after a
 // barrier never wait on LDS: their fragments are already in registers.
-template <bool BLOCKED>
-__global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
-    constexpr int BM = 256, BN = 256, KT = 128, KS = KT / 32, WGN = 4, WT = 64, F = 2;
+template <bool BLOCKED, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_int8_direct_kernel(Int8Args g) {
+    constexpr int BM = 256, BN = 256, KT = 128, KS = KT / 32;
+    constexpr int WAVES = WGM * WGN, WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
+    constexpr int BLK = 32 / WAVES;  // 8-row blocks of each operand's stage per wavefront
     constexpr int STAGE = BM * KT;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[2][2][STAGE];  // [buffer][A, B]
 
@@ -612,13 +616,13 @@ __global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
     tile_coords<BM, BN>(g.m, g.n, tm, tn);
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
 
-    // Direct loads: wavefront w fills blocks q = 2 w + i (i < 2, rows 8 q .. 8 q + 7)
-    // of each operand's stage.  Rows past m (n) read row m - 1 (n - 1); they only
-    // reach outputs that are not stored.
-    const int8_t *a_src[2], *b_src[2];
+    // Direct loads: wavefront w fills blocks q = BLK w + i (i < BLK, rows 8 q ..
+    // 8 q + 7) of each operand's stage.  Rows past m (n) read row m - 1 (n - 1); they
+    // only reach outputs that are not stored.
+    const int8_t *a_src[BLK], *b_src[BLK];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int q = 2 * wave + i, r = 8 * q + (lane >> 3);
+    for (int i = 0; i < BLK; ++i) {
+        const int q = BLK * wave + i, r = 8 * q + (lane >> 3);
         const int chunk = (lane & 7) ^ (r & 7) ^ ((r >> 3) & 1);
         const int64_t ar = min(row0 + r, g.m - 1), br = min(col0 + r, g.n - 1);
         a_src[i] = (const int8_t *)g.A + ar * g.lda + 16 * chunk;
@@ -627,33 +631,33 @@ __global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
     auto issue = [&](int kt, int b) {
         const int64_t k0 = (int64_t)kt * KT;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < BLK; ++i) {
             __builtin_amdgcn_global_load_lds((const void *)(a_src[i] + k0),
-                                             (__attribute__((address_space(3))) void *)&lds[b][0][(2 * wave + i) * 1024],
+                                             (__attribute__((address_space(3))) void *)&lds[b][0][(BLK * wave + i) * 1024],
                                              16, 0, 0);
             __builtin_amdgcn_global_load_lds((const void *)(b_src[i] + k0),
-                                             (__attribute__((address_space(3))) void *)&lds[b][1][(2 * wave + i) * 1024],
+                                             (__attribute__((address_space(3))) void *)&lds[b][1][(BLK * wave + i) * 1024],
                                              16, 0, 0);
         }
     };
 
-    ix16 acc[F][F];
+    ix16 acc[FM][FN];
 #pragma unroll
-    for (int mi = 0; mi < F; ++mi)
+    for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < F; ++ni) acc[mi][ni] = ix16{};
+        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
 
     // Fragment rows are 32 x + l % 32, so swz(row) = (l % 8) ^ ((l / 8) % 2), and the
     // chunk 2 ks + l / 32 sits at position (2 ks) ^ (l / 32) ^ swz.
     const int swz = (lane & 7) ^ ((lane >> 3) & 1) ^ (lane >> 5);
-    const int a_row = (wm * WT + (lane & 31)) * KT, b_row = (wn * WT + (lane & 31)) * KT;
-    ix4 af[2][F], bf[2][F];
+    const int a_row = (wm * WTM + (lane & 31)) * KT, b_row = (wn * WTN + (lane & 31)) * KT;
+    ix4 af[2][FM], bf[2][FN];
     auto read_frags = [&](int b, int ks, int slot) {
         const int co = 16 * ((2 * ks) ^ swz);
 #pragma unroll
-        for (int ni = 0; ni < F; ++ni) bf[slot][ni] = *(const ix4 *)&lds[b][1][b_row + ni * 32 * KT + co];
+        for (int ni = 0; ni < FN; ++ni) bf[slot][ni] = *(const ix4 *)&lds[b][1][b_row + ni * 32 * KT + co];
 #pragma unroll
-        for (int mi = 0; mi < F; ++mi) af[slot][mi] = *(const ix4 *)&lds[b][0][a_row + mi * 32 * KT + co];
+        for (int mi = 0; mi < FM; ++mi) af[slot][mi] = *(const ix4 *)&lds[b][0][a_row + mi * 32 * KT + co];
     };
 
     const int ntiles = (int)ceil_div(g.k, KT);
@@ -672,15 +676,16 @@ __global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
             // on the last stage the other buffer's reads are not used
             read_frags(ks + 1 < KS ? buf : buf ^ 1, (ks + 1) % KS, cur ^ 1);
 #pragma unroll
-            for (int mi = 0; mi < F; ++mi)
+            for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < F; ++ni)
+                for (int ni = 0; ni < FN; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
 #pragma unroll
-            for (int x = 0; x < 2 * F; ++x) {
+            for (int x = 0; x < FM + FN; ++x) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             }
+            if constexpr (FM * FN > FM + FN) __builtin_amdgcn_sched_group_barrier(0x008, FM * FN - (FM + FN), 0);
             if (ks == KS - 2 && more) {
                 asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
                 __syncthreads();
@@ -689,9 +694,9 @@ __global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
         if constexpr (BLOCKED) {
             if ((kt + 1) % g.kb_tiles == 0 && more) {
 #pragma unroll
-                for (int mi = 0; mi < F; ++mi)
+                for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-                    for (int ni = 0; ni < F; ++ni)
+                    for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
                         for (int r = 0; r < 16; ++r)
                             acc[mi][ni][r] = (int)mod_u32_m32((uint32_t)acc[mi][ni][r] + g.off, g.p, g.magic32);
@@ -704,11 +709,11 @@ __global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
         // (R = 8q + 4 (l / 32)); packed into a dword and transposed across the lane's
         // quad, they become 4 consecutive bytes of row R + (l % 4), one dword store.
         const int j = lane & 3;
-        uint8_t *cbase = g.C + (row0 + wm * WT + 4 * (lane >> 5) + j) * g.ldc + col0 + wn * WT + (lane & 31) - j;
+        uint8_t *cbase = g.C + (row0 + wm * WTM + 4 * (lane >> 5) + j) * g.ldc + col0 + wn * WTN + (lane & 31) - j;
 #pragma unroll
-        for (int mi = 0; mi < F; ++mi)
+        for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < F; ++ni)
+            for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     uint32_t w = 0;
@@ -721,13 +726,13 @@ __global__ __launch_bounds__(1024, 1) void gemm_int8_direct_kernel(Int8Args g) {
         return;
     }
 #pragma unroll
-    for (int mi = 0; mi < F; ++mi)
+    for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < F; ++ni)
+        for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t row = row0 + wm * WT + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t col = col0 + wn * WT + ni * 32 + (lane & 31);
+                const int64_t row = row0 + wm * WTM + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t col = col0 + wn * WTN + ni * 32 + (lane & 31);
                 if (row < g.m && col < g.n)
                     g.C[row * g.ldc + col] = (uint8_t)mod_i32_magic((int32_t)acc[mi][ni][r], g.p, g.magic, g.off);
             }
@@ -1008,7 +1013,7 @@ bool int8_centres_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
 
 int int8_tile_for(int64_t m, int64_t n, bool fp4) {
     // 256 x 256 tiles once they (nearly) fill the 256 CUs, 128 x 128 below that.
-    // INT8: the direct-load tile (16 wavefronts of 64 x 64, both operands straight
+    // INT8: the direct-load tile (8 wavefronts of 128 x 64, both operands straight
     // from HBM into LDS, one barrier per K stage); the product kernels fall back to
     // tile 3 where A's rows cannot be read whole.  FP4: 16 wavefronts of 64 x 64
     // with register-staged loads (measured interleaved on one GPU against 8
@@ -1316,9 +1321,9 @@ qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
         if (tile == 3) return run_int8<256, 256, 128, 4, 4>(a, blocked, s);
         const dim3 grid((unsigned)(ceil_div(a.m, 256) * ceil_div(a.n, 256)));
         if (blocked)
-            gemm_int8_direct_kernel<true><<<grid, 1024, 0, s>>>(a);
+            gemm_int8_direct_kernel<true, 2, 4><<<grid, 512, 0, s>>>(a);
         else
-            gemm_int8_direct_kernel<false><<<grid, 1024, 0, s>>>(a);
+            gemm_int8_direct_kernel<false, 2, 4><<<grid, 512, 0, s>>>(a);
         return check_launch("gemm_int8_direct");
     };
     if (tile < 2 || tile > 4) return small_tiles(g);
