@@ -23,6 +23,11 @@
 //           MFMA (e2m1 codes of p <= 8, 64 k per instruction), with the next
 //           stage's loads in flight during the MFMAs, then reduces mod p and
 //           stores its bytes.
+// Device side, INT8 raw (QMM_BATCH_RAW: no pack stage, no workspace): one persistent
+// kernel per tile shape reads A's rows and B's k-rows in place with unaligned 16-byte
+// loads, from one self-contained record per tile, and pipelines K stages across
+// its tiles (the next tile's first loads go out during the current tile's last
+// stage).
 // Device side, FP64 Q-adic: one persistent kernel whose tiles pack rows of A
 // reversed and columns of B forward straight from the bytes on the way into LDS.
 #include <hip/hip_runtime.h>
@@ -85,7 +90,6 @@ struct Desc {
     int32_t kp, mp, np, kpb;
     uint32_t fp4, lut_lo, lut_hi;
     uint32_t magic32;  // floor(2^32 / p)
-    uint32_t c_vec;    // C and ldc 4-byte aligned: whole tiles are stored as dwords
 };
 
 // One operand block for the pack kernel: kind 0 = rows r0 .. r0+63 of A at k bytes
@@ -272,11 +276,7 @@ constexpr int raw_bpitch(int bn) { return bn + 16; }
 constexpr int tile_lds_bytes(int bm, int bn, bool raw) {
     return bm * PT + (raw && KT * raw_bpitch(bn) > bn * PT ? KT * raw_bpitch(bn) : bn * PT);
 }
-// RAW: the operands come straight from the products' own residue matrices (no pack
-// kernel, no workspace): A's 16-byte row segments are centred in registers, and B's
-// k-rows, centred, go to LDS as they are (k-major); the MFMA's B fragments are read
-// from them with the LDS transpose load.
-template <int BM, int BN, int WGM, int WGN, bool FP4, bool RAW = false>
+template <int BM, int BN, int WGM, int WGN, bool FP4>
 __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
     constexpr int SEGS = KT / 16;
@@ -286,9 +286,8 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
-    const int kp = RAW ? D.k : D.kpb;  // bytes per packed row (k values for INT8, half of them for FP4)
+    const int kp = D.kpb;  // bytes per packed row (k values for INT8, half of them for FP4)
     constexpr bool fp4 = FP4;  // the tile list of an FP4 class holds only FP4 products
-    static_assert(!(RAW && FP4), "raw tiles are INT8");
     const int stages = (kp + KT - 1) / KT;
 
     // Thread tid stages the 16-byte segment seg = tid % 8 of rows tid / 8 + 32 i: the
@@ -296,44 +295,18 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     static_assert(A_SEGS % NT == 0 && B_SEGS % NT == 0, "whole rows per load step");
     constexpr int RSTEP = NT / SEGS;
     const int seg = tid % SEGS, rfirst = tid / SEGS;
-    const int8_t *a_base = RAW ? nullptr : D.Ac + (row0 + rfirst) * kp + 16 * seg;
-    const int8_t *b_base = RAW ? nullptr : D.Bt + (col0 + rfirst) * kp + 16 * seg;
+    const int8_t *a_base = D.Ac + (row0 + rfirst) * kp + 16 * seg;
+    const int8_t *b_base = D.Bt + (col0 + rfirst) * kp + 16 * seg;
     const int slot = rfirst * PT + 16 * seg;
     const int64_t rstride = (int64_t)RSTEP * kp;
-    // RAW: B segment c = tid + NT i is k-row c / CSEG of the stage, columns 16 (c % CSEG) ..
-    constexpr int CSEG = BN / 16;
-    // RAW: 32-bit offsets into A and B; A's rows and B's columns are fixed per tile
-    const uint32_t a_size = D.m > 0 && D.k > 0 ? (uint32_t)((D.m - 1) * D.lda + D.k) : 0u;
-    const uint32_t b_size = D.k > 0 && D.n > 0 ? (uint32_t)((D.k - 1) * D.ldb + D.n) : 0u;
-    const uint32_t lda32 = (uint32_t)D.lda, ldb32 = (uint32_t)D.ldb;
-    const int32_t b_cols = D.n - (int32_t)(col0 + 16 * (tid % CSEG));  // the same for every B segment
     ix4 ra[A_LOADS], rb[B_LOADS];
-    // RAW: the windows of a stage's segments, finished into ra / rb when published
-    constexpr int RA = RAW ? A_LOADS : 1, RB = RAW ? B_LOADS : 1;
-    uint32_t wa[RA][5], wb[RB][5];
-    int32_t ma[RA], mb[RB];
     auto fetch = [&](int st) __attribute__((always_inline)) {
         const int k0 = st * KT;
-        if constexpr (RAW) {
-            const int32_t kk = k0 + 16 * seg;
+        const bool ok = k0 + 16 * seg < kp;
 #pragma unroll
-            for (int i = 0; i < A_LOADS; ++i) {
-                const int32_t row = (int32_t)row0 + rfirst + i * RSTEP;
-                raw_issue32(wa[i], ma[i], D.A, (uint32_t)row * lda32 + (uint32_t)kk, row < D.m ? D.k - kk : 0, a_size);
-            }
+        for (int i = 0; i < A_LOADS; ++i) ra[i] = ok ? gload16(a_base + i * rstride + k0) : ix4{0, 0, 0, 0};
 #pragma unroll
-            for (int i = 0; i < B_LOADS; ++i) {
-                const int32_t krow = k0 + (tid + NT * i) / CSEG;
-                raw_issue32(wb[i], mb[i], D.B, (uint32_t)krow * ldb32 + (uint32_t)(col0 + 16 * (tid % CSEG)),
-                            krow < D.k ? b_cols : 0, b_size);
-            }
-        } else {
-            const bool ok = k0 + 16 * seg < kp;
-#pragma unroll
-            for (int i = 0; i < A_LOADS; ++i) ra[i] = ok ? gload16(a_base + i * rstride + k0) : ix4{0, 0, 0, 0};
-#pragma unroll
-            for (int i = 0; i < B_LOADS; ++i) rb[i] = ok ? gload16(b_base + i * rstride + k0) : ix4{0, 0, 0, 0};
-        }
+        for (int i = 0; i < B_LOADS; ++i) rb[i] = ok ? gload16(b_base + i * rstride + k0) : ix4{0, 0, 0, 0};
     };
 
     ix16 acc[FM][FN];
@@ -342,50 +315,10 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
 #pragma unroll
         for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
     auto publish = [&]() __attribute__((always_inline)) {
-        if constexpr (RAW) {
 #pragma unroll
-            for (int i = 0; i < A_LOADS; ++i) {
-                uint32_t o[4];
-                raw_finish(wa[i], ma[i], o);
-                ra[i] = ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
-            }
+        for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
 #pragma unroll
-            for (int i = 0; i < B_LOADS; ++i) {
-                uint32_t o[4];
-                raw_finish(wb[i], mb[i], o);
-                rb[i] = ix4{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
-            }
-            if (D.neg_p == 0) {  // residues below 128, sum exact uncentred: bytes as they are
-#pragma unroll
-                for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
-#pragma unroll
-                for (int i = 0; i < B_LOADS; ++i) {
-                    const int c = tid + NT * i;
-                    *(ix4 *)&lds[BM * PT + (c / CSEG) * raw_bpitch(BN) + 16 * (c % CSEG)] = rb[i];
-                }
-                __syncthreads();
-                return;
-            }
-#pragma unroll
-            for (int i = 0; i < A_LOADS; ++i) {
-                const ix4 v = ra[i];
-                *(ix4 *)&lds[slot + i * RSTEP * PT] =
-                    ix4{(int)centre4((uint32_t)v.x, D.add_h, D.neg_p), (int)centre4((uint32_t)v.y, D.add_h, D.neg_p),
-                        (int)centre4((uint32_t)v.z, D.add_h, D.neg_p), (int)centre4((uint32_t)v.w, D.add_h, D.neg_p)};
-            }
-#pragma unroll
-            for (int i = 0; i < B_LOADS; ++i) {
-                const int c = tid + NT * i, kr = c / CSEG, cs = c % CSEG;
-                *(ix4 *)&lds[BM * PT + kr * raw_bpitch(BN) + 16 * cs] =
-                    ix4{(int)centre4((uint32_t)rb[i].x, D.add_h, D.neg_p), (int)centre4((uint32_t)rb[i].y, D.add_h, D.neg_p),
-                        (int)centre4((uint32_t)rb[i].z, D.add_h, D.neg_p), (int)centre4((uint32_t)rb[i].w, D.add_h, D.neg_p)};
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[slot + i * RSTEP * PT] = ra[i];
-#pragma unroll
-            for (int i = 0; i < B_LOADS; ++i) *(ix4 *)&lds[BM * PT + slot + i * RSTEP * PT] = rb[i];
-        }
+        for (int i = 0; i < B_LOADS; ++i) *(ix4 *)&lds[BM * PT + slot + i * RSTEP * PT] = rb[i];
         __syncthreads();
     };
     auto compute = [&](int st) __attribute__((always_inline)) {
@@ -395,27 +328,9 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
         const int ksteps = (min(KT, kp - st * KT) + 31) / 32;  // bytes past k are zero
         for (int ks = 0; ks < ksteps; ++ks) {
             ix4 bf[FN];
-            if constexpr (RAW) {
-                // Lane l's fragment: column l % 32 of the block, k-bytes 16 (l / 32) .. + 15
-                // of the step (the same k order as A's), as two transpose loads of 8 k-rows
-                // each: group g = l / 16 reads rows 16 (g / 2) .., columns 16 (g % 2) ..,
-                // lane 2b + c of the group giving bytes 8c .. 8c + 7 of row b.
-                constexpr int BP = raw_bpitch(BN);
-                const int g = lane >> 4, sl = lane & 15;
 #pragma unroll
-                for (int ni = 0; ni < FN; ++ni) {
-                    const uint8_t *bp = &sB[(ks * 32 + 16 * (g >> 1) + (sl >> 1)) * BP + wn * WTN + ni * 32 +
-                                            16 * (g & 1) + 8 * (sl & 1)];
-                    const v2i b0 = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i *)bp);
-                    const v2i b1 =
-                        __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i *)(bp + 8 * BP));
-                    bf[ni] = ix4{b0.x, b0.y, b1.x, b1.y};
-                }
-            } else {
-#pragma unroll
-                for (int ni = 0; ni < FN; ++ni)
-                    bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
-            }
+            for (int ni = 0; ni < FN; ++ni)
+                bf[ni] = *(const ix4 *)&sB[(wn * WTN + ni * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
 #pragma unroll
             for (int mi = 0; mi < FM; ++mi) {
                 const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * PT + ks * 32 + 16 * (lane >> 5)];
@@ -458,10 +373,11 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
     auto residue = [&](int32_t bits) __attribute__((always_inline)) {
         return mod_u32_m32((uint32_t)acc_value(bits, fp4) + D.off, D.p, D.magic32);
     };
-    if (full && D.c_vec) {
-        // Interior tile, aligned C: registers 4q .. 4q+3 (rows R .. R+3 of one column)
-        // packed into a dword and transposed across the lane's quad become 4
-        // consecutive bytes of row R + l % 4: one dword store each.
+    if (full) {
+        // Interior tile: registers 4q .. 4q+3 (rows R .. R+3 of one column) packed
+        // into a dword and transposed across the lane's quad become 4 consecutive
+        // bytes of row R + l % 4: one dword store each, unaligned when ldc or C is
+        // not a multiple of 4 (served like the unaligned loads of load16_any).
         const int j = lane & 3;
         const uint32_t b0 = (uint32_t)(row0 + wm * WTM + 4 * (lane >> 5) + j) * ldc +
                             (uint32_t)(col0 + wn * WTN + (lane & 31) - j);
@@ -475,7 +391,7 @@ __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t
 #pragma unroll
                     for (int i = 0; i < 4; ++i) w |= residue(acc[mi][ni][4 * q + i]) << (8 * i);
                     w = quad_transpose_bytes(w, j);
-                    *(QMM_GLOBAL uint32_t *)(cbase + b0 + (uint32_t)(mi * 32 + 8 * q) * ldc + ni * 32) = w;
+                    *(QMM_GLOBAL u32a1 *)(cbase + b0 + (uint32_t)(mi * 32 + 8 * q) * ldc + ni * 32) = w;
                 }
     } else {
 #pragma unroll
@@ -586,14 +502,247 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 // One persistent kernel per tile class (so each gets the registers and occupancy
 // of its own shape).  Workgroup w takes tiles w, w + G, w + 2G, ... of its class's
 // list, which is sorted longest first.
-template <uint32_t SHAPE, bool FP4, bool RAW = false>
-__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 && !RAW ? 7 : 5))
+template <uint32_t SHAPE, bool FP4>
+__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 ? 7 : 5))
 void batched_int8_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles, int32_t ntiles) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[tile_lds_bytes(shape_bm(SHAPE), shape_bn(SHAPE), RAW)];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[tile_lds_bytes(shape_bm(SHAPE), shape_bn(SHAPE), false)];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
-        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_wgm(SHAPE), 4 / shape_wgm(SHAPE), FP4, RAW>(D, tr.tm, tr.tn, lds);
+        int8_tile<shape_bm(SHAPE), shape_bn(SHAPE), shape_wgm(SHAPE), 4 / shape_wgm(SHAPE), FP4>(D, tr.tm, tr.tn, lds);
+    }
+}
+
+// One tile of a raw batch: everything its workgroup needs in one record, the
+// operand bases moved to the tile's origin (row0, col0), so a tile starts without
+// a dependent descriptor lookup.  Sizes are bytes of data from the moved bases.
+struct RawTile {
+    const uint8_t *A;          // A + row0 lda
+    const uint8_t *B;          // B + col0
+    uint8_t *C;                // C + row0 ldc + col0
+    uint32_t lda, ldb, ldc;
+    int32_t rows, cols, k;     // m - row0, n - col0, k
+    uint32_t a_size, b_size;   // (rows - 1) lda + k and (k - 1) ldb + cols (0 when k = 0)
+    uint32_t p, off, magic32;  // modulus, epilogue offset (0 for uncentred sums), floor(2^32 / p)
+    uint32_t add_h, neg_p;     // centring constants (0: residues used as they are)
+    uint32_t pad[5];
+};
+static_assert(sizeof(RawTile) == 96, "RawTile is 24 dwords");
+constexpr int kRawTileDwords = (int)(sizeof(RawTile) / 4);
+
+// The record of the next tile, loaded by lanes 0 .. 23 as vector loads (so its
+// wait is ordered with the operand loads', not with the LDS traffic), then read
+// back into uniform registers lane by lane.
+__device__ __forceinline__ uint32_t raw_record_issue(const RawTile *recs, int32_t i, int lane) {
+    const QMM_GLOBAL uint32_t *w = (const QMM_GLOBAL uint32_t *)(recs + i);
+    return w[lane < kRawTileDwords ? lane : 0];  // every lane loads: no branch around the load
+}
+__device__ __forceinline__ RawTile raw_record_read(uint32_t v) {
+    uint32_t d[kRawTileDwords];
+#pragma unroll
+    for (int j = 0; j < kRawTileDwords; ++j) d[j] = __builtin_amdgcn_readlane(v, j);
+    return __builtin_bit_cast(RawTile, d);
+}
+
+// Persistent raw tiles of one shape: A's rows and B's k-rows come straight from the
+// products' residue matrices as unaligned 16-byte loads (A centred in registers when
+// the product needs it; B's k-rows go to LDS as they are and the MFMA's B fragments
+// are read from them with the LDS transpose load).  Workgroup w takes records w,
+// w + G, ... and runs their K stages as one pipeline: while a stage computes, the
+// next stage's loads are in flight, and the next tile's first stage and record are
+// loaded during the current tile's last stage, so neither a tile's first loads nor
+// its record wait in the open.  One LDS buffer (so several workgroups share a CU).
+template <uint32_t SHAPE>
+__global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : 5)
+void batched_raw_kernel(const RawTile *__restrict__ recs, int32_t ntiles) {
+    constexpr int BM = shape_bm(SHAPE), BN = shape_bn(SHAPE), WGM = shape_wgm(SHAPE), WGN = 4 / WGM;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
+    constexpr int SEGS = KT / 16, CSEG = BN / 16, RSTEP = NT / SEGS;
+    constexpr int A_LOADS = BM * SEGS / NT, B_LOADS = KT * CSEG / NT;
+    // LDS: A's stage as BM rows of 128 bytes, B's as KT k-rows of BN bytes.  A (and B
+    // when BN = 128) without padding, 16-byte chunk c of row r at position
+    // c ^ swz(r), swz(r) = (r % 8) ^ ((r / 8) % 2): the register writes (8 lanes per
+    // row, 16 lanes on two rows), the A fragment reads (16 lanes on 16 rows at one
+    // chunk) and the B transpose reads (32 lanes on 8 rows, two chunks) each touch
+    // every bank once.  Narrower B keeps rows of BN + 16 bytes.
+    constexpr bool BSWZ = BN == 128;
+    constexpr int BP = BSWZ ? BN : raw_bpitch(BN);
+    constexpr int A_BYTES = BM * KT;
+    static_assert(A_LOADS * NT == BM * SEGS && B_LOADS * NT == KT * CSEG, "whole load steps");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[A_BYTES + KT * BP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    // thread tid loads 16-byte segment seg of A rows rfirst + RSTEP i, and B segment
+    // c = tid + NT i: k-row c / CSEG of the stage, columns 16 (c % CSEG) ..
+    const int seg = tid % SEGS, rfirst = tid / SEGS;
+    const uint32_t bcol = 16u * (uint32_t)(tid % CSEG);
+    // swizzles: of this thread's A rows rfirst + RSTEP i (RSTEP = 32), of its B k-rows
+    // (tid + NT i) / 8 when BN = 128, of the fragment rows 32 x + l % 32
+    const int a_swz = (rfirst & 7) ^ ((rfirst >> 3) & 1);
+    const int b_swz = ((tid >> 3) & 7) ^ ((tid >> 6) & 1);
+    const int f_swz = (lane & 7) ^ ((lane >> 3) & 1);
+
+    ix4 ra[A_LOADS], rb[B_LOADS];
+    uint32_t sa[A_LOADS], sb[B_LOADS];
+    auto as_ix4 = [](uint4v_t v) { return ix4{(int)v.x, (int)v.y, (int)v.z, (int)v.w}; };
+    // Issue stage st of tile t.  A's bytes past k in a row are the next row's: they
+    // meet B's k-rows past k, which are zero, so they add nothing.  B's columns past
+    // the product's n reach only outputs that are not stored.
+    auto fetch = [&](const RawTile &t, int st) __attribute__((always_inline)) {
+        const int32_t kk = st * KT + 16 * seg;
+        const bool bcol_ok = (int32_t)bcol < t.cols;
+        if (t.a_size >= 16u && t.b_size >= 16u) {
+#pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) {
+                const int32_t r = rfirst + i * RSTEP;
+                ra[i] = as_ix4(load16_clamped(t.A, (uint32_t)r * t.lda + (uint32_t)kk, r < t.rows && kk < t.k, t.a_size, sa[i]));
+            }
+#pragma unroll
+            for (int i = 0; i < B_LOADS; ++i) {
+                const int32_t kr = st * KT + (tid + NT * i) / CSEG;
+                rb[i] = as_ix4(load16_clamped(t.B, (uint32_t)kr * t.ldb + bcol, kr < t.k && bcol_ok, t.b_size, sb[i]));
+            }
+        } else {  // an operand under 16 bytes from the tile's origin: byte loads
+#pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) {
+                const int32_t r = rfirst + i * RSTEP;
+                ra[i] = as_ix4(load16_tiny(t.A, (uint32_t)r * t.lda + (uint32_t)kk, r < t.rows && kk < t.k, t.a_size));
+                sa[i] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < B_LOADS; ++i) {
+                const int32_t kr = st * KT + (tid + NT * i) / CSEG;
+                rb[i] = as_ix4(load16_tiny(t.B, (uint32_t)kr * t.ldb + bcol, kr < t.k && bcol_ok, t.b_size));
+                sb[i] = 0;
+            }
+        }
+    };
+    auto publish = [&](const RawTile &t) __attribute__((always_inline)) {
+        auto fix = [](ix4 v, uint32_t sh) {
+            return sh ? __builtin_bit_cast(ix4, shift_down_bytes(__builtin_bit_cast(uint4v_t, v), sh)) : v;
+        };
+#pragma unroll
+        for (int i = 0; i < A_LOADS; ++i) ra[i] = fix(ra[i], sa[i]);
+#pragma unroll
+        for (int i = 0; i < B_LOADS; ++i) rb[i] = fix(rb[i], sb[i]);
+        if (t.neg_p != 0) {
+            auto centre = [&](ix4 v) {
+                return ix4{(int)centre4((uint32_t)v.x, t.add_h, t.neg_p), (int)centre4((uint32_t)v.y, t.add_h, t.neg_p),
+                           (int)centre4((uint32_t)v.z, t.add_h, t.neg_p), (int)centre4((uint32_t)v.w, t.add_h, t.neg_p)};
+            };
+#pragma unroll
+            for (int i = 0; i < A_LOADS; ++i) ra[i] = centre(ra[i]);
+#pragma unroll
+            for (int i = 0; i < B_LOADS; ++i) rb[i] = centre(rb[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < A_LOADS; ++i) *(ix4 *)&lds[(rfirst + i * RSTEP) * KT + 16 * (seg ^ a_swz)] = ra[i];
+#pragma unroll
+        for (int i = 0; i < B_LOADS; ++i) {
+            const int c = tid + NT * i, kr = c / CSEG, cs = c % CSEG;
+            *(ix4 *)&lds[A_BYTES + kr * BP + 16 * (BSWZ ? cs ^ b_swz : cs)] = rb[i];
+        }
+        __syncthreads();
+    };
+    ix16 acc[FM][FN];
+    auto compute = [&](const RawTile &t, int st) __attribute__((always_inline)) {
+        const uint8_t *sA = lds, *sB = lds + A_BYTES;
+        const int ksteps = (min(KT, t.k - st * KT) + 31) / 32;
+        const int g = lane >> 4, sl = lane & 15;
+        for (int ks = 0; ks < ksteps; ++ks) {
+            // lane l's B fragment: column l % 32 of the block, k-bytes 16 (l / 32) .. + 15
+            // of the step, as two transpose loads of 8 k-rows: group g = l / 16 reads rows
+            // 16 (g / 2) .., columns 16 (g % 2) .., lane 2b + c of the group giving bytes
+            // 8c .. 8c + 7 of row b
+            ix4 bf[FN];
+#pragma unroll
+            for (int ni = 0; ni < FN; ++ni) {
+                // rows 16 (g / 2) + sl / 2 and 8 more: swz = sl / 2 and sl / 2 ^ 1
+                const int row = ks * 32 + 16 * (g >> 1) + (sl >> 1), chunk = (wn * WTN + ni * 32) / 16 + (g & 1);
+                const uint8_t *bp0, *bp1;
+                if constexpr (BSWZ) {
+                    bp0 = &sB[row * BP + 16 * (chunk ^ (sl >> 1)) + 8 * (sl & 1)];
+                    bp1 = &sB[(row + 8) * BP + 16 * (chunk ^ (sl >> 1) ^ 1) + 8 * (sl & 1)];
+                } else {
+                    bp0 = &sB[row * BP + 16 * chunk + 8 * (sl & 1)];
+                    bp1 = bp0 + 8 * BP;
+                }
+                const v2i b0 = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i *)bp0);
+                const v2i b1 = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i *)bp1);
+                bf[ni] = ix4{b0.x, b0.y, b1.x, b1.y};
+            }
+#pragma unroll
+            for (int mi = 0; mi < FM; ++mi) {
+                const ix4 af = *(const ix4 *)&sA[(wm * WTM + mi * 32 + (lane & 31)) * KT + 16 * ((2 * ks + (lane >> 5)) ^ f_swz)];
+#pragma unroll
+                for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // the stage's LDS is read before the next stage overwrites it
+    };
+    // Epilogue: register r of a block holds row 8 (r/4) + 4 (l/32) + r % 4 of column
+    // l % 32; every C offset of a product fits 32 bits (checked on the host).
+    auto epilogue = [&](const RawTile &t) __attribute__((always_inline)) {
+        QMM_GLOBAL uint8_t *cbase = (QMM_GLOBAL uint8_t *)t.C;
+        auto residue = [&](int32_t v) { return mod_u32_m32((uint32_t)v + t.off, t.p, t.magic32); };
+        // Registers 4q .. 4q+3 (rows R .. R+3 of one column) packed into a dword and
+        // transposed across the lane's quad become 4 consecutive bytes of row R + l % 4,
+        // columns c .. c+3 (c a multiple of 4): one dword store (unaligned when ldc or C
+        // is not a multiple of 4); on a tile's edge, byte stores for a quad that the
+        // product's last column cuts, nothing past its last row.
+        const int j = lane & 3;
+        const int32_t r0 = wm * WTM + 4 * (lane >> 5) + j, c0 = wn * WTN + (lane & 31) - j;
+        const bool whole = t.rows >= BM && t.cols >= BN;
+#pragma unroll
+        for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < FN; ++ni)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w |= residue(acc[mi][ni][4 * q + i]) << (8 * i);
+                    w = quad_transpose_bytes(w, j);
+                    const int32_t r = r0 + mi * 32 + 8 * q, c = c0 + ni * 32;
+                    QMM_GLOBAL uint8_t *dst = cbase + (uint32_t)r * t.ldc + (uint32_t)c;
+                    if (whole || (r < t.rows && c + 4 <= t.cols)) {
+                        *(QMM_GLOBAL u32a1 *)dst = w;
+                    } else if (r < t.rows && c < t.cols) {
+                        const int32_t nb = t.cols - c;  // 1 .. 3 bytes
+                        dst[0] = (uint8_t)w;
+                        if (nb > 1) dst[1] = (uint8_t)(w >> 8);
+                        if (nb > 2) dst[2] = (uint8_t)(w >> 16);
+                    }
+                }
+    };
+
+    int32_t i = blockIdx.x;
+    if (i >= ntiles) return;
+    RawTile t = recs[i];
+    fetch(t, 0);
+    for (;;) {
+        const int32_t inext = i + (int32_t)gridDim.x;
+        const bool more = inext < ntiles;
+        // the next record stays in one vector register (lane j: dword j) until used
+        const uint32_t rv = raw_record_issue(recs, more ? inext : i, lane);
+#pragma unroll
+        for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = ix16{};
+        const int stages = (t.k + KT - 1) / KT;
+        for (int st = 0; st < stages; ++st) {
+            publish(t);
+            if (st + 1 < stages)
+                fetch(t, st + 1);
+            else if (more)
+                fetch(raw_record_read(rv), 0);
+            compute(t, st);
+        }
+        if (more && stages == 0) fetch(raw_record_read(rv), 0);  // k = 0: nothing to wait for
+        epilogue(t);
+        if (!more) break;
+        t = raw_record_read(rv);
+        i = inext;
     }
 }
 
@@ -712,6 +861,7 @@ struct qmm_batched {
     std::vector<qmm_plan> plans;
     Desc *d_desc = nullptr;
     TileRef *d_tiles = nullptr;
+    RawTile *d_raw = nullptr;  // raw batches: one record per INT8 tile, in d_tiles' order
     int32_t ntiles = 0;
     PackJob *d_jobs = nullptr;
     int32_t njobs = 0;
@@ -733,6 +883,7 @@ void release(qmm_batched *b) {
     if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_raw) (void)hipFree(b->d_raw);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_ws) (void)hipFree(b->d_ws);
     delete b;
@@ -802,7 +953,6 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         D.magic = mod_magic(P.p);
         D.off = P.p * ((1u << 31) / P.p);
         D.magic32 = (uint32_t)((1ull << 32) / P.p);
-        D.c_vec = ((uintptr_t)P.C % 4 == 0) && (P.ldc % 4 == 0);
         D.invp = 1.0 / (double)P.p;
         int bm = 64, bn = 64;
         ShapeCost costs[SHAPE_COUNT];  // the product's tile costs (INT8 and FP4 tiles)
@@ -879,8 +1029,8 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         (const void *)batched_int8_kernel<SHAPE_128x32, true>,  (const void *)batched_int8_kernel<SHAPE_128x128, true>,
         (const void *)batched_fp64_kernel};
     const void *kraw[SHAPE_COUNT] = {
-        (const void *)batched_int8_kernel<SHAPE_64x64, false, true>,  (const void *)batched_int8_kernel<SHAPE_32x128, false, true>,
-        (const void *)batched_int8_kernel<SHAPE_128x32, false, true>, (const void *)batched_int8_kernel<SHAPE_128x128, false, true>};
+        (const void *)batched_raw_kernel<SHAPE_64x64>, (const void *)batched_raw_kernel<SHAPE_32x128>,
+        (const void *)batched_raw_kernel<SHAPE_128x32>, (const void *)batched_raw_kernel<SHAPE_128x128>};
     int grid[kClasses];
     for (int c = 0; c < kClasses; ++c) {
         int per_cu = 1;
@@ -936,6 +1086,37 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         return hip_fail(e, "hipMemcpy");
     if (!flat.empty() && (e = hipMemcpy(b->d_tiles, flat.data(), sizeof(TileRef) * flat.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "hipMemcpy");
+    if (b->raw && !flat.empty()) {
+        // raw tiles: one self-contained record per INT8 tile (FP64 entries stay empty)
+        std::vector<RawTile> recs(flat.size());
+        std::memset(recs.data(), 0, sizeof(RawTile) * recs.size());
+        for (uint32_t c = 0; c < SHAPE_COUNT; ++c)
+            for (int64_t j = b->class_first[c]; j < (int64_t)b->class_first[c] + b->class_count[c]; ++j) {
+                const TileRef &tr = flat[(size_t)j];
+                const Desc &D = descs[(size_t)tr.desc];
+                const int64_t row0 = (int64_t)tr.tm * shape_bm(c), col0 = (int64_t)tr.tn * shape_bn(c);
+                RawTile &r = recs[(size_t)j];
+                r.A = D.A + row0 * D.lda;
+                r.B = D.B + col0;
+                r.C = D.C + row0 * D.ldc + col0;
+                r.lda = (uint32_t)D.lda;
+                r.ldb = (uint32_t)D.ldb;
+                r.ldc = (uint32_t)D.ldc;
+                r.rows = (int32_t)(D.m - row0);
+                r.cols = (int32_t)(D.n - col0);
+                r.k = D.k;
+                r.a_size = D.k > 0 ? (uint32_t)((r.rows - 1) * D.lda + D.k) : 0u;
+                r.b_size = D.k > 0 ? (uint32_t)((int64_t)(D.k - 1) * D.ldb + r.cols) : 0u;
+                r.p = D.p;
+                r.off = D.off;
+                r.magic32 = D.magic32;
+                r.add_h = D.add_h;
+                r.neg_p = D.neg_p;
+            }
+        if ((e = hipMalloc(&b->d_raw, sizeof(RawTile) * recs.size())) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMemcpy(b->d_raw, recs.data(), sizeof(RawTile) * recs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy");
+    }
 
     // Record the launches in one graph: the pack kernel, then each class's persistent
     // kernel in turn, each with the whole GPU (measured marginally faster than the
@@ -956,11 +1137,12 @@ qmm_status build_batch(int64_t count, const qmm_problem *probs, uint32_t flags, 
         const TileRef *tt = b->d_tiles + b->class_first[c];
         const int32_t nt = b->class_count[c];
         if (b->raw && c < SHAPE_COUNT) {
+            const RawTile *rr = b->d_raw + b->class_first[c];
             switch (c) {
-            case 0: batched_int8_kernel<SHAPE_64x64, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
-            case 1: batched_int8_kernel<SHAPE_32x128, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
-            case 2: batched_int8_kernel<SHAPE_128x32, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
-            default: batched_int8_kernel<SHAPE_128x128, false, true><<<grid[c], NT, 0, s0>>>(dd, tt, nt); break;
+            case 0: batched_raw_kernel<SHAPE_64x64><<<grid[c], NT, 0, s0>>>(rr, nt); break;
+            case 1: batched_raw_kernel<SHAPE_32x128><<<grid[c], NT, 0, s0>>>(rr, nt); break;
+            case 2: batched_raw_kernel<SHAPE_128x32><<<grid[c], NT, 0, s0>>>(rr, nt); break;
+            default: batched_raw_kernel<SHAPE_128x128><<<grid[c], NT, 0, s0>>>(rr, nt); break;
             }
             if (le == hipSuccess) le = hipGetLastError();
             continue;

@@ -204,6 +204,57 @@ __device__ __forceinline__ void raw_issue32(uint32_t (&w)[5], int32_t &meta, con
     }
 }
 
+// Unaligned 16-byte access: the memory system serves vector loads and stores at
+// any byte address (compute queues run with unaligned access enabled; the compiler
+// emits one dwordx4 load for a 1-byte aligned 16-byte vector on this target).
+typedef unsigned int u32x4a1 __attribute__((ext_vector_type(4), aligned(1)));
+typedef unsigned int u32a1 __attribute__((aligned(1)));
+typedef unsigned int uint4v_t __attribute__((ext_vector_type(4)));
+
+// Issue half of a 16-byte load at X + off of a byte matrix whose data is size >= 16
+// bytes from X: the load starts at min(off, size - 16), so it never leaves the
+// data, and shift (0 for every load that fits) says how many bytes to move down
+// when it is finished (shift_down_bytes).  Zero, with no load, when !ok.  Bytes past
+// a row's end are NOT cleared: they are the next row's, and the caller must make
+// them harmless.
+__device__ __forceinline__ uint4v_t load16_clamped(const uint8_t *X, uint32_t off, bool ok, uint32_t size,
+                                                  uint32_t &shift) {
+    const uint32_t oc = off + 16u <= size ? off : size - 16u;
+    uint4v_t v = {0u, 0u, 0u, 0u};
+    shift = 0;
+    if (ok) {
+        const u32x4a1 x = *(const QMM_GLOBAL u32x4a1 *)(X + oc);
+        v = uint4v_t{x.x, x.y, x.z, x.w};
+        shift = off - oc;
+    }
+    return v;
+}
+
+// v moved down by s bytes (0 <= s < 16), zeros shifted in at the top.
+__device__ __forceinline__ uint4v_t shift_down_bytes(uint4v_t v, uint32_t s) {
+    const uint32_t q = s >> 2, r = s & 3u;
+    auto dw = [&](uint32_t i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : i == 3 ? v.w : 0u; };
+    uint32_t o[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) o[j] = __builtin_amdgcn_alignbyte(dw(j + q + 1), dw(j + q), r);
+    return uint4v_t{o[0], o[1], o[2], o[3]};
+}
+
+// 16 bytes at X + off of a byte matrix whose data is shorter than 16 bytes: byte
+// loads of what lies inside it, zeros elsewhere (and none when !ok).
+__device__ __forceinline__ uint4v_t load16_tiny(const uint8_t *X, uint32_t off, bool ok, uint32_t size) {
+    uint64_t lo = 0, hi = 0;
+    if (ok) {
+        // one byte at a time (a rare path: kept rolled, so it holds few registers)
+#pragma nounroll
+        for (uint32_t b = 0; b < 16u; ++b) {
+            const uint64_t x = off + b < size ? (uint64_t)((const QMM_GLOBAL uint8_t *)X)[off + b] << (8 * (b & 7)) : 0;
+            if (b < 8) lo |= x; else hi |= x;
+        }
+    }
+    return uint4v_t{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+}
+
 // The issue half with a plain pointer p into data that ends at end (any length:
 // the window is checked against end in 64 bits).
 __device__ __forceinline__ void raw_issue_ptr(uint32_t (&w)[5], int32_t &meta, const uint8_t *p, int64_t valid,

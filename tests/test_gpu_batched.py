@@ -45,7 +45,10 @@ def check_all(host, dev):
 
 EDGE_SHAPES = [(7, 1, 1, 1), (3, 16, 16, 16), (101, 17, 33, 5), (2, 513, 31, 70), (251, 64, 64, 64),
                (256, 65, 129, 200), (5, 3, 300, 1), (13, 200, 1, 90), (31, 128, 32, 512), (11, 32, 128, 17),
-               (3, 0, 5, 5), (3, 5, 0, 5), (7, 9, 9, 0)]
+               (3, 0, 5, 5), (3, 5, 0, 5), (7, 9, 9, 0),
+               # operands just over 16 bytes, and last segments that end past the data
+               # (raw tiles pull such loads back inside it and shift the bytes down)
+               (11, 16, 16, 1), (7, 20, 20, 3), (101, 33, 17, 15), (3, 130, 67, 129), (5, 2, 9, 9)]
 
 
 @pytest.mark.parametrize("flags", [0, qmm.BATCH_SHAPE_64x64, qmm.BATCH_SHAPE_32x128, qmm.BATCH_SHAPE_128x32,
