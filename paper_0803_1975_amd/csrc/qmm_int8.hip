@@ -1168,6 +1168,86 @@ __global__ __launch_bounds__(256) void tail_combine_kernel(const uint8_t *__rest
     C[r * ldc + (idx - r * n)] = (uint8_t)mod_u32_m32(sum, p, magic32);
 }
 
+// A thin edge strip (at most 16 rows or columns): out[x][y] = (X[x] . Y[y]) mod p for
+// x < nx, y < ny <= RMAX, X and Y rows of int8 values, 16-byte aligned, readable up
+// to k16 bytes (zero past k), each dot product within int32 (the plan's bound).
+// out[x][y] goes to C[x sx + y sy].  One wavefront per XR rows of X: each lane takes
+// 16 bytes of k at a time (a wavefront reads 1 KB of a row per load), four v_dot4
+// per 16 bytes and Y row; then the XR x RMAX sums are reduced across the wavefront
+// by halving exchanges (each step keeps half the values and adds the partner's
+// other half), which leaves lane l with the total of value (l >> (6 - log2 NV)).
+// Memory-bound on X, which the strip reads once (Y stays in the caches).
+template <int XR, int RMAX>
+__global__ __launch_bounds__(256) void thin_strip_kernel(const int8_t *__restrict__ X, int64_t ldx, int64_t nx,
+                                                         const int8_t *__restrict__ Y, int64_t ldy, int32_t ny,
+                                                         int64_t k16, uint8_t *__restrict__ C, int64_t sx, int64_t sy,
+                                                         uint32_t p, uint64_t magic, uint32_t off) {
+    constexpr int NV = XR * RMAX, LOGNV = NV == 32 ? 5 : NV == 16 ? 4 : NV == 8 ? 3 : NV == 4 ? 2 : NV == 2 ? 1 : 0;
+    static_assert((1 << LOGNV) == NV && NV <= 32, "XR x RMAX is a power of two up to 32");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * XR;
+    if (x0 >= nx) return;  // the whole wavefront
+    const QMM_GLOBAL int8_t *xrow[XR];
+#pragma unroll
+    for (int i = 0; i < XR; ++i) xrow[i] = (const QMM_GLOBAL int8_t *)X + (x0 + i < nx ? x0 + i : nx - 1) * ldx;
+    const QMM_GLOBAL int8_t *yb = (const QMM_GLOBAL int8_t *)Y;
+    int32_t v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = 0;
+#pragma unroll 2
+    for (int64_t c = 16 * lane; c < k16; c += 1024) {
+        ix4 xv[XR];
+#pragma unroll
+        for (int i = 0; i < XR; ++i) xv[i] = *(const QMM_GLOBAL ix4 *)(xrow[i] + c);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < ny) {
+                const ix4 yv = *(const QMM_GLOBAL ix4 *)(yb + r * ldy + c);
+#pragma unroll
+                for (int i = 0; i < XR; ++i) {
+                    int32_t a = v[i * RMAX + r];
+                    a = __builtin_amdgcn_sdot4(xv[i].x, yv.x, a, false);
+                    a = __builtin_amdgcn_sdot4(xv[i].y, yv.y, a, false);
+                    a = __builtin_amdgcn_sdot4(xv[i].z, yv.z, a, false);
+                    a = __builtin_amdgcn_sdot4(xv[i].w, yv.w, a, false);
+                    v[i * RMAX + r] = a;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < LOGNV; ++s) {
+        const int o = 32 >> s, h = (NV >> s) / 2;
+        const bool upper = (lane & o) != 0;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const int32_t keep = upper ? v[j + h] : v[j], send = upper ? v[j] : v[j + h];
+            v[j] = keep + __shfl_xor(send, o);
+        }
+    }
+#pragma unroll
+    for (int o = 32 >> LOGNV; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o);
+    const int idx = (lane >> (6 - LOGNV)) & (NV - 1), i = idx / RMAX, r = idx % RMAX;
+    if ((lane & ((64 >> LOGNV) - 1)) == 0 && x0 + i < nx && r < ny)
+        C[(x0 + i) * sx + (int64_t)r * sy] = (uint8_t)mod_i32_magic(v[0], p, magic, off);
+}
+
+// Runs a thin strip (ny <= 16) with the smallest register block that holds it.
+qmm_status run_thin_strip(const int8_t *X, int64_t ldx, int64_t nx, const int8_t *Y, int64_t ldy, int32_t ny,
+                          int64_t k16, uint8_t *C, int64_t sx, int64_t sy, const Int8Args &g, hipStream_t s) {
+    if (nx == 0 || ny == 0) return QMM_OK;
+    auto go = [&](auto kern, int xr) {
+        const dim3 grid((unsigned)ceil_div(nx, 4 * (int64_t)xr));
+        kern<<<grid, 256, 0, s>>>(X, ldx, nx, Y, ldy, ny, k16, C, sx, sy, g.p, g.magic, g.off);
+        return check_launch("thin_strip");
+    };
+    if (ny <= 2) return go(thin_strip_kernel<2, 2>, 2);
+    if (ny <= 4) return go(thin_strip_kernel<2, 4>, 2);
+    if (ny <= 8) return go(thin_strip_kernel<2, 8>, 2);
+    return go(thin_strip_kernel<2, 16>, 2);
+}
+constexpr int64_t kThinStrip = 16;  // strips this thin or thinner take thin_strip_kernel
+
 // One edge strip: args `a` already describe the strip's A rows, Bt rows and C; run
 // it whole (one chunk) or as chunks into `part` and combine.
 template <typename Run>
@@ -1265,8 +1345,13 @@ qmm_status launch_gemm_int8(const qmm_plan &pl, int64_t m, int64_t n, int64_t k,
 qmm_status launch_gemm_int8_centred_a(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, const int8_t *Ac,
                                       int64_t ldac, const int8_t *Bt, int64_t ldbt, uint8_t *C, int64_t ldc,
                                       void *stream, uint8_t *tail_ws, size_t tail_bytes) {
-    return gemm_int8_impl(pl, m, n, ceil_div(k, 16) * 16, (const uint8_t *)Ac, ldac, true, Bt, ldbt, C, ldc, stream,
-                          tail_ws, tail_bytes);
+    // an unblocked plan stays unblocked over the padded k (its zero terms keep every
+    // sum within the plan's bound)
+    const int64_t k16 = ceil_div(k, 16) * 16;
+    qmm_plan p16 = pl;
+    if (p16.k_block >= k) p16.k_block = k16;
+    return gemm_int8_impl(p16, m, n, k16, (const uint8_t *)Ac, ldac, true, Bt, ldbt, C, ldc, stream, tail_ws,
+                          tail_bytes);
 }
 
 size_t lowp_tail_bytes(const qmm_plan &pl, int64_t m, int64_t n, int64_t k) {
@@ -1343,8 +1428,23 @@ qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     bottom.C = C + t.m0 * ldc;
     right.Bt = Bt + t.n0 * ldbt;
     right.C = C + t.n0;
-    if (st == QMM_OK) st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
-    if (st == QMM_OK) st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
+    // Strips of at most kThinStrip rows (columns) are dot products of int8 rows read
+    // straight from A and Bt: A's rows must be int8 values already (centred, or
+    // residues usable as they are) and both operands whole 16-byte segments.
+    const bool thin_ok = !blocked && (a_centred || int8_raw_a_ok(pl, k)) && k % 16 == 0 && lda % 16 == 0 &&
+                         ldbt % 16 == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)Bt % 16 == 0;
+    if (st == QMM_OK) {
+        if (thin_ok && t.bottom.rows <= kThinStrip)  // C[m0 + y][x] = Bt[x] . A[m0 + y]
+            st = run_thin_strip(Bt, ldbt, n, (const int8_t *)bottom.A, lda, (int32_t)t.bottom.rows, k, bottom.C, 1, ldc, g, s);
+        else
+            st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
+    }
+    if (st == QMM_OK) {
+        if (thin_ok && t.right.cols <= kThinStrip)  // C[x][n0 + y] = A[x] . Bt[n0 + y]
+            st = run_thin_strip((const int8_t *)A, lda, t.m0, right.Bt, ldbt, (int32_t)t.right.cols, k, right.C, ldc, 1, g, s);
+        else
+            st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
+    }
     return st;
 }
 }  // namespace

@@ -640,6 +640,22 @@ def test_tail_of_a_partial_round_on_small_tiles(torch, p, k, k_block, tile, path
     np.testing.assert_array_equal(got, ref.modmul(A, B, p))
 
 
+# Edge strips of at most 16 rows (columns) past whole rounds of 256 x 256 tiles run
+# as int8 dot products of whole rows (thin strips); 17 rows take the split-K strips.
+# Raw residues (p <= 128, k a multiple of 128) and centred rows, bottom and right.
+@pytest.mark.parametrize("p,k,r,side", [(101, 256, 1, "bottom"), (101, 250, 16, "bottom"), (7, 256, 5, "bottom"),
+                                        (251, 256, 9, "right"), (101, 250, 3, "right"), (101, 256, 17, "right")])
+def test_thin_edge_strips(torch, p, k, r, side):
+    m, n = (512 + r, 32768) if side == "bottom" else (32768, 512 + r)
+    rng = np.random.default_rng(p * 1000 + k + r)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    note("thin strip", side, r, plan, m, n, k)
+    got = host(qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan))
+    np.testing.assert_array_equal(got, ref.modmul(A, B, p))
+
+
 @pytest.mark.parametrize("k", (1001, 4097, 2049))
 def test_int8_unaligned_rows_on_every_tile(torch, k):
     # k odd: rows of A start at every byte offset within a dword, so the product
