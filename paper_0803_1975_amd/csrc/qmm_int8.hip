@@ -1168,48 +1168,93 @@ __global__ __launch_bounds__(256) void tail_combine_kernel(const uint8_t *__rest
     C[r * ldc + (idx - r * n)] = (uint8_t)mod_u32_m32(sum, p, magic32);
 }
 
+// Four e2m1 codes (one per byte, as the FP4 rows hold them: magnitudes 0..4 as the
+// codes 0, 2, 4, 5, 6, sign bit 8, never a negative zero) as four int8 values.
+__device__ __forceinline__ uint32_t e2m1x4_to_int8x4(uint32_t codes) {
+    const uint32_t mag = codes & 0x07070707u, sgn = (codes >> 3) & 0x01010101u;
+    // byte c of the table (c = 0 .. 7) is the magnitude of code c: 0, 0.5, 1, 1.5, 2,
+    // 3, 4, 6 (the halves never occur; they read 0)
+    const uint32_t val = __builtin_amdgcn_perm(0x06040302u, 0x00010000u, mag);
+    const uint32_t neg = sgn * 0xffu;  // 0xff in each negative byte
+    return (val ^ neg) + sgn;          // two's complement of a non-zero byte: no carry
+}
+
 // A thin edge strip (at most 16 rows or columns): out[x][y] = (X[x] . Y[y]) mod p for
-// x < nx, y < ny <= RMAX, X and Y rows of int8 values, 16-byte aligned, readable up
-// to k16 bytes (zero past k), each dot product within int32 (the plan's bound).
-// out[x][y] goes to C[x sx + y sy].  One wavefront per XR rows of X: each lane takes
-// 16 bytes of k at a time (a wavefront reads 1 KB of a row per load), four v_dot4
-// per 16 bytes and Y row; then the XR x RMAX sums are reduced across the wavefront
-// by halving exchanges (each step keeps half the values and adds the partner's
-// other half), which leaves lane l with the total of value (l >> (6 - log2 NV)).
-// Memory-bound on X, which the strip reads once (Y stays in the caches).
-template <int XR, int RMAX>
-__global__ __launch_bounds__(256) void thin_strip_kernel(const int8_t *__restrict__ X, int64_t ldx, int64_t nx,
-                                                         const int8_t *__restrict__ Y, int64_t ldy, int32_t ny,
-                                                         int64_t k16, uint8_t *__restrict__ C, int64_t sx, int64_t sy,
-                                                         uint32_t p, uint64_t magic, uint32_t off) {
+// x < nx, y < ny <= RMAX, X and Y rows 16-byte aligned, readable up to k16 bytes
+// (zero past k): int8 values, or (FP4) e2m1 codes two per byte, the even k in the low
+// nibble, decoded to int8 here.  Each dot product stays within int32 (INT8: the plan's
+// bound; FP4: |x| <= 4, so 16 k per product at most).  out[x][y] goes to C[x sx + y sy].
+// One wavefront per XR rows of X: each lane takes 16 bytes of k at a time (a
+// wavefront reads 1 KB of a row per load), v_dot4 on four int8 pairs at a time; then
+// the XR x RMAX sums are reduced across the wavefront by halving exchanges (each step
+// keeps half the values and adds the partner's other half), which leaves lane l with
+// the total of value (l >> (6 - log2 NV)).  Memory-bound on X, which the strip reads
+// once (Y stays in the caches).
+struct ThinStrip {
+    const int8_t *X, *Y;
+    int64_t ldx, ldy, nx;
+    uint8_t *C;
+    int64_t sx, sy;
+    int32_t ny;
+    uint32_t blocks;  // workgroups of this strip
+};
+struct ThinStrips {
+    ThinStrip s[2];  // the bottom and the right strip of one product, one launch
+    int64_t k16;
+    uint32_t p, off;
+    uint64_t magic;
+};
+
+template <int XR, int RMAX, bool FP4>
+__global__ __launch_bounds__(256) void thin_strip_kernel(ThinStrips g) {
     constexpr int NV = XR * RMAX, LOGNV = NV == 32 ? 5 : NV == 16 ? 4 : NV == 8 ? 3 : NV == 4 ? 2 : NV == 2 ? 1 : 0;
     static_assert((1 << LOGNV) == NV && NV <= 32, "XR x RMAX is a power of two up to 32");
+    constexpr int DW = FP4 ? 8 : 4;  // int8x4 words per 16 bytes of a row
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * XR;
+    const bool second = blockIdx.x >= g.s[0].blocks;
+    const ThinStrip &js = second ? g.s[1] : g.s[0];
+    const int8_t *X = js.X, *Y = js.Y;
+    const int64_t ldx = js.ldx, ldy = js.ldy, nx = js.nx, sx = js.sx, sy = js.sy, k16 = g.k16;
+    const int32_t ny = js.ny;
+    uint8_t *C = js.C;
+    const int64_t x0 = ((int64_t)(blockIdx.x - (second ? g.s[0].blocks : 0u)) * 4 + wave) * XR;
     if (x0 >= nx) return;  // the whole wavefront
     const QMM_GLOBAL int8_t *xrow[XR];
 #pragma unroll
     for (int i = 0; i < XR; ++i) xrow[i] = (const QMM_GLOBAL int8_t *)X + (x0 + i < nx ? x0 + i : nx - 1) * ldx;
     const QMM_GLOBAL int8_t *yb = (const QMM_GLOBAL int8_t *)Y;
+    // 16 bytes of a row as DW int8x4 words (FP4: low nibbles then high nibbles of
+    // each dword, the same k order for X and Y)
+    auto words = [](const ix4 v, int32_t (&w)[DW]) {
+        const int32_t in[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (FP4) {
+                w[2 * j] = (int32_t)e2m1x4_to_int8x4((uint32_t)in[j] & 0x0f0f0f0fu);
+                w[2 * j + 1] = (int32_t)e2m1x4_to_int8x4(((uint32_t)in[j] >> 4) & 0x0f0f0f0fu);
+            } else {
+                w[j] = in[j];
+            }
+        }
+    };
     int32_t v[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = 0;
 #pragma unroll 2
     for (int64_t c = 16 * lane; c < k16; c += 1024) {
-        ix4 xv[XR];
+        int32_t xw[XR][DW];
 #pragma unroll
-        for (int i = 0; i < XR; ++i) xv[i] = *(const QMM_GLOBAL ix4 *)(xrow[i] + c);
+        for (int i = 0; i < XR; ++i) words(*(const QMM_GLOBAL ix4 *)(xrow[i] + c), xw[i]);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < ny) {
-                const ix4 yv = *(const QMM_GLOBAL ix4 *)(yb + r * ldy + c);
+                int32_t yw[DW];
+                words(*(const QMM_GLOBAL ix4 *)(yb + r * ldy + c), yw);
 #pragma unroll
                 for (int i = 0; i < XR; ++i) {
                     int32_t a = v[i * RMAX + r];
-                    a = __builtin_amdgcn_sdot4(xv[i].x, yv.x, a, false);
-                    a = __builtin_amdgcn_sdot4(xv[i].y, yv.y, a, false);
-                    a = __builtin_amdgcn_sdot4(xv[i].z, yv.z, a, false);
-                    a = __builtin_amdgcn_sdot4(xv[i].w, yv.w, a, false);
+#pragma unroll
+                    for (int j = 0; j < DW; ++j) a = __builtin_amdgcn_sdot4(xw[i][j], yw[j], a, false);
                     v[i * RMAX + r] = a;
                 }
             }
@@ -1229,22 +1274,30 @@ __global__ __launch_bounds__(256) void thin_strip_kernel(const int8_t *__restric
     for (int o = 32 >> LOGNV; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o);
     const int idx = (lane >> (6 - LOGNV)) & (NV - 1), i = idx / RMAX, r = idx % RMAX;
     if ((lane & ((64 >> LOGNV) - 1)) == 0 && x0 + i < nx && r < ny)
-        C[(x0 + i) * sx + (int64_t)r * sy] = (uint8_t)mod_i32_magic(v[0], p, magic, off);
+        C[(x0 + i) * sx + (int64_t)r * sy] = (uint8_t)mod_i32_magic(v[0], g.p, g.magic, g.off);
 }
 
-// Runs a thin strip (ny <= 16) with the smallest register block that holds it.
-qmm_status run_thin_strip(const int8_t *X, int64_t ldx, int64_t nx, const int8_t *Y, int64_t ldy, int32_t ny,
-                          int64_t k16, uint8_t *C, int64_t sx, int64_t sy, const Int8Args &g, hipStream_t s) {
-    if (nx == 0 || ny == 0) return QMM_OK;
-    auto go = [&](auto kern, int xr) {
-        const dim3 grid((unsigned)ceil_div(nx, 4 * (int64_t)xr));
-        kern<<<grid, 256, 0, s>>>(X, ldx, nx, Y, ldy, ny, k16, C, sx, sy, g.p, g.magic, g.off);
-        return check_launch("thin_strip");
-    };
-    if (ny <= 2) return go(thin_strip_kernel<2, 2>, 2);
-    if (ny <= 4) return go(thin_strip_kernel<2, 4>, 2);
-    if (ny <= 8) return go(thin_strip_kernel<2, 8>, 2);
-    return go(thin_strip_kernel<2, 16>, 2);
+// Runs the thin strips of one product (each ny <= 16; an empty one has nx = 0) in one
+// launch, with the smallest register block that holds the thicker.
+template <bool FP4>
+qmm_status run_thin_strips(ThinStrips t, const Int8Args &g, hipStream_t s) {
+    constexpr int XR = 2;
+    t.p = g.p;
+    t.off = g.off;
+    t.magic = g.magic;
+    int32_t ny = 0;
+    for (ThinStrip &j : t.s) {
+        if (j.nx == 0 || j.ny == 0) j.nx = j.ny = 0;
+        j.blocks = (uint32_t)ceil_div(j.nx, 4 * (int64_t)XR);
+        ny = std::max(ny, j.ny);
+    }
+    const unsigned blocks = t.s[0].blocks + t.s[1].blocks;
+    if (blocks == 0) return QMM_OK;
+    if (ny <= 2) thin_strip_kernel<XR, 2, FP4><<<blocks, 256, 0, s>>>(t);
+    else if (ny <= 4) thin_strip_kernel<XR, 4, FP4><<<blocks, 256, 0, s>>>(t);
+    else if (ny <= 8) thin_strip_kernel<XR, 8, FP4><<<blocks, 256, 0, s>>>(t);
+    else thin_strip_kernel<XR, 16, FP4><<<blocks, 256, 0, s>>>(t);
+    return check_launch("thin_strip");
 }
 constexpr int64_t kThinStrip = 16;  // strips this thin or thinner take thin_strip_kernel
 
@@ -1322,8 +1375,19 @@ qmm_status launch_gemm_fp4(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, 
     bottom.C = C + t.m0 * ldc;
     right.Bt = (const int8_t *)(Bt4 + t.n0 * ldbt4);
     right.C = C + t.n0;
-    if (st == QMM_OK) st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
-    if (st == QMM_OK) st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
+    // strips of at most kThinStrip rows (columns): dot products of decoded code rows
+    const bool thin_ok = lda4 % 16 == 0 && ldbt4 % 16 == 0 && (uintptr_t)A4 % 16 == 0 && (uintptr_t)Bt4 % 16 == 0;
+    const int8_t *a4 = (const int8_t *)A4, *b4 = (const int8_t *)Bt4;
+    const bool tb = thin_ok && t.bottom.rows <= kThinStrip, tr = thin_ok && t.right.cols <= kThinStrip;
+    ThinStrips ts{};
+    ts.k16 = g.k;
+    if (tb)  // C[m0 + y][x] = Bt4[x] . A4[m0 + y]
+        ts.s[0] = ThinStrip{b4, a4 + t.m0 * lda4, ldbt4, lda4, n, bottom.C, 1, ldc, (int32_t)t.bottom.rows, 0};
+    if (tr)  // C[x][n0 + y] = A4[x] . Bt4[n0 + y]
+        ts.s[1] = ThinStrip{a4, right.Bt, lda4, ldbt4, t.m0, right.C, ldc, 1, (int32_t)t.right.cols, 0};
+    if (st == QMM_OK && (tb || tr)) st = run_thin_strips<true>(ts, g, s);
+    if (st == QMM_OK && !tb) st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
+    if (st == QMM_OK && !tr) st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
     return st;
 }
 
@@ -1433,18 +1497,16 @@ qmm_status gemm_int8_impl(const qmm_plan &pl, int64_t m, int64_t n, int64_t k, c
     // residues usable as they are) and both operands whole 16-byte segments.
     const bool thin_ok = !blocked && (a_centred || int8_raw_a_ok(pl, k)) && k % 16 == 0 && lda % 16 == 0 &&
                          ldbt % 16 == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)Bt % 16 == 0;
-    if (st == QMM_OK) {
-        if (thin_ok && t.bottom.rows <= kThinStrip)  // C[m0 + y][x] = Bt[x] . A[m0 + y]
-            st = run_thin_strip(Bt, ldbt, n, (const int8_t *)bottom.A, lda, (int32_t)t.bottom.rows, k, bottom.C, 1, ldc, g, s);
-        else
-            st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
-    }
-    if (st == QMM_OK) {
-        if (thin_ok && t.right.cols <= kThinStrip)  // C[x][n0 + y] = A[x] . Bt[n0 + y]
-            st = run_thin_strip((const int8_t *)A, lda, t.m0, right.Bt, ldbt, (int32_t)t.right.cols, k, right.C, ldc, 1, g, s);
-        else
-            st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
-    }
+    const bool tb = thin_ok && t.bottom.rows <= kThinStrip, tr = thin_ok && t.right.cols <= kThinStrip;
+    ThinStrips ts{};
+    ts.k16 = k;
+    if (tb)  // C[m0 + y][x] = Bt[x] . A[m0 + y]
+        ts.s[0] = ThinStrip{Bt, (const int8_t *)bottom.A, ldbt, lda, n, bottom.C, 1, ldc, (int32_t)t.bottom.rows, 0};
+    if (tr)  // C[x][n0 + y] = A[x] . Bt[n0 + y]
+        ts.s[1] = ThinStrip{(const int8_t *)A, right.Bt, lda, ldbt, t.m0, right.C, ldc, 1, (int32_t)t.right.cols, 0};
+    if (st == QMM_OK && (tb || tr)) st = run_thin_strips<false>(ts, g, s);
+    if (st == QMM_OK && !tb) st = run_strip(t.bottom, bottom, tail_ws + t.bottom.off, pl.p, s, run);
+    if (st == QMM_OK && !tr) st = run_strip(t.right, right, tail_ws + t.right.off, pl.p, s, run);
     return st;
 }
 }  // namespace

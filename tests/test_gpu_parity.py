@@ -625,7 +625,9 @@ def test_int8_direct_tile_on_raw_and_centred_rows(torch, p, k, k_block):
 @pytest.mark.parametrize("p,k,k_block,tile,path,n", [
     (101, 1024, 0, 0, qmm.PATH_INT8, 4096), (101, 1000, 0, 0, qmm.PATH_INT8, 4097),
     (251, 1024, 384, 0, qmm.PATH_INT8, 4097), (101, 1024, 0, 3, qmm.PATH_INT8, 4097),
-    (7, 700, 0, 0, qmm.PATH_FP4, 4096), (7, 3000, 0, 0, qmm.PATH_FP4, 4097)])
+    (7, 700, 0, 0, qmm.PATH_FP4, 4096), (7, 3000, 0, 0, qmm.PATH_FP4, 4097),
+    # a thin bottom strip (1 row) beside a split-K right strip (20 columns)
+    (101, 1024, 0, 0, qmm.PATH_INT8, 4116), (7, 700, 0, 0, qmm.PATH_FP4, 4116)])
 def test_tail_of_a_partial_round_on_small_tiles(torch, p, k, k_block, tile, path, n):
     m = 4097
     rng = np.random.default_rng(p + k + tile + n)
@@ -642,15 +644,19 @@ def test_tail_of_a_partial_round_on_small_tiles(torch, p, k, k_block, tile, path
 
 # Edge strips of at most 16 rows (columns) past whole rounds of 256 x 256 tiles run
 # as int8 dot products of whole rows (thin strips); 17 rows take the split-K strips.
-# Raw residues (p <= 128, k a multiple of 128) and centred rows, bottom and right.
-@pytest.mark.parametrize("p,k,r,side", [(101, 256, 1, "bottom"), (101, 250, 16, "bottom"), (7, 256, 5, "bottom"),
-                                        (251, 256, 9, "right"), (101, 250, 3, "right"), (101, 256, 17, "right")])
-def test_thin_edge_strips(torch, p, k, r, side):
+# Raw residues (p <= 128, k a multiple of 128) and centred rows, bottom and right;
+# FP4 strips decode their e2m1 codes to int8 first.
+@pytest.mark.parametrize("p,k,r,side,path", [
+    (101, 256, 1, "bottom", qmm.PATH_INT8), (101, 250, 16, "bottom", qmm.PATH_INT8),
+    (7, 256, 5, "bottom", qmm.PATH_INT8), (251, 256, 9, "right", qmm.PATH_INT8), (101, 250, 3, "right", qmm.PATH_INT8),
+    (101, 256, 17, "right", qmm.PATH_INT8), (7, 301, 1, "bottom", qmm.PATH_FP4), (5, 256, 16, "right", qmm.PATH_FP4),
+    (3, 999, 7, "bottom", qmm.PATH_FP4)])
+def test_thin_edge_strips(torch, p, k, r, side, path):
     m, n = (512 + r, 32768) if side == "bottom" else (32768, 512 + r)
     rng = np.random.default_rng(p * 1000 + k + r)
     A = rng.integers(0, p, (m, k), dtype=np.uint8)
     B = rng.integers(0, p, (k, n), dtype=np.uint8)
-    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    plan = qmm.choose_Qd(p, m, n, k, path=path)
     note("thin strip", side, r, plan, m, n, k)
     got = host(qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan))
     np.testing.assert_array_equal(got, ref.modmul(A, B, p))
