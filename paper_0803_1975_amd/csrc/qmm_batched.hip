@@ -269,13 +269,11 @@ __device__ __forceinline__ int32_t acc_value(int32_t bits, bool fp4) {
 constexpr int KT = 128;            // K stage (bytes)
 constexpr int PT = KT + 16;        // LDS row pitch: 8 lanes reading 8 rows hit distinct banks
 constexpr int KP_ALIGN = 64;       // workspace rows: k rounded up to this
-// LDS pitch of B's k-rows in raw tiles: 8 lanes reading 8 consecutive rows at one
-// column hit distinct banks for every tile width used here (32, 64, 128).
+// LDS pitch of B's k-rows in raw tiles narrower than 128 bytes: 8 lanes reading 8
+// consecutive rows at one column hit distinct banks for the widths used (32, 64).
 constexpr int raw_bpitch(int bn) { return bn + 16; }
-// LDS bytes of one tile: A rows, then B (n-rows of packed codes, or k-rows when raw)
-constexpr int tile_lds_bytes(int bm, int bn, bool raw) {
-    return bm * PT + (raw && KT * raw_bpitch(bn) > bn * PT ? KT * raw_bpitch(bn) : bn * PT);
-}
+// LDS bytes of one packed tile: A rows, then B's n-rows of packed codes
+constexpr int tile_lds_bytes(int bm, int bn) { return (bm + bn) * PT; }
 template <int BM, int BN, int WGM, int WGN, bool FP4>
 __device__ __forceinline__ void int8_tile(const Desc &D, int tm, int tn, uint8_t *lds) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 32, FN = WTN / 32;
@@ -505,7 +503,7 @@ __device__ __forceinline__ void fp64_tile(const Desc &D, int tm, int tn, double 
 template <uint32_t SHAPE, bool FP4>
 __global__ __launch_bounds__(NT, SHAPE == SHAPE_128x128 ? 3 : (SHAPE == SHAPE_64x64 && !FP4 ? 7 : 5))
 void batched_int8_kernel(const Desc *__restrict__ descs, const TileRef *__restrict__ tiles, int32_t ntiles) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[tile_lds_bytes(shape_bm(SHAPE), shape_bn(SHAPE), false)];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[tile_lds_bytes(shape_bm(SHAPE), shape_bn(SHAPE))];
     for (int32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const TileRef tr = tiles[i];
         const Desc D = descs[tr.desc];
