@@ -191,7 +191,9 @@ qmm_status qmm_redq(const qmm_plan *plan, int64_t m, int64_t n, const void *CC, 
  * they are: p > 128, k not a multiple of 128, or uncentred sums past int32; INT8
  * and FP4: plus the partial outputs of the split-K edge strips when the grid of
  * 256 x 256 tiles is just past whole rounds over the device's compute units, so
- * the size can depend on the current device). */
+ * the size can depend on the current device; edge strips of at most 16 rows or
+ * columns with 16-byte aligned operand rows run as dot products and leave that
+ * part unused). */
 qmm_status qmm_gemm_workspace_size(const qmm_plan *plan, int64_t m, int64_t n, int64_t k,
                                    size_t *bytes);
 
