@@ -126,7 +126,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g) {
     using MM = Mma<W>;
     using acc_t = typename MM::acc_t;
     __shared__ W sA[2][BM][KT + APAD];
-    __shared__ W sB[2][KT][BN];
+    // FP32: B's k-rows padded by 64 bytes, so the four groups of 16 lanes of a
+    // fragment read (four consecutive k-rows at the same columns) start 16 banks apart
+    // (measured: square FP32 products 1.3 % faster; FP64 unchanged, so left unpadded)
+    constexpr int BPAD = sizeof(W) == 4 ? 16 : 0;
+    __shared__ W sB[2][KT][BN + BPAD];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
