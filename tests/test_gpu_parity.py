@@ -662,6 +662,22 @@ def test_thin_edge_strips(torch, p, k, r, side, path):
     np.testing.assert_array_equal(got, ref.modmul(A, B, p))
 
 
+def test_edge_strips_of_unaligned_rows_take_split_k(torch):
+    # A view whose rows are not 16-byte aligned, with k a multiple of 16 and p <= 128,
+    # is read in place (no centred copy) on the register-staged tile, and the thin
+    # dot-product strips need aligned rows: the 5-row bottom strip then runs as split-K
+    # products on small tiles.  Every entry against the oracle.
+    p, m, n, k = 101, 517, 32768, 256
+    rng = np.random.default_rng(517)
+    Ab = rng.integers(0, p, (m, k + 3), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    A = np.ascontiguousarray(Ab[:, 1:1 + k])
+    dA = torch.from_numpy(Ab).cuda()[:, 1:1 + k]
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    note("unaligned A view, split-K strips", plan, m, n, k)
+    np.testing.assert_array_equal(host(qmm.gemm_mod_p(dA, dev(torch, B), p, plan=plan)), ref.modmul(A, B, p))
+
+
 @pytest.mark.parametrize("k", (1001, 4097, 2049))
 def test_int8_unaligned_rows_on_every_tile(torch, k):
     # k odd: rows of A start at every byte offset within a dword, so the product
