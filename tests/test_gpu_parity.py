@@ -662,6 +662,22 @@ def test_thin_edge_strips(torch, p, k, r, side, path):
     np.testing.assert_array_equal(got, ref.modmul(A, B, p))
 
 
+# More than one round of 256 x 256 tiles on the direct-load tile: 18 x 18 tiles
+# (ragged last row and column, too many whole tiles for the edge split), raw and
+# centred rows, one blocked plan.
+@pytest.mark.parametrize("p,k,k_block", [(101, 1024, 0), (101, 1000, 0), (251, 640, 384), (7, 256, 0)])
+def test_int8_direct_tile_over_two_rounds(torch, p, k, k_block):
+    m = n = 4600
+    rng = np.random.default_rng(p + k)
+    A = rng.integers(0, p, (m, k), dtype=np.uint8)
+    B = rng.integers(0, p, (k, n), dtype=np.uint8)
+    plan = qmm.choose_Qd(p, m, n, k, path=qmm.PATH_INT8)
+    if k_block:
+        plan.k_block = k_block
+    note("direct tile, two rounds", plan, m, n, k)
+    np.testing.assert_array_equal(host(qmm.gemm_mod_p(dev(torch, A), dev(torch, B), p, plan=plan)), ref.modmul(A, B, p))
+
+
 def test_edge_strips_of_unaligned_rows_take_split_k(torch):
     # A view whose rows are not 16-byte aligned, with k a multiple of 16 and p <= 128,
     # is read in place (no centred copy) on the register-staged tile, and the thin
